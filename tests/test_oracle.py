@@ -1,0 +1,295 @@
+"""Pins of the FP64 reference gridder against facts that do not come from it.
+
+Eq. (1) of Sec. 2.2 defines the result; the reference evaluates it with the
+haversine form of the great-circle distance and a declination-band index.
+These tests check it against: the definition of the FWHM, an independent
+distance formula (atan2 of the cross and dot products of unit vectors), the
+inclusive support rule of Algorithm 1, closed forms, invariants of a
+normalised positive-weight average, numpy's weighted average, and
+brute-force searches.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_04584_amd import synth
+
+ARC = 1.0 / 60.0
+
+
+def unit(ra_deg, dec_deg):
+    a, d = np.deg2rad(ra_deg), np.deg2rad(dec_deg)
+    return np.stack([np.cos(d) * np.cos(a), np.cos(d) * np.sin(a), np.sin(d)], -1)
+
+
+def angle(ra1, dec1, ra2, dec2):
+    """Great-circle angle (radians) via atan2(|u x v|, u . v)."""
+    u, v = unit(ra1, dec1), unit(ra2, dec2)
+    return np.arctan2(np.linalg.norm(np.cross(u, v), axis=-1), np.sum(u * v, axis=-1))
+
+
+def gauss(d_rad, fwhm_deg):
+    # a Gaussian falls to one half at distance FWHM / 2
+    sigma = math.radians(fwhm_deg) / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    return np.exp(-0.5 * (d_rad / sigma) ** 2)
+
+
+def centres(m):
+    i = np.arange(m["nx"])
+    j = np.arange(m["ny"])
+    ra = m["ra0_deg"] + (i - (m["nx"] - 1) / 2.0) * m["dra_deg"]
+    dec = m["dec0_deg"] + (j - (m["ny"] - 1) / 2.0) * m["ddec_deg"]
+    RA, DEC = np.meshgrid(ra, dec)  # [ny][nx]
+    return RA.ravel(), DEC.ravel()
+
+
+def run(ra, dec, vals, m, k, **kw):
+    vals = np.asarray(vals, dtype=np.float64)
+    if vals.ndim == 1:
+        vals = vals[:, None]
+    return oracle.grid(ra, dec, vals, "f64", m, k["fwhm_deg"], k["support_deg"], **kw)
+
+
+def test_half_maximum_at_half_fwhm():
+    fwhm = 3.0 * ARC
+    m = synth.make_map(150.0, 20.0, 1, 1)
+    k = {"fwhm_deg": fwhm, "support_deg": 3 * fwhm}
+    V, cnt, W, _ = run([150.0], [20.0 + fwhm / 2], [7.25], m, k)
+    assert cnt[0] == 1
+    assert W[0] == pytest.approx(0.5, rel=1e-12)
+    assert V[0, 0] == 7.25
+
+
+def test_single_sample_reproduces_kernel_profile():
+    fwhm = 3.0 * ARC
+    sig = fwhm / math.sqrt(8 * math.log(2))
+    m = synth.make_map(210.0, 40.0, 21, 17)  # nx != ny: a transposed layout fails
+    k = {"fwhm_deg": fwhm, "support_deg": 3 * sig}
+    sra, sdec = 210.0 + 2.3 * ARC, 40.0 - 1.7 * ARC
+    V, cnt, W, margin = run([sra], [sdec], [3.5], m, k)
+    pra, pdec = centres(m)
+    d = angle(pra, pdec, sra, sdec)
+    R = math.radians(k["support_deg"])
+    assert np.min(np.abs(d - R)) > 1e-9  # no pixel sits on the support edge
+    inside = d <= R
+    assert inside.sum() > 20 and (~inside).sum() > 20
+    np.testing.assert_array_equal(cnt, inside.astype(np.int32))
+    np.testing.assert_allclose(W[inside], gauss(d[inside], fwhm), rtol=1e-11)
+    assert np.all(W[~inside] == 0.0)
+    np.testing.assert_allclose(V[0, inside], 3.5, rtol=2 * np.finfo(float).eps)  # w v / w
+    assert np.all(np.isnan(V[0, ~inside]))
+    # the peak pixel is the one nearest to the sample, at index (j, i) of [ny][nx]
+    p = int(np.argmax(W))
+    assert (p // m["nx"], p % m["nx"]) == (8 - 2, 10 + 2)
+    assert margin > 1e-9
+
+
+def test_support_is_inclusive():
+    m = synth.make_map(10.0, 0.0, 1, 1)
+    R = 4.0 * ARC
+    k = {"fwhm_deg": 3 * ARC, "support_deg": R}
+    _, cnt, _, margin = run([10.0], [R], [1.0], m, k)
+    assert cnt[0] == 1 and margin == 0.0  # d == R exactly: included
+    _, cnt, _, _ = run([10.0], [R * (1 + 1e-9)], [1.0], m, k)
+    assert cnt[0] == 0
+    _, cnt, _, _ = run([10.0 + R * (1 + 1e-9)], [0.0], [1.0], m, k)
+    assert cnt[0] == 0
+
+
+def test_empty_pixels_are_nan():
+    m = synth.make_map(100.0, -30.0, 5, 4)
+    k = synth.make_kernel(3.0)
+    V, cnt, W, _ = run([101.0, 99.0], [-30.0, -30.5], [[1.0, 2.0], [3.0, 4.0]], m, k)
+    assert np.all(cnt == 0) and np.all(W == 0) and np.all(np.isnan(V))
+
+
+def _field(seed, n=600, nx=13, ny=11, ra0=33.0, dec0=-12.0, fwhm=3.0, C=3):
+    rng = np.random.default_rng(seed)
+    ra = ra0 + (rng.random(n) - 0.5) * nx * ARC * 1.3
+    dec = dec0 + (rng.random(n) - 0.5) * ny * ARC * 1.3
+    vals = rng.normal(size=(n, C))
+    return ra, dec, vals, synth.make_map(ra0, dec0, nx, ny), synth.make_kernel(fwhm)
+
+
+def test_constant_input_gives_constant_map():
+    ra, dec, _, m, k = _field(1)
+    V, cnt, _, _ = run(ra, dec, np.full(ra.shape[0], -2.75), m, k)
+    ok = cnt > 0
+    assert ok.sum() > 100
+    np.testing.assert_allclose(V[0, ok], -2.75, rtol=1e-14)  # rounding of the two sums
+    assert np.all(np.isnan(V[0, ~ok]))
+
+
+def test_output_within_neighbour_min_max():
+    ra, dec, vals, m, k = _field(2)
+    V, cnt, _, _ = run(ra, dec, vals, m, k)
+    rp, idx, _ = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"])
+    for p in range(cnt.shape[0]):
+        nb = idx[rp[p]:rp[p + 1]]
+        if nb.size == 0:
+            continue
+        lo, hi = vals[nb].min(0), vals[nb].max(0)
+        assert np.all(V[:, p] >= lo - 1e-12) and np.all(V[:, p] <= hi + 1e-12)
+
+
+def test_linearity():
+    ra, dec, vals, m, k = _field(3)
+    x, y = vals[:, 0], vals[:, 1]
+    Vx = run(ra, dec, x, m, k)[0][0]
+    Vy = run(ra, dec, y, m, k)[0][0]
+    Vz = run(ra, dec, 2.5 * x - 0.75 * y, m, k)[0][0]
+    ok = ~np.isnan(Vz)
+    scale = np.abs(Vz[ok]).max()
+    assert np.max(np.abs(Vz[ok] - (2.5 * Vx[ok] - 0.75 * Vy[ok]))) <= 1e-13 * scale
+
+
+def test_channel_permutation_is_exact():
+    ra, dec, vals, m, k = _field(4, C=5)
+    perm = np.array([3, 0, 4, 2, 1])
+    V = run(ra, dec, vals, m, k)[0]
+    Vp = run(ra, dec, vals[:, perm], m, k)[0]
+    np.testing.assert_array_equal(Vp, V[perm])
+
+
+def test_sample_shuffle_invariance():
+    ra, dec, vals, m, k = _field(5)
+    rng = np.random.default_rng(55)
+    perm = rng.permutation(ra.shape[0])
+    rp, idx, _ = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"])
+    rq, jdx, _ = oracle.neighbours(ra[perm], dec[perm], m, k["fwhm_deg"], k["support_deg"])
+    np.testing.assert_array_equal(rp, rq)
+    for p in range(rp.shape[0] - 1):
+        a = np.sort(idx[rp[p]:rp[p + 1]])
+        b = np.sort(perm[jdx[rq[p]:rq[p + 1]]])
+        np.testing.assert_array_equal(a, b)
+    V = run(ra, dec, vals, m, k)[0]
+    Vs = run(ra[perm], dec[perm], vals[perm], m, k)[0]
+    np.testing.assert_allclose(Vs, V, rtol=1e-13, atol=1e-13)
+
+
+def test_two_symmetric_samples_give_the_mean():
+    m = synth.make_map(45.0, 60.0, 1, 1)
+    k = synth.make_kernel(4.0)
+    off = 1.3 * ARC
+    V, cnt, W, _ = run([45.0, 45.0], [60.0 - off, 60.0 + off], [1.0, 4.0], m, k)
+    assert cnt[0] == 2
+    # the two distances differ only by rounding
+    assert V[0, 0] == pytest.approx(2.5, abs=1e-12)
+
+
+def test_huge_support_is_numpy_weighted_average():
+    rng = np.random.default_rng(6)
+    ra = 120.0 + rng.normal(0, 0.4, 300)
+    dec = 5.0 + rng.normal(0, 0.4, 300)
+    v = rng.normal(size=300)
+    fwhm = 0.7
+    m = synth.make_map(120.0, 5.0, 1, 1)
+    k = {"fwhm_deg": fwhm, "support_deg": 10.0}
+    V, cnt, W, _ = run(ra, dec, v, m, k)
+    w = gauss(angle(120.0, 5.0, ra, dec), fwhm)
+    assert cnt[0] == 300
+    assert V[0, 0] == pytest.approx(np.average(v, weights=w), rel=1e-11)
+    assert W[0] == pytest.approx(w.sum(), rel=1e-11)
+
+
+@pytest.mark.parametrize("seed,ra0,dec0", [(7, 33.0, -12.0), (8, 0.05, 20.0), (9, 359.97, -45.0),
+                                           (10, 180.0, 84.0), (11, 270.0, -87.5)])
+def test_brute_force_matches_index(seed, ra0, dec0):
+    ra, dec, vals, m, k = _field(seed, n=800, ra0=ra0, dec0=dec0)
+    ra = np.mod(ra, 360.0)
+    a = run(ra, dec, vals, m, k)
+    b = run(ra, dec, vals, m, k, brute=True)
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
+    assert a[3] == b[3]
+    na = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"])
+    nb = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"], brute=True)
+    for x, y in zip(na, nb):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("seed,ra0,dec0", [(12, 33.0, -12.0), (13, 359.98, 10.0),
+                                           (14, 15.0, 86.0)])
+def test_neighbour_sets_match_independent_distance(seed, ra0, dec0):
+    ra, dec, _, m, k = _field(seed, n=700, ra0=ra0, dec0=dec0)
+    ra = np.mod(ra, 360.0)
+    rp, idx, w = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"])
+    pra, pdec = centres(m)
+    R = math.radians(k["support_deg"])
+    checked = 0
+    for p in range(pra.shape[0]):
+        d = angle(pra[p], pdec[p], ra, dec)
+        clear = np.abs(d - R) > 1e-12
+        want = np.nonzero((d <= R) & clear)[0]
+        got = idx[rp[p]:rp[p + 1]]
+        got = got[clear[got]]
+        np.testing.assert_array_equal(got, want)
+        np.testing.assert_allclose(w[rp[p]:rp[p + 1]], gauss(d[idx[rp[p]:rp[p + 1]]],
+                                                             k["fwhm_deg"]), rtol=1e-10)
+        checked += want.size
+    assert checked > 1000
+
+
+def test_decoding_of_stored_types():
+    rng = np.random.default_rng(16)
+    ra, dec, _, m, k = _field(17, n=400)
+    f32 = (rng.normal(size=(400, 2)) * 3).astype(np.float32)
+    bf16_bits = (f32.view(np.uint32) >> 16).astype(np.uint16)  # truncation: any bf16 value
+    bf_vals = (bf16_bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    f16 = f32.astype(np.float16)
+    f16[0, 0] = np.float16(3e-6)  # subnormal binary16
+    f16[1, 1] = -np.float16(6.1e-5)
+    for bits, ref, code in ((bf16_bits, bf_vals, "bf16"), (f16.view(np.uint16),
+                                                            f16.astype(np.float64), "f16")):
+        V = oracle.grid(ra, dec, bits, code, m, k["fwhm_deg"], k["support_deg"])[0]
+        Vr = run(ra, dec, ref, m, k)[0]
+        np.testing.assert_array_equal(V, Vr)
+
+
+def test_csr_export_consistent_with_counts_and_sums():
+    ra, dec, _, m, k = _field(18)
+    _, cnt, W, _ = run(ra, dec, np.zeros(ra.shape[0]), m, k)
+    rp, idx, w = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"])
+    np.testing.assert_array_equal(np.diff(rp), cnt)
+    for p in range(cnt.shape[0]):
+        seg = idx[rp[p]:rp[p + 1]]
+        assert np.all(np.diff(seg) > 0)  # ascending original index
+        assert math.fsum(w[rp[p]:rp[p + 1]]) == pytest.approx(W[p], rel=1e-14)
+
+
+def test_subset_of_pixels_and_channels():
+    ra, dec, vals, m, k = _field(19, C=4)
+    V, cnt, W, _ = run(ra, dec, vals, m, k)
+    pix = np.array([5, 0, 77, 142])
+    ch = np.array([3, 1])
+    Vs, cs, Ws, _ = run(ra, dec, vals, m, k, pix=pix, chans=ch)
+    np.testing.assert_array_equal(Vs, V[np.ix_(ch, pix)])
+    np.testing.assert_array_equal(cs, cnt[pix])
+    np.testing.assert_array_equal(Ws, W[pix])
+
+
+def test_cfg1_index_matches_brute_force_on_a_pixel_sample():
+    f = synth.config("cfg1")
+    rng = np.random.default_rng(20)
+    pix = rng.choice(64 * 64, 300, replace=False)
+    vals = rng.normal(size=(f["ra"].shape[0], 1))
+    a = oracle.grid(f["ra"], f["dec"], vals, "f64", f["map"], f["kernel"]["fwhm_deg"],
+                    f["kernel"]["support_deg"], pix=pix)
+    b = oracle.grid(f["ra"], f["dec"], vals, "f64", f["map"], f["kernel"]["fwhm_deg"],
+                    f["kernel"]["support_deg"], pix=pix, brute=True)
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
+    # about 294 neighbours per pixel away from the field edge (6.42 / arcmin^2)
+    assert 200 < np.median(a[1]) < 400
+    assert a[3] > 1e-12
+
+
+def test_bad_arguments_are_rejected():
+    m = synth.make_map(0.0, 0.0, 2, 2)
+    with pytest.raises(ValueError):
+        oracle.grid([0.0], [0.0], np.zeros((1, 1)), "f64", m, 0.0, 0.1)
+    bad = dict(m, nx=0)
+    with pytest.raises(ValueError):
+        oracle.grid([0.0], [0.0], np.zeros((1, 1)), "f64", bad, 0.05, 0.1)
