@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libhegrid (include/hegrid.h).
+
+Argument marshalling only: torch supplies device memory (``data_ptr()``) and
+the current HIP stream; every step of the gridding runs in the library's
+kernels.  There is no fallback: if ``libhegrid.so`` is missing or cannot be
+loaded, every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhegrid.so")
+
+HG_OK, HG_ERR_ARG, HG_ERR_STATE, HG_ERR_NOMEM, HG_ERR_DEVICE, HG_ERR_UNSUPPORTED, \
+    HG_ERR_INTERNAL = range(7)
+HG_F32, HG_BF16, HG_F16 = 0, 1, 2
+HG_PREC_FP32 = 0
+HG_FLAG_TIME_CHANNELS = 1
+
+ABI_FUNCTIONS = ("hg_grid_setup", "hg_grid_channels", "hg_grid_finish", "hg_plan_stats",
+                 "hg_plan_counts", "hg_plan_weight_sums", "hg_plan_neighbours",
+                 "hg_ang2pix_ring", "hg_last_error")
+
+
+class HegridError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"[status {status}] {msg}")
+        self.status = status
+
+
+class hg_map(ctypes.Structure):
+    _fields_ = [("ra0_deg", ctypes.c_double), ("dec0_deg", ctypes.c_double),
+                ("dra_deg", ctypes.c_double), ("ddec_deg", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class hg_kernel(ctypes.Structure):
+    _fields_ = [("fwhm_deg", ctypes.c_double), ("support_deg", ctypes.c_double)]
+
+
+class hg_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("nside", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("device_mem_cap", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32)]
+
+
+class hg_stats(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int64), ("n_used", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("n_entries", ctypes.c_int64),
+                ("n_cells", ctypes.c_int64), ("total_slots", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("nside", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("setup_ms", ctypes.c_double),
+                ("last_channels_ms", ctypes.c_double), ("total_channels_ms", ctypes.c_double),
+                ("channels_calls", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhegrid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HegridError(HG_ERR_DEVICE, f"{LIB_PATH} is not built "
+                          "(python -m paper_2207_04584_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.hg_grid_setup.argtypes = [P, P, i64, ctypes.POINTER(hg_kernel), ctypes.POINTER(hg_map),
+                                ctypes.POINTER(hg_opts), P, ctypes.POINTER(ctypes.c_void_p)]
+    L.hg_grid_channels.argtypes = [P, P, i64, i32, i32, P, P]
+    L.hg_grid_finish.argtypes = [P]
+    L.hg_plan_stats.argtypes = [P, ctypes.POINTER(hg_stats)]
+    L.hg_plan_counts.argtypes = [P, P]
+    L.hg_plan_weight_sums.argtypes = [P, P]
+    L.hg_plan_neighbours.argtypes = [P, P, P, P, i64, ctypes.POINTER(ctypes.c_int64)]
+    L.hg_ang2pix_ring.argtypes = [i32, P, P, i64, P, P]
+    for f in ABI_FUNCTIONS[:-1]:
+        getattr(L, f).restype = ctypes.c_int
+    L.hg_last_error.argtypes = []
+    L.hg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def last_error():
+    return lib().hg_last_error().decode()
+
+
+def _check(rc, what):
+    if rc != HG_OK:
+        raise HegridError(rc, f"{what}: {last_error()}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(x):
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if t.device.type != "cuda":
+        t = t.to("cuda")
+    return t.contiguous()
+
+
+def make_map(m):
+    return hg_map(float(m["ra0_deg"]), float(m["dec0_deg"]), float(m["dra_deg"]),
+                  float(m["ddec_deg"]), int(m["nx"]), int(m["ny"]))
+
+
+def make_kernel(k):
+    return hg_kernel(float(k["fwhm_deg"]), float(k["support_deg"]))
+
+
+_DTYPES = None
+
+
+def _dtype_code(t):
+    torch = _torch()
+    codes = {torch.float32: HG_F32, torch.bfloat16: HG_BF16, torch.float16: HG_F16}
+    if t.dtype not in codes:
+        raise HegridError(HG_ERR_ARG, f"unsupported value dtype {t.dtype}")
+    return codes[t.dtype]
+
+
+class Plan:
+    """A gridding plan: grid_setup on construction, grid_channels per call,
+    grid_finish on close()."""
+
+    def __init__(self, ra_deg, dec_deg, map, kernel, precision=HG_PREC_FP32, nside=0, chunk=0,
+                 device_mem_cap=0, time_channels=False, stream=None):
+        L = lib()
+        ra, dec = _dev_f64(ra_deg), _dev_f64(dec_deg)
+        if ra.shape != dec.shape or ra.dim() != 1:
+            raise HegridError(HG_ERR_ARG, "ra and dec must be 1-D and of equal length")
+        self.map = dict(map)
+        self.kernel = dict(kernel)
+        self.n = ra.shape[0]
+        self._m, self._k = make_map(map), make_kernel(kernel)
+        self._o = hg_opts(int(precision), int(nside), int(chunk), 0, int(device_mem_cap),
+                          HG_FLAG_TIME_CHANNELS if time_channels else 0, 0)
+        self._h = ctypes.c_void_p()
+        rc = L.hg_grid_setup(ctypes.c_void_p(ra.data_ptr() if self.n else 0),
+                             ctypes.c_void_p(dec.data_ptr() if self.n else 0), self.n,
+                             ctypes.byref(self._k), ctypes.byref(self._m), ctypes.byref(self._o),
+                             _stream_ptr(stream), ctypes.byref(self._h))
+        _check(rc, "hg_grid_setup")
+
+    @property
+    def shape(self):
+        return int(self.map["ny"]), int(self.map["nx"])
+
+    def _handle(self):
+        if not self._h:
+            raise HegridError(HG_ERR_STATE, "plan is closed")
+        return self._h
+
+    def grid(self, values, out=None, stream=None):
+        """values: cuda tensor [n][C] (float32 / bfloat16 / float16, unit
+        channel stride); returns float32 [C][ny][nx] on the same device."""
+        torch = _torch()
+        if values.dim() == 1:
+            values = values.reshape(-1, 1)
+        if values.shape[0] != self.n or values.stride(1) != 1 or values.device.type != "cuda":
+            raise HegridError(HG_ERR_ARG, "values must be a cuda tensor [n][C] with unit "
+                              "channel stride")
+        nchan = values.shape[1]
+        ny, nx = self.shape
+        if out is None:
+            out = torch.empty((nchan, ny, nx), dtype=torch.float32, device=values.device)
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != nchan * ny * nx:
+            raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 [C][ny][nx] tensor")
+        ld = values.stride(0) if values.shape[0] > 1 else nchan
+        rc = lib().hg_grid_channels(self._handle(), ctypes.c_void_p(values.data_ptr()), ld, nchan,
+                                    _dtype_code(values), ctypes.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream))
+        _check(rc, "hg_grid_channels")
+        return out
+
+    def stats(self):
+        st = hg_stats()
+        _check(lib().hg_plan_stats(self._handle(), ctypes.byref(st)), "hg_plan_stats")
+        return {f: getattr(st, f) for f, _ in hg_stats._fields_}
+
+    def counts(self):
+        ny, nx = self.shape
+        c = np.empty(ny * nx, dtype=np.int32)
+        _check(lib().hg_plan_counts(self._handle(), c.ctypes.data_as(ctypes.c_void_p)),
+               "hg_plan_counts")
+        return c
+
+    def weight_sums(self):
+        ny, nx = self.shape
+        w = np.empty(ny * nx, dtype=np.float64)
+        _check(lib().hg_plan_weight_sums(self._handle(), w.ctypes.data_as(ctypes.c_void_p)),
+               "hg_plan_weight_sums")
+        return w
+
+    def neighbours(self):
+        """(row_ptr, idx, w): per pixel, ascending original sample index."""
+        ny, nx = self.shape
+        row_ptr = np.zeros(ny * nx + 1, dtype=np.int64)
+        nnz = ctypes.c_int64(0)
+        L = lib()
+        _check(L.hg_plan_neighbours(self._handle(), row_ptr.ctypes.data_as(ctypes.c_void_p), None,
+                                    None, 0, ctypes.byref(nnz)), "hg_plan_neighbours")
+        idx = np.empty(max(nnz.value, 1), dtype=np.int64)
+        w = np.empty(max(nnz.value, 1), dtype=np.float32)
+        _check(L.hg_plan_neighbours(self._handle(), row_ptr.ctypes.data_as(ctypes.c_void_p),
+                                    idx.ctypes.data_as(ctypes.c_void_p),
+                                    w.ctypes.data_as(ctypes.c_void_p), nnz.value,
+                                    ctypes.byref(nnz)), "hg_plan_neighbours")
+        return row_ptr, idx[:nnz.value], w[:nnz.value]
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, ctypes.c_void_p()
+            _check(lib().hg_grid_finish(h), "hg_grid_finish")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ang2pix_ring(nside, ra_deg, dec_deg, stream=None):
+    """HEALPix RING pixel of each direction, computed by the library on the GPU."""
+    torch = _torch()
+    ra, dec = _dev_f64(ra_deg), _dev_f64(dec_deg)
+    pix = torch.empty(ra.shape[0], dtype=torch.int64, device=ra.device)
+    rc = lib().hg_ang2pix_ring(int(nside), ctypes.c_void_p(ra.data_ptr()),
+                               ctypes.c_void_p(dec.data_ptr()), ra.shape[0],
+                               ctypes.c_void_p(pix.data_ptr()), _stream_ptr(stream))
+    _check(rc, "hg_ang2pix_ring")
+    return pix

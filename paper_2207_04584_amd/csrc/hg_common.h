@@ -1,0 +1,202 @@
+// Internal declarations of libhegrid: HEALPix RING geometry, the plan's device
+// layout and the kernel launchers.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hegrid.h"
+
+namespace hg {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kDeg = 3.14159265358979323846 / 180.0;
+
+// Pixel groups (PG): 2 x 2 map pixels that share one neighbour walk and one
+// entry list; slot r = 2*(j&1) + (i&1).  Tiles: TILE_PGX x TILE_PGY groups
+// (16 x 16 pixels) that share one staged sample list in the channel kernels.
+constexpr int PG = 2;
+constexpr int TILE_PGX = 8;
+constexpr int TILE_PGY = 8;
+constexpr int TILE_PGS = TILE_PGX * TILE_PGY;
+constexpr uint32_t SLOT_MASK = 0x0FFFFFFFu;  // low 28 bits: tile-local slot
+constexpr int SLOT_SHIFT = 28;               // high 4 bits: in-support mask
+
+// ---------------------------------------------------------------------------
+// HEALPix RING scheme (Gorski et al. 2005; the partition used by the paper's
+// look-up table, Sec. 4.1.1).  Rings i = 1 .. 4N-1 from the north pole; ring
+// i holds n_i pixels numbered from `first`, centred at z_i, azimuths
+// (k + shift/2) 2 pi / n_i for k = 0 .. n_i - 1.
+struct Ring {
+    int64_t first;
+    int64_t n;
+    double z;
+    int shift;
+};
+
+__host__ __device__ inline Ring hp_ring(int64_t N, int64_t i) {
+    Ring r;
+    if (i < N) {
+        r.first = 2 * i * (i - 1);
+        r.n = 4 * i;
+        r.z = 1.0 - (double)(i * i) / (3.0 * (double)N * (double)N);
+        r.shift = 1;
+    } else if (i <= 3 * N) {
+        r.first = 2 * N * (N - 1) + (i - N) * 4 * N;
+        r.n = 4 * N;
+        r.z = 4.0 / 3.0 - 2.0 * (double)i / (3.0 * (double)N);
+        r.shift = (int)((i - N + 1) & 1);
+    } else {
+        int64_t k = 4 * N - i;
+        r.first = 12 * N * N - 2 * k * (k + 1);
+        r.n = 4 * k;
+        r.z = -(1.0 - (double)(k * k) / (3.0 * (double)N * (double)N));
+        r.shift = 1;
+    }
+    return r;
+}
+
+// Continuous ring coordinate of latitude z: ring centres sit at integers, and a
+// pixel of ring i covers latitudes strictly between rings i-1 and i+1.
+__host__ __device__ inline double hp_ring_coord(int64_t N, double z) {
+    if (z > 2.0 / 3.0) return (double)N * sqrt(3.0 * (1.0 - z));
+    if (z < -2.0 / 3.0) return 4.0 * (double)N - (double)N * sqrt(3.0 * (1.0 + z));
+    return (double)N * (2.0 - 1.5 * z);
+}
+
+__host__ __device__ inline int64_t floor_div2(int64_t a) { return (a >= 0) ? a / 2 : -((1 - a) / 2); }
+
+__host__ __device__ inline int64_t mod_pos(int64_t a, int64_t m) {
+    int64_t r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+// RING index of the pixel containing (z = sin Dec, phi = RA in radians).
+// In the equatorial belt (|z| <= 2/3) pixel edges are the lines
+// N (phi/(pi/2) + 1/2) -+ (3/4) N z = integer; in the polar caps they are the
+// curves t N sqrt(3 (1-|z|)) = integer and (1-t) N sqrt(3 (1-|z|)) = integer,
+// t the azimuth fraction within a base pixel.
+__host__ __device__ inline int64_t hp_ang2pix(int64_t N, double z, double phi) {
+    double twopi = 2.0 * kPi;
+    phi = fmod(phi, twopi);
+    if (phi < 0.0) phi += twopi;
+    double tt = phi / (0.5 * kPi);
+    if (tt >= 4.0) tt = 0.0;
+    double za = fabs(z);
+    if (za <= 2.0 / 3.0) {
+        double t1 = (double)N * (0.5 + tt);
+        double t2 = (double)N * z * 0.75;
+        int64_t jp = (int64_t)floor(t1 - t2);
+        int64_t jm = (int64_t)floor(t1 + t2);
+        int64_t ir = N + 1 + jp - jm;
+        int64_t kshift = 1 - (ir & 1);
+        int64_t ip = mod_pos(floor_div2(jp + jm - N + kshift + 1), 4 * N);
+        return 2 * N * (N - 1) + (ir - 1) * 4 * N + ip;
+    }
+    double tp = tt - floor(tt);
+    double tmp = (double)N * sqrt(3.0 * (1.0 - za));
+    int64_t jp = (int64_t)floor(tp * tmp);
+    int64_t jm = (int64_t)floor((1.0 - tp) * tmp);
+    int64_t ir = jp + jm + 1;
+    int64_t ip = mod_pos((int64_t)floor(tt * (double)ir), 4 * ir);
+    return (z > 0.0) ? 2 * ir * (ir - 1) + ip : 12 * N * N - 2 * ir * (ir + 1) + ip;
+}
+
+// Pixels of ring r whose azimuth extent (centre -+ pi/n) meets [pa, pb]
+// (radians, unwrapped), widened by one pixel each side.  Written as at most two
+// pieces of wrapped indices, in ascending order.  Returns the piece count.
+__host__ __device__ inline int hp_ring_pieces(const Ring& r, double pa, double pb, int64_t* a0,
+                                              int64_t* b0, int64_t* a1, int64_t* b1) {
+    double scale = (double)r.n / (2.0 * kPi);
+    double off = 0.5 * (double)r.shift;
+    int64_t ka = (int64_t)ceil(pa * scale - off - 0.5) - 1;
+    int64_t kb = (int64_t)floor(pb * scale - off + 0.5) + 1;
+    if (kb - ka + 1 >= r.n) {
+        *a0 = 0;
+        *b0 = r.n - 1;
+        return 1;
+    }
+    int64_t wa = mod_pos(ka, r.n), wb = mod_pos(kb, r.n);
+    if (wa <= wb) {
+        *a0 = wa;
+        *b0 = wb;
+        return 1;
+    }
+    *a0 = 0;
+    *b0 = wb;
+    *a1 = wa;
+    *b1 = r.n - 1;
+    return 2;
+}
+
+// ---------------------------------------------------------------------------
+// Plan: everything grid_setup leaves on the device for grid_channels.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    int device = 0;
+    // geometry and kernel constants (row a1)
+    hg_map map{};
+    hg_kernel kern{};
+    hg_opts opts{};
+    double sigma = 0, r_rad = 0, h_r = 0;
+    int64_t n = 0, n_used = 0;
+    int64_t nside = 0;
+    int64_t ring_lo = 0, ring_hi = 0;  // band of rings that can hold a neighbour
+    int64_t cell_base = 0, n_cells = 0;
+    int32_t npgx = 0, npgy = 0, ntx = 0, nty = 0;
+    int64_t npg = 0, ntiles = 0, npix = 0;
+    int32_t tile_rings = 0, pg_rings = 0;  // max rings per tile / per pixel group
+    int32_t chunk = 64;                    // tile slots per staged chunk
+    int64_t total_slots = 0, ent_cap = 0, nnz_entries = 0, chunk_ptrs = 0;
+    int64_t nnz = 0;  // (pixel, sample) pairs in support
+    double setup_ms = 0;
+    // device arrays
+    DevBuf srt_idx;      // uint32 [n_used]   original index, sorted by (cell, index)
+    DevBuf srt_coord;    // double4 [n_used]  (ra, dec, cos dec, -) radians
+    DevBuf cell_off;     // uint32 [n_cells+1]
+    DevBuf tile_piece;   // int4 [ntiles][tile_rings*2] (pos_a, len, slot0, cell_a)
+    DevBuf tile_nslots;  // int64 [ntiles+1] exclusive scan of slots per tile
+    DevBuf pg_piece;     // int4 [npg][pg_rings*2]   (pos_a, len, slot0, -)
+    DevBuf pg_base;      // int64 [npg+1] entry capacity scan
+    DevBuf pg_cnt;       // uint32 [npg] entries used
+    DevBuf slot_idx;     // uint32 [total_slots] original index of each tile slot
+    DevBuf ent_slot;     // uint32 [ent_cap] slot | mask << 28
+    DevBuf ent_w;        // float4 [ent_cap]
+    DevBuf cp_base;      // int64 [ntiles+1] chunk-pointer base per tile
+    DevBuf chunk_ptr;    // uint32 [chunk_ptrs] entry offset (relative to pg_base)
+    DevBuf pix_count;    // int32 [npix]
+    DevBuf pix_W;        // double [npix]
+    DevBuf pix_Wf;       // float [npix] W rounded to FP32 (0 where count = 0)
+    DevBuf scratch;      // small device scratch (flags, totals)
+    // channel-kernel timing: event pairs recorded around launches, resolved
+    // lazily (hg_plan_stats) so that timed calls stay asynchronous
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
+    int64_t ch_calls = 0, ch_timed_calls = 0;
+    double ch_ms_total = 0, ch_ms_last = 0;
+    bool finished = false;
+};
+
+// kernel launchers (setup.hip, channels.hip)
+hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hipStream_t s,
+                        std::string& err, int& status);
+hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
+                           float* out, hipStream_t s);
+hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
+                          int64_t* pix, hipStream_t s);
+
+void plan_band(Plan& P, double eps);
+
+// device memory (runtime.hip)
+hipError_t dev_alloc(DevBuf& b, size_t bytes);
+void dev_free(DevBuf& b);
+
+}  // namespace hg

@@ -1,0 +1,837 @@
+// Setup path of libhegrid: everything that depends only on the sample
+// positions, run once per field (the shared component of Sec. 4.3.1).
+//
+//   1. sky-cell binning: HEALPix RING ang2pix in FP64      (Sec. 4.1.1, step 1)
+//   2. counting sort by (cell, original index)             (steps 1 and 2)
+//   3. look-up table: CSR offsets per cell of the band     (step 4)
+//   4. tile / pixel-group planner: per ring, the cell range (hence the sample
+//      range) that can reach the group                     (Algorithm 1,
+//      ring_min..ring_max and pixel_min..pixel_max)
+//   5. neighbour gather: exact FP64 support test d <= R and Gaussian weight for
+//      every (pixel, candidate) pair                       (Algorithm 1, Eq. 1)
+//
+// This file is compiled with -ffp-contract=off so that the FP64 support test
+// and weight evaluate in the same operation order as a plain C evaluation of
+// the same formulas.
+#include "hg_common.h"
+
+namespace hg {
+namespace {
+
+constexpr uint32_t BAD_KEY = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// exclusive scan (reduce -> scan of block sums -> final), out has n + 1 items
+constexpr int SCAN_T = 256, SCAN_I = 16, SCAN_B = SCAN_T * SCAN_I;
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* sh, T& total) {
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = 0;
+        for (int w = 0; w < SCAN_T / 64; w++) {
+            T t = sh[w];
+            sh[w] = acc;
+            acc += t;
+        }
+        sh[SCAN_T / 64] = acc;
+    }
+    __syncthreads();
+    T res = x - v + sh[wid];
+    total = sh[SCAN_T / 64];
+    __syncthreads();
+    return res;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(SCAN_T) void k_scan_reduce(const Tin* in, int64_t n, Tout* bsum) {
+    __shared__ Tout sh[SCAN_T / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    Tout s = 0;
+    for (int k = 0; k < SCAN_I; k++) {
+        int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+        if (i < n) s += (Tout)in[i];
+    }
+    Tout tot;
+    block_exclusive_scan<Tout>(s, sh, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <typename Tout>
+__global__ __launch_bounds__(SCAN_T) void k_scan_bsums(Tout* bsum, int64_t nb) {
+    __shared__ Tout sh[SCAN_T / 64 + 1];
+    Tout carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_T) {
+        int64_t i = b0 + threadIdx.x;
+        Tout v = i < nb ? bsum[i] : (Tout)0;
+        Tout tot;
+        Tout ex = block_exclusive_scan<Tout>(v, sh, tot);
+        if (i < nb) bsum[i] = ex + carry;
+        carry += tot;
+    }
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(SCAN_T) void k_scan_final(const Tin* in, int64_t n, const Tout* bsum,
+                                                       Tout* out) {
+    __shared__ Tout vals[SCAN_B];
+    __shared__ Tout sh[SCAN_T / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    for (int k = 0; k < SCAN_I; k++) {
+        int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+        vals[k * SCAN_T + threadIdx.x] = i < n ? (Tout)in[i] : (Tout)0;
+    }
+    __syncthreads();
+    Tout s = 0;
+    for (int k = 0; k < SCAN_I; k++) s += vals[threadIdx.x * SCAN_I + k];
+    Tout tot;
+    Tout run = block_exclusive_scan<Tout>(s, sh, tot) + bsum[blockIdx.x];
+    for (int k = 0; k < SCAN_I; k++) {
+        Tout v = vals[threadIdx.x * SCAN_I + k];
+        vals[threadIdx.x * SCAN_I + k] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int k = 0; k < SCAN_I; k++) {
+        int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+        if (i < n) out[i] = vals[k * SCAN_T + threadIdx.x];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = run;
+}
+
+// scratch must hold ceil(n / SCAN_B) Tout
+template <typename Tin, typename Tout>
+hipError_t scan_exclusive(const Tin* in, int64_t n, Tout* out, Tout* scratch, hipStream_t s) {
+    int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n,
+                       scratch);
+    hipLaunchKernelGGL((k_scan_bsums<Tout>), dim3(1), dim3(SCAN_T), 0, s, scratch, nb);
+    hipLaunchKernelGGL((k_scan_final<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n,
+                       scratch, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__device__ inline double pix_ra(const hg_map& m, int64_t i) {
+    return (m.ra0_deg + ((double)i - (m.nx - 1) / 2.0) * m.dra_deg) * kDeg;
+}
+__device__ inline double pix_dec(const hg_map& m, int64_t j) {
+    return (m.dec0_deg + ((double)j - (m.ny - 1) / 2.0) * m.ddec_deg) * kDeg;
+}
+
+struct RowInfo {
+    int32_t ring_lo, nrings;
+    double dalpha;  // RA half-width (radians) that can hold a neighbour; > pi = any
+};
+
+// 1. binning ------------------------------------------------------------------
+__global__ void k_bin(const double* __restrict__ ra_deg, const double* __restrict__ dec_deg,
+                      int64_t n, int64_t nside, int64_t cell_base, int64_t n_cells,
+                      uint32_t* __restrict__ key, uint32_t* __restrict__ cnt, int* flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a = ra_deg[i], d = dec_deg[i];
+    if (!isfinite(a) || !isfinite(d) || fabs(d) > 90.0) {
+        atomicOr(flag, 1);
+        key[i] = BAD_KEY;
+        return;
+    }
+    int64_t c = hp_ang2pix(nside, sin(d * kDeg), a * kDeg) - cell_base;
+    if (c < 0 || c >= n_cells) {
+        key[i] = BAD_KEY;
+        return;
+    }
+    key[i] = (uint32_t)c;
+    atomicAdd(&cnt[c], 1u);
+}
+
+__global__ void k_ang2pix(const double* __restrict__ ra_deg, const double* __restrict__ dec_deg,
+                          int64_t n, int64_t nside, int64_t* __restrict__ pix) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a = ra_deg[i], d = dec_deg[i];
+    pix[i] = hp_ang2pix(nside, sin(d * kDeg), a * kDeg);
+}
+
+// 2. sort ------------------------------------------------------------------------
+__global__ void k_scatter(const uint32_t* __restrict__ key, int64_t n, uint32_t* __restrict__ cursor,
+                          uint32_t* __restrict__ srt_idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = key[i];
+    if (c == BAD_KEY) return;
+    uint32_t pos = atomicAdd(&cursor[c], 1u);
+    srt_idx[pos] = (uint32_t)i;
+}
+
+__device__ inline void sift_down(uint32_t* v, uint32_t root, uint32_t end) {
+    while (2 * root + 1 < end) {
+        uint32_t child = 2 * root + 1;
+        if (child + 1 < end && v[child] < v[child + 1]) child++;
+        if (v[root] < v[child]) {
+            uint32_t t = v[root];
+            v[root] = v[child];
+            v[child] = t;
+            root = child;
+        } else {
+            return;
+        }
+    }
+}
+
+// The atomic scatter leaves each cell's samples in arbitrary order; sorting
+// them by original index makes the key (cell, index) total and the layout
+// deterministic.
+__global__ void k_cell_sort(const uint32_t* __restrict__ off, int64_t n_cells,
+                            uint32_t* __restrict__ idx) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    uint32_t a = off[c], b = off[c + 1];
+    uint32_t len = b - a;
+    if (len < 2) return;
+    uint32_t* v = idx + a;
+    if (len <= 32) {
+        for (uint32_t t = 1; t < len; t++) {
+            uint32_t x = v[t];
+            uint32_t u = t;
+            while (u > 0 && v[u - 1] > x) {
+                v[u] = v[u - 1];
+                u--;
+            }
+            v[u] = x;
+        }
+        return;
+    }
+    for (uint32_t st = len / 2; st-- > 0;) sift_down(v, st, len);
+    for (uint32_t end = len - 1; end > 0; end--) {
+        uint32_t t = v[0];
+        v[0] = v[end];
+        v[end] = t;
+        sift_down(v, 0, end);
+    }
+}
+
+// 4. planner --------------------------------------------------------------------
+// Tile pieces: for ring k of the tile's band, up to two runs of cells (wrapped
+// indices, ascending) -> (first sorted position, length, first slot, packed
+// cell range a | b << 16).  Slots number the tile's candidates ring by ring.
+__global__ void k_tile_plan(const RowInfo* __restrict__ rows, int32_t ntx, int64_t ntiles,
+                            int32_t tile_rings, int64_t nside, int64_t cell_base, int64_t n_cells,
+                            const uint32_t* __restrict__ cell_off, hg_map m, double eps,
+                            int4* __restrict__ tile_piece, int* flag) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tile = gid / tile_rings;
+    int rk = (int)(gid % tile_rings);
+    if (tile >= ntiles) return;
+    int tx = (int)(tile % ntx), ty = (int)(tile / ntx);
+    RowInfo ri = rows[ty];
+    int4* out = tile_piece + (tile * tile_rings + rk) * 2;
+    out[0] = make_int4(0, 0, 0, 0);
+    out[1] = make_int4(0, 0, 0, 0);
+    if (rk >= ri.nrings) return;
+    Ring r = hp_ring(nside, ri.ring_lo + rk);
+    int64_t i0 = (int64_t)tx * TILE_PGX * PG;
+    int64_t i1 = i0 + TILE_PGX * PG - 1;
+    if (i1 > m.nx - 1) i1 = m.nx - 1;
+    double a0 = pix_ra(m, i0) - ri.dalpha - eps, a1 = pix_ra(m, i1) + ri.dalpha + eps;
+    int64_t pa[2], pb[2];
+    int np = hp_ring_pieces(r, a0, a1, &pa[0], &pb[0], &pa[1], &pb[1]);
+    for (int q = 0; q < np; q++) {
+        int64_t ka = r.first + pa[q] - cell_base, kb = r.first + pb[q] - cell_base;
+        if (ka < 0 || kb >= n_cells) {
+            atomicOr(flag, 4);
+            continue;
+        }
+        uint32_t p0 = cell_off[ka], p1 = cell_off[kb + 1];
+        out[q] = make_int4((int)p0, (int)(p1 - p0), 0, (int)(pa[q] | (pb[q] << 16)));
+    }
+}
+
+__global__ void k_tile_prefix(int4* __restrict__ tile_piece, int64_t ntiles, int32_t tile_rings,
+                              int32_t chunk, int64_t* __restrict__ tile_nslots,
+                              int64_t* __restrict__ tile_ncp, int* flag) {
+    int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
+    int4* tp = tile_piece + tile * tile_rings * 2;
+    int64_t s = 0;
+    for (int k = 0; k < 2 * tile_rings; k++) {
+        int4 p = tp[k];
+        p.z = (int)s;
+        tp[k] = p;
+        s += p.y;
+    }
+    if (s > (int64_t)SLOT_MASK) atomicOr(flag, 2);
+    tile_nslots[tile] = s;
+    tile_ncp[tile] = (int64_t)TILE_PGS * ((s + chunk - 1) / chunk + 1);
+}
+
+// Pixel-group pieces: the group's own ring / cell ranges, intersected with its
+// tile's pieces, as (first sorted position, length, first tile slot).
+__global__ void k_pg_plan(const RowInfo* __restrict__ pg_rows, const RowInfo* __restrict__ tile_rows,
+                          int32_t npgx, int64_t npg, int32_t ntx, int32_t pg_rings,
+                          int32_t tile_rings, int64_t nside, int64_t cell_base,
+                          const uint32_t* __restrict__ cell_off, hg_map m, double eps,
+                          const int4* __restrict__ tile_piece, int4* __restrict__ pg_piece,
+                          int* flag) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t pg = gid / pg_rings;
+    int rk = (int)(gid % pg_rings);
+    if (pg >= npg) return;
+    int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
+    int tx = gx / TILE_PGX, ty = gy / TILE_PGY;
+    int64_t tile = (int64_t)ty * ntx + tx;
+    RowInfo pr = pg_rows[gy];
+    int4* out = pg_piece + (pg * pg_rings + rk) * 2;
+    out[0] = make_int4(0, 0, 0, 0);
+    out[1] = make_int4(0, 0, 0, 0);
+    if (rk >= pr.nrings) return;
+    int64_t ring = pr.ring_lo + rk;
+    Ring r = hp_ring(nside, ring);
+    int64_t i0 = (int64_t)gx * PG, i1 = i0 + PG - 1;
+    if (i1 > m.nx - 1) i1 = m.nx - 1;
+    double a0 = pix_ra(m, i0) - pr.dalpha - eps, a1 = pix_ra(m, i1) + pr.dalpha + eps;
+    int64_t pa[2], pb[2];
+    int np = hp_ring_pieces(r, a0, a1, &pa[0], &pb[0], &pa[1], &pb[1]);
+    RowInfo tr = tile_rows[ty];
+    int64_t tk = ring - tr.ring_lo;
+    if (tk < 0 || tk >= tr.nrings) {
+        atomicOr(flag, 8);
+        return;
+    }
+    const int4* tp = tile_piece + (tile * tile_rings + tk) * 2;
+    int nout = 0;
+    for (int qt = 0; qt < 2; qt++) {
+        int4 t = tp[qt];
+        if (t.y == 0) continue;
+        int64_t A = t.w & 0xFFFF, B = (t.w >> 16) & 0xFFFF;
+        for (int qp = 0; qp < np; qp++) {
+            int64_t lo = pa[qp] > A ? pa[qp] : A, hi = pb[qp] < B ? pb[qp] : B;
+            if (lo > hi) continue;
+            uint32_t p0 = cell_off[r.first + lo - cell_base];
+            uint32_t p1 = cell_off[r.first + hi + 1 - cell_base];
+            if (p1 == p0) continue;
+            if (nout == 2) {
+                atomicOr(flag, 16);
+                continue;
+            }
+            out[nout++] = make_int4((int)p0, (int)(p1 - p0), t.z + (int)(p0 - (uint32_t)t.x), 0);
+        }
+    }
+}
+
+__global__ void k_pg_capacity(const int4* __restrict__ pg_piece, int64_t npg, int32_t pg_rings,
+                              int64_t* __restrict__ cap) {
+    int64_t pg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pg >= npg) return;
+    const int4* p = pg_piece + pg * pg_rings * 2;
+    int64_t s = 0;
+    for (int k = 0; k < 2 * pg_rings; k++) s += p[k].y;
+    cap[pg] = s;
+}
+
+__global__ __launch_bounds__(256) void k_slot_fill(const int4* __restrict__ tile_piece,
+                                                   int32_t tile_rings,
+                                                   const int64_t* __restrict__ tile_base,
+                                                   const uint32_t* __restrict__ srt_idx,
+                                                   uint32_t* __restrict__ slot_idx) {
+    int64_t tile = blockIdx.x;
+    const int4* tp = tile_piece + tile * tile_rings * 2;
+    uint32_t* dst = slot_idx + tile_base[tile];
+    for (int k = 0; k < 2 * tile_rings; k++) {
+        int4 p = tp[k];
+        for (int t = threadIdx.x; t < p.y; t += blockDim.x) dst[p.z + t] = srt_idx[p.x + t];
+    }
+}
+
+// 5. neighbour gather -------------------------------------------------------------
+// One wave per pixel group.  Lanes walk the group's candidates in slot order;
+// each lane tests its candidate against the group's (up to) four pixels with
+// the exact FP64 haversine test, and surviving candidates are compacted in
+// order into the group's entry list with their four FP32 weights.
+constexpr int GATHER_WAVES = 4;
+
+__global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
+    const int4* __restrict__ pg_piece, int32_t pg_rings, const int64_t* __restrict__ pg_base,
+    const double4* __restrict__ srt_coord, int32_t npgx, int64_t npg, hg_map m, double h_r,
+    double two_s2, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
+    uint32_t* __restrict__ pg_cnt, int32_t* __restrict__ pix_count, double* __restrict__ pix_W,
+    float* __restrict__ pix_Wf, unsigned long long* __restrict__ nnz_total) {
+    extern __shared__ int sh_gather[];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t pg = (int64_t)blockIdx.x * GATHER_WAVES + wave;
+    if (pg >= npg) return;  // uniform per wave; no block barrier below
+    int npc = 2 * pg_rings;
+    int* pref = sh_gather + wave * 3 * (npc + 1);
+    int* ppos = pref + (npc + 1);
+    int* pslot = ppos + (npc + 1);
+    const int4* pp = pg_piece + pg * npc;
+    if (lane == 0) {
+        int s = 0;
+        for (int k = 0; k < npc; k++) {
+            int4 p = pp[k];
+            pref[k] = s;
+            ppos[k] = p.x;
+            pslot[k] = p.z;
+            s += p.y;
+        }
+        pref[npc] = s;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int total = pref[npc];
+    int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
+    int64_t ix = (int64_t)gx * PG, iy = (int64_t)gy * PG;
+    bool vx1 = ix + 1 < m.nx, vy1 = iy + 1 < m.ny;
+    double pra0 = pix_ra(m, ix), pra1 = pix_ra(m, ix + 1);
+    double pdec0 = pix_dec(m, iy), pdec1 = pix_dec(m, iy + 1);
+    double pcos0 = cos(pdec0), pcos1 = cos(pdec1);
+    int cnt[4] = {0, 0, 0, 0};
+    double wsum[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t base_out = pg_base[pg];
+    int written = 0;
+    for (int v0 = 0; v0 < total; v0 += 64) {
+        int v = v0 + lane;
+        bool active = v < total;
+        uint32_t mask = 0;
+        float w[4] = {0.f, 0.f, 0.f, 0.f};
+        uint32_t slot = 0;
+        if (active) {
+            int lo = 0, hi = npc - 1;  // last piece with pref <= v
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (pref[mid] <= v)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            int off = v - pref[lo];
+            double4 c = srt_coord[ppos[lo] + off];
+            slot = (uint32_t)(pslot[lo] + off);
+            double sd0 = sin(0.5 * (c.y - pdec0)), sd1 = sin(0.5 * (c.y - pdec1));
+            double sa0 = sin(0.5 * (c.x - pra0)), sa1 = sin(0.5 * (c.x - pra1));
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                bool ok = ((k & 1) == 0 || vx1) && ((k >> 1) == 0 || vy1);
+                double sd = (k >> 1) ? sd1 : sd0;
+                double sa = (k & 1) ? sa1 : sa0;
+                double pc = (k >> 1) ? pcos1 : pcos0;
+                double h = sd * sd + pc * c.z * sa * sa;
+                if (ok && h <= h_r) {
+                    double d = 2.0 * asin(fmin(1.0, sqrt(h)));
+                    float wf = (float)exp(-(d * d) / two_s2);
+                    w[k] = wf;
+                    mask |= 1u << k;
+                    cnt[k] += 1;
+                    wsum[k] += (double)wf;
+                }
+            }
+        }
+        bool keep = active && mask != 0;
+        uint64_t bal = __ballot(keep);
+        if (keep) {
+            int o = written + __popcll(bal & ((1ull << lane) - 1ull));
+            ent_slot[base_out + o] = slot | (mask << SLOT_SHIFT);
+            ent_w[base_out + o] = make_float4(w[0], w[1], w[2], w[3]);
+        }
+        written += __popcll(bal);
+    }
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        int c = cnt[k];
+        double s = wsum[k];
+        for (int o = 32; o > 0; o >>= 1) {
+            c += __shfl_xor(c, o, 64);
+            s += __shfl_xor(s, o, 64);
+        }
+        cnt[k] = c;
+        wsum[k] = s;
+        tot += c;
+    }
+    if (lane == 0) {
+        pg_cnt[pg] = (uint32_t)written;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            int64_t i = ix + (k & 1), j = iy + (k >> 1);
+            if (i < m.nx && j < m.ny) {
+                int64_t p = j * m.nx + i;
+                pix_count[p] = cnt[k];
+                pix_W[p] = wsum[k];
+                pix_Wf[p] = (float)wsum[k];
+            }
+        }
+        atomicAdd(nnz_total, (unsigned long long)tot);
+    }
+}
+
+// Per (pixel group, chunk): first entry whose slot is in the chunk, relative to
+// the group's entry base; entries are in ascending slot order.
+__global__ __launch_bounds__(256) void k_chunk_ptr(
+    int32_t npgx, int64_t npg, int32_t ntx, int32_t chunk, const int64_t* __restrict__ tile_base,
+    const int64_t* __restrict__ cp_base, const int64_t* __restrict__ pg_base,
+    const uint32_t* __restrict__ pg_cnt, const uint32_t* __restrict__ ent_slot,
+    uint32_t* __restrict__ chunk_ptr) {
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t pg = (int64_t)blockIdx.x * 4 + wave;
+    if (pg >= npg) return;
+    int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
+    int64_t tile = (int64_t)(gy / TILE_PGY) * ntx + gx / TILE_PGX;
+    int lp = (gy % TILE_PGY) * TILE_PGX + gx % TILE_PGX;
+    int64_t nslots = tile_base[tile + 1] - tile_base[tile];
+    int64_t nch = (nslots + chunk - 1) / chunk;
+    uint32_t* cp = chunk_ptr + cp_base[tile] + (int64_t)lp * (nch + 1);
+    const uint32_t* es = ent_slot + pg_base[pg];
+    uint32_t ne = pg_cnt[pg];
+    for (int64_t c = lane; c <= nch; c += 64) {
+        uint32_t target = (uint32_t)(c * chunk);
+        uint32_t lo = 0, hi = ne;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if ((es[mid] & SLOT_MASK) < target)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        cp[c] = lo;
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// host-side ring band of a declination range [d0, d1] (radians) widened by r
+void ring_range(int64_t nside, double d0, double d1, double r, double eps, int32_t* lo,
+                int32_t* cnt) {
+    double za = sin(fmax(-0.5 * kPi, d0 - r - eps));
+    double zb = sin(fmin(0.5 * kPi, d1 + r + eps));
+    double t_lo = hp_ring_coord(nside, zb), t_hi = hp_ring_coord(nside, za);
+    int64_t a = (int64_t)floor(t_lo) - 1, b = (int64_t)ceil(t_hi) + 1;
+    if (a < 1) a = 1;
+    if (b > 4 * nside - 1) b = 4 * nside - 1;
+    *lo = (int32_t)a;
+    *cnt = (int32_t)(b - a + 1);
+}
+
+double ra_halfwidth(double d0, double d1, double r, double eps) {
+    double far = fmax(fabs(d0), fabs(d1));
+    if (far + r + eps >= 0.5 * kPi - 1e-12) return 4.0 * kPi;  // support reaches a pole
+    double x = sin(r) / cos(far);
+    if (x >= 1.0) return 4.0 * kPi;
+    return asin(x);
+}
+
+double host_pix_dec(const hg_map& m, int64_t j) {
+    return (m.dec0_deg + ((double)j - (m.ny - 1) / 2.0) * m.ddec_deg) * kDeg;
+}
+
+}  // namespace
+
+hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
+                          int64_t* pix, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ang2pix, dim3(blocks_for(n, 256)), dim3(256), 0, s, ra_deg, dec_deg, n,
+                       nside, pix);
+    return hipGetLastError();
+}
+
+// Plan geometry that needs no sample data (row a1 of the path): ring bands per
+// tile row and per pixel-group row.
+static void plan_rows(Plan& P, std::vector<RowInfo>& trows, std::vector<RowInfo>& prows,
+                      double eps) {
+    const hg_map& m = P.map;
+    trows.resize(P.nty);
+    prows.resize(P.npgy);
+    int32_t tmax = 1, pmax = 1;
+    for (int ty = 0; ty < P.nty; ty++) {
+        int64_t j0 = (int64_t)ty * TILE_PGY * PG, j1 = j0 + TILE_PGY * PG - 1;
+        if (j1 > m.ny - 1) j1 = m.ny - 1;
+        double d0 = host_pix_dec(m, j0), d1 = host_pix_dec(m, j1);
+        RowInfo ri;
+        ring_range(P.nside, d0, d1, P.r_rad, eps, &ri.ring_lo, &ri.nrings);
+        ri.dalpha = ra_halfwidth(d0, d1, P.r_rad, eps);
+        trows[ty] = ri;
+        if (ri.nrings > tmax) tmax = ri.nrings;
+    }
+    for (int gy = 0; gy < P.npgy; gy++) {
+        int64_t j0 = (int64_t)gy * PG, j1 = j0 + PG - 1;
+        if (j1 > m.ny - 1) j1 = m.ny - 1;
+        double d0 = host_pix_dec(m, j0), d1 = host_pix_dec(m, j1);
+        RowInfo ri;
+        ring_range(P.nside, d0, d1, P.r_rad, eps, &ri.ring_lo, &ri.nrings);
+        ri.dalpha = ra_halfwidth(d0, d1, P.r_rad, eps);
+        prows[gy] = ri;
+        if (ri.nrings > pmax) pmax = ri.nrings;
+    }
+    P.tile_rings = tmax;
+    P.pg_rings = pmax;
+}
+
+void plan_band(Plan& P, double eps) {
+    const hg_map& m = P.map;
+    double d0 = host_pix_dec(m, 0), d1 = host_pix_dec(m, m.ny - 1);
+    int32_t lo, cnt;
+    ring_range(P.nside, d0, d1, P.r_rad, eps, &lo, &cnt);
+    P.ring_lo = lo;
+    P.ring_hi = lo + cnt - 1;
+    Ring a = hp_ring(P.nside, P.ring_lo), b = hp_ring(P.nside, P.ring_hi);
+    P.cell_base = a.first;
+    P.n_cells = b.first + b.n - a.first;
+}
+
+// small kernel: gather the totals the host needs to size the second stage
+__global__ void k_totals(const uint32_t* cell_off, int64_t n_cells, const int64_t* tile_base,
+                         int64_t ntiles, const int64_t* pg_base, int64_t npg,
+                         const int64_t* cp_base, const int* flag, int64_t* out) {
+    out[0] = cell_off[n_cells];
+    out[1] = tile_base[ntiles];
+    out[2] = pg_base[npg];
+    out[3] = cp_base[ntiles];
+    out[4] = *flag;
+}
+
+__global__ void k_sorted_coords_dev(const double* __restrict__ ra_deg,
+                                    const double* __restrict__ dec_deg,
+                                    const uint32_t* __restrict__ srt_idx,
+                                    const uint32_t* __restrict__ n_used_dev, int64_t n,
+                                    double4* __restrict__ out) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n || q >= (int64_t)*n_used_dev) return;
+    uint32_t k = srt_idx[q];
+    double ra = ra_deg[k] * kDeg, dec = dec_deg[k] * kDeg;
+    out[q] = make_double4(ra, dec, cos(dec), 0.0);
+}
+
+// Runs the whole setup.  Allocation sizes that depend on the data are read
+// back once (one stream synchronisation in the middle, one at the end).
+hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hipStream_t s,
+                        std::string& err, int& status) {
+    const double eps = 1e-9;
+    status = HG_OK;
+    std::vector<RowInfo> trows, prows;
+    plan_rows(P, trows, prows, eps);
+    if (P.pg_rings > 2000) {
+        status = HG_ERR_UNSUPPORTED;
+        err = "support spans too many HEALPix rings; use a coarser nside";
+        return hipSuccess;
+    }
+    const int64_t n = P.n;
+    const int64_t npc_t = (int64_t)P.tile_rings * 2, npc_p = (int64_t)P.pg_rings * 2;
+    int64_t big = std::max<int64_t>(std::max<int64_t>(n, P.n_cells + 1),
+                                    std::max<int64_t>(P.npg + 1, P.ntiles + 1));
+    int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
+
+    DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, pcap, totals;
+    auto cleanup = [&]() {
+        dev_free(key);
+        dev_free(cnt);
+        dev_free(cursor);
+        dev_free(rows_t);
+        dev_free(rows_p);
+        dev_free(tslots);
+        dev_free(tcp);
+        dev_free(pcap);
+        dev_free(totals);
+    };
+#define HG_STEP(x)              \
+    do {                        \
+        hipError_t e_ = (x);    \
+        if (e_ != hipSuccess) { \
+            cleanup();          \
+            return e_;          \
+        }                       \
+    } while (0)
+    const int64_t n1 = n ? n : 1;
+    if (P.opts.device_mem_cap > 0) {
+        // first-stage footprint, checked before anything is allocated
+        size_t need = 64 + (size_t)scan_nb * 8 + 64 + (size_t)n1 * (4 + 4 + sizeof(double4)) +
+                      (size_t)(P.n_cells + 1) * 12 + sizeof(RowInfo) * (trows.size() + prows.size()) +
+                      sizeof(int4) * (size_t)(P.ntiles * npc_t + P.npg * npc_p) +
+                      sizeof(int64_t) * (size_t)(4 * (P.ntiles + 1) + 2 * (P.npg + 1)) +
+                      4 * (size_t)P.npg + 16 * (size_t)P.npix;
+        if ((int64_t)need > P.opts.device_mem_cap) {
+            status = HG_ERR_NOMEM;
+            err = "setup needs at least " + std::to_string(need) + " device bytes, over the cap";
+            return hipSuccess;
+        }
+    }
+    HG_STEP(dev_alloc(P.scratch, 64 + (size_t)scan_nb * 8));
+    HG_STEP(dev_alloc(totals, 64));
+    HG_STEP(dev_alloc(key, (size_t)n1 * 4));
+    HG_STEP(dev_alloc(cnt, (size_t)(P.n_cells + 1) * 4));
+    HG_STEP(dev_alloc(cursor, (size_t)(P.n_cells + 1) * 4));
+    HG_STEP(dev_alloc(P.cell_off, (size_t)(P.n_cells + 1) * 4));
+    HG_STEP(dev_alloc(P.srt_idx, (size_t)n1 * 4));
+    HG_STEP(dev_alloc(P.srt_coord, (size_t)n1 * sizeof(double4)));
+    HG_STEP(dev_alloc(rows_t, sizeof(RowInfo) * trows.size()));
+    HG_STEP(dev_alloc(rows_p, sizeof(RowInfo) * prows.size()));
+    HG_STEP(dev_alloc(P.tile_piece, sizeof(int4) * (size_t)(P.ntiles * npc_t)));
+    HG_STEP(dev_alloc(tslots, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+    HG_STEP(dev_alloc(tcp, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+    HG_STEP(dev_alloc(P.tile_nslots, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+    HG_STEP(dev_alloc(P.cp_base, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+    HG_STEP(dev_alloc(P.pg_piece, sizeof(int4) * (size_t)(P.npg * npc_p)));
+    HG_STEP(dev_alloc(pcap, sizeof(int64_t) * (size_t)(P.npg + 1)));
+    HG_STEP(dev_alloc(P.pg_base, sizeof(int64_t) * (size_t)(P.npg + 1)));
+    HG_STEP(dev_alloc(P.pg_cnt, sizeof(uint32_t) * (size_t)P.npg));
+    HG_STEP(dev_alloc(P.pix_count, sizeof(int32_t) * (size_t)P.npix));
+    HG_STEP(dev_alloc(P.pix_W, sizeof(double) * (size_t)P.npix));
+    HG_STEP(dev_alloc(P.pix_Wf, sizeof(float) * (size_t)P.npix));
+
+    int* flag = (int*)P.scratch.p;
+    unsigned long long* nnz_total = (unsigned long long*)((char*)P.scratch.p + 8);
+    void* scan_tmp = (char*)P.scratch.p + 64;
+
+    HG_STEP(hipMemsetAsync(P.scratch.p, 0, 64, s));
+    HG_STEP(hipMemsetAsync(cnt.p, 0, (size_t)(P.n_cells + 1) * 4, s));
+    HG_STEP(hipMemsetAsync(P.pix_count.p, 0, sizeof(int32_t) * (size_t)P.npix, s));
+    HG_STEP(hipMemsetAsync(P.pix_W.p, 0, sizeof(double) * (size_t)P.npix, s));
+    HG_STEP(hipMemsetAsync(P.pix_Wf.p, 0, sizeof(float) * (size_t)P.npix, s));
+    HG_STEP(hipMemsetAsync(P.pg_cnt.p, 0, sizeof(uint32_t) * (size_t)P.npg, s));
+    HG_STEP(hipMemcpyAsync(rows_t.p, trows.data(), sizeof(RowInfo) * trows.size(),
+                           hipMemcpyHostToDevice, s));
+    HG_STEP(hipMemcpyAsync(rows_p.p, prows.data(), sizeof(RowInfo) * prows.size(),
+                           hipMemcpyHostToDevice, s));
+
+    // 1-3: bin, count, look-up table, scatter, per-cell order, sorted coordinates
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, ra_deg, dec_deg, n,
+                           P.nside, P.cell_base, P.n_cells, (uint32_t*)key.p, (uint32_t*)cnt.p,
+                           flag);
+        HG_STEP(hipGetLastError());
+    }
+    HG_STEP((scan_exclusive<uint32_t, uint32_t>((const uint32_t*)cnt.p, P.n_cells,
+                                                (uint32_t*)P.cell_off.p, (uint32_t*)scan_tmp, s)));
+    if (n > 0) {
+        HG_STEP(hipMemcpyAsync(cursor.p, P.cell_off.p, (size_t)P.n_cells * 4,
+                               hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                           (const uint32_t*)key.p, n, (uint32_t*)cursor.p, (uint32_t*)P.srt_idx.p);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(P.n_cells, 256)), dim3(256), 0, s,
+                           (const uint32_t*)P.cell_off.p, P.n_cells, (uint32_t*)P.srt_idx.p);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_sorted_coords_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, ra_deg,
+                           dec_deg, (const uint32_t*)P.srt_idx.p,
+                           (const uint32_t*)P.cell_off.p + P.n_cells, n,
+                           (double4*)P.srt_coord.p);
+        HG_STEP(hipGetLastError());
+    }
+    // 4: planner (geometry and look-up table only)
+    {
+        int64_t nt = P.ntiles * P.tile_rings;
+        hipLaunchKernelGGL(k_tile_plan, dim3(blocks_for(nt, 256)), dim3(256), 0, s,
+                           (const RowInfo*)rows_t.p, P.ntx, P.ntiles, P.tile_rings, P.nside,
+                           P.cell_base, P.n_cells, (const uint32_t*)P.cell_off.p, P.map, eps,
+                           (int4*)P.tile_piece.p, flag);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_tile_prefix, dim3(blocks_for(P.ntiles, 256)), dim3(256), 0, s,
+                           (int4*)P.tile_piece.p, P.ntiles, P.tile_rings, P.chunk,
+                           (int64_t*)tslots.p, (int64_t*)tcp.p, flag);
+        HG_STEP(hipGetLastError());
+        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tslots.p, P.ntiles,
+                                                  (int64_t*)P.tile_nslots.p, (int64_t*)scan_tmp,
+                                                  s)));
+        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tcp.p, P.ntiles,
+                                                  (int64_t*)P.cp_base.p, (int64_t*)scan_tmp, s)));
+        int64_t np = P.npg * P.pg_rings;
+        hipLaunchKernelGGL(k_pg_plan, dim3(blocks_for(np, 256)), dim3(256), 0, s,
+                           (const RowInfo*)rows_p.p, (const RowInfo*)rows_t.p, P.npgx, P.npg,
+                           P.ntx, P.pg_rings, P.tile_rings, P.nside, P.cell_base,
+                           (const uint32_t*)P.cell_off.p, P.map, eps,
+                           (const int4*)P.tile_piece.p, (int4*)P.pg_piece.p, flag);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_pg_capacity, dim3(blocks_for(P.npg, 256)), dim3(256), 0, s,
+                           (const int4*)P.pg_piece.p, P.npg, P.pg_rings, (int64_t*)pcap.p);
+        HG_STEP(hipGetLastError());
+        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)pcap.p, P.npg,
+                                                  (int64_t*)P.pg_base.p, (int64_t*)scan_tmp, s)));
+    }
+    hipLaunchKernelGGL(k_totals, dim3(1), dim3(1), 0, s, (const uint32_t*)P.cell_off.p, P.n_cells,
+                       (const int64_t*)P.tile_nslots.p, P.ntiles, (const int64_t*)P.pg_base.p,
+                       P.npg, (const int64_t*)P.cp_base.p, (const int*)flag, (int64_t*)totals.p);
+    HG_STEP(hipGetLastError());
+    int64_t tot[5];
+    HG_STEP(hipMemcpyAsync(tot, totals.p, sizeof tot, hipMemcpyDeviceToHost, s));
+    HG_STEP(hipStreamSynchronize(s));
+    P.n_used = tot[0];
+    P.total_slots = tot[1];
+    P.ent_cap = tot[2];
+    P.chunk_ptrs = tot[3];
+    if (tot[4] & 1) {
+        status = HG_ERR_ARG;
+        err = "sample coordinates must be finite with |dec| <= 90 degrees";
+        cleanup();
+        return hipSuccess;
+    }
+    if (tot[4] & 2) {
+        status = HG_ERR_UNSUPPORTED;
+        err = "a tile holds more than 2^28 candidate samples";
+        cleanup();
+        return hipSuccess;
+    }
+    if (tot[4] & ~3) {
+        status = HG_ERR_INTERNAL;
+        err = "planner consistency check failed (flag " + std::to_string(tot[4]) + ")";
+        cleanup();
+        return hipSuccess;
+    }
+    if (P.opts.device_mem_cap > 0) {
+        size_t need = (size_t)P.total_slots * 4 + (size_t)P.ent_cap * 20 + (size_t)P.chunk_ptrs * 4;
+        size_t have = 0;
+        for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
+                          &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.cp_base, &P.pix_count, &P.pix_W,
+                          &P.pix_Wf, &P.scratch})
+            have += b->bytes;
+        if ((int64_t)(need + have) > P.opts.device_mem_cap) {
+            status = HG_ERR_NOMEM;
+            err = "plan needs " + std::to_string(need + have) + " device bytes, over the cap";
+            cleanup();
+            return hipSuccess;
+        }
+    }
+    HG_STEP(dev_alloc(P.slot_idx, (size_t)(P.total_slots ? P.total_slots : 1) * 4));
+    HG_STEP(dev_alloc(P.ent_slot, (size_t)(P.ent_cap ? P.ent_cap : 1) * 4));
+    HG_STEP(dev_alloc(P.ent_w, (size_t)(P.ent_cap ? P.ent_cap : 1) * 16));
+    HG_STEP(dev_alloc(P.chunk_ptr, (size_t)(P.chunk_ptrs ? P.chunk_ptrs : 1) * 4));
+
+    // 5: candidate slots, neighbour gather, chunk pointers
+    hipLaunchKernelGGL(k_slot_fill, dim3((unsigned)P.ntiles), dim3(256), 0, s,
+                       (const int4*)P.tile_piece.p, P.tile_rings, (const int64_t*)P.tile_nslots.p,
+                       (const uint32_t*)P.srt_idx.p, (uint32_t*)P.slot_idx.p);
+    HG_STEP(hipGetLastError());
+    {
+        size_t shm = (size_t)GATHER_WAVES * 3 * (npc_p + 1) * sizeof(int);
+        double two_s2 = 2.0 * P.sigma * P.sigma;
+        hipLaunchKernelGGL(k_gather, dim3(blocks_for(P.npg, GATHER_WAVES)), dim3(64 * GATHER_WAVES),
+                           shm, s, (const int4*)P.pg_piece.p, P.pg_rings,
+                           (const int64_t*)P.pg_base.p, (const double4*)P.srt_coord.p, P.npgx,
+                           P.npg, P.map, P.h_r, two_s2, (uint32_t*)P.ent_slot.p,
+                           (float4*)P.ent_w.p, (uint32_t*)P.pg_cnt.p, (int32_t*)P.pix_count.p,
+                           (double*)P.pix_W.p, (float*)P.pix_Wf.p, nnz_total);
+        HG_STEP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_chunk_ptr, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
+                       P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
+                       (const int64_t*)P.cp_base.p, (const int64_t*)P.pg_base.p,
+                       (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
+                       (uint32_t*)P.chunk_ptr.p);
+    HG_STEP(hipGetLastError());
+    unsigned long long nz = 0;
+    HG_STEP(hipMemcpyAsync(&nz, nnz_total, sizeof nz, hipMemcpyDeviceToHost, s));
+    HG_STEP(hipStreamSynchronize(s));
+    P.nnz = (int64_t)nz;
+    cleanup();
+    return hipSuccess;
+#undef HG_STEP
+}
+
+}  // namespace hg

@@ -1,0 +1,156 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, the ctypes structs match the header's layout, and argument errors are
+reported before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2207_04584_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hegrid.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree_on_entry_points():
+    assert declared_functions() == sorted(api.ABI_FUNCTIONS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = api.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", api.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (hg_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "hegrid.h"
+#define F(T, m) printf(#T " " #m " %zu %zu\n", offsetof(T, m), sizeof(((T*)0)->m));
+int main(void) {
+  printf("hg_map size %zu\nhg_kernel size %zu\nhg_opts size %zu\nhg_stats size %zu\n",
+         sizeof(hg_map), sizeof(hg_kernel), sizeof(hg_opts), sizeof(hg_stats));
+  %FIELDS%
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    lines = []
+    structs = {"hg_map": api.hg_map, "hg_kernel": api.hg_kernel, "hg_opts": api.hg_opts,
+               "hg_stats": api.hg_stats}
+    for cname, cls in structs.items():
+        for f, _ in cls._fields_:
+            lines.append(f"F({cname}, {f})")
+    src = tmp_path / "probe.c"
+    src.write_text(PROBE.replace("%FIELDS%", "\n  ".join(lines)))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    for ln in out.splitlines():
+        parts = ln.split()
+        if parts[1] == "size":
+            assert int(parts[2]) == ctypes.sizeof(structs[parts[0]]), ln
+        else:
+            desc = getattr(structs[parts[0]], parts[1])
+            assert (desc.offset, desc.size) == (int(parts[2]), int(parts[3])), ln
+
+
+def _setup(ra=None, dec=None, n=0, k=None, m=None, o=None, out=True):
+    L = api.lib()
+    h = ctypes.c_void_p(123)
+    rc = L.hg_grid_setup(ra, dec, n, ctypes.byref(k) if k else None,
+                         ctypes.byref(m) if m else None, ctypes.byref(o) if o else None, None,
+                         ctypes.byref(h) if out else None)
+    return rc, h
+
+
+def good():
+    return (api.hg_kernel(0.05, 0.064), api.hg_map(180.0, 30.0, 1 / 60, 1 / 60, 16, 16))
+
+
+@pytest.mark.parametrize("case", ["null_out", "null_kernel", "neg_n", "null_coords", "fwhm",
+                                  "support", "nx", "spacing", "pole", "nside", "chunk",
+                                  "reserved", "memcap"])
+def test_setup_rejects_bad_arguments_without_a_device(case):
+    k, m = good()
+    o = api.hg_opts()
+    kw = dict(k=k, m=m, o=o)
+    if case == "null_out":
+        kw["out"] = False
+    elif case == "null_kernel":
+        kw["k"] = None
+    elif case == "neg_n":
+        kw["n"] = -1
+    elif case == "null_coords":
+        kw["n"] = 5
+    elif case == "fwhm":
+        k.fwhm_deg = 0.0
+    elif case == "support":
+        k.support_deg = float("nan")
+    elif case == "nx":
+        m.nx = 0
+    elif case == "spacing":
+        m.ddec_deg = -1.0
+    elif case == "pole":
+        m.dec0_deg = 89.9
+    elif case == "nside":
+        o.nside = 3
+    elif case == "chunk":
+        o.chunk = 7
+    elif case == "reserved":
+        o.reserved = 1
+    elif case == "memcap":
+        o.device_mem_cap = -5
+    rc, h = _setup(**kw)
+    assert rc == api.HG_ERR_ARG, api.last_error()
+    assert api.last_error()
+    if case != "null_out":
+        assert not h.value  # *out is cleared on failure
+
+
+def test_unknown_precision_is_unsupported():
+    k, m = good()
+    o = api.hg_opts(precision=99)
+    rc, h = _setup(k=k, m=m, o=o)
+    assert rc == api.HG_ERR_UNSUPPORTED
+
+
+def test_channels_and_finish_state_rules():
+    L = api.lib()
+    assert L.hg_grid_finish(None) == api.HG_OK
+    assert L.hg_grid_channels(None, None, 1, 1, 0, None, None) == api.HG_ERR_ARG
+    st = api.hg_stats()
+    assert L.hg_plan_stats(None, ctypes.byref(st)) == api.HG_ERR_ARG
+    assert L.hg_plan_counts(None, None) == api.HG_ERR_ARG
+    assert L.hg_ang2pix_ring(0, None, None, 1, None, None) == api.HG_ERR_ARG
+    assert L.hg_ang2pix_ring(8, None, None, 0, None, None) == api.HG_OK  # nothing to do
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device path")
+def test_valid_setup_without_device_reports_device_error():
+    k, m = good()
+    rc, h = _setup(k=k, m=m, o=api.hg_opts())
+    assert rc == api.HG_ERR_DEVICE
+    assert "device" in api.last_error()
