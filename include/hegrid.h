@@ -73,7 +73,7 @@ typedef struct {
 typedef struct {
     int32_t precision;      /* HG_PREC_*; 0 = HG_PREC_FP32                      */
     int32_t nside;          /* HEALPix resolution of the sky cells; 0 = auto    */
-    int32_t chunk;          /* tile slots staged per step; 0 = default (64)     */
+    int32_t chunk;          /* tile slots staged per step: 0 (= 32), 8, 16, 24, 32 */
     int32_t reserved;       /* must be 0                                        */
     int64_t device_mem_cap; /* bytes; 0 = none.  Setup fails with HG_ERR_NOMEM
                                before any allocation beyond it                  */

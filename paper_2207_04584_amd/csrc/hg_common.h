@@ -26,6 +26,8 @@ constexpr int TILE_PGY = 8;
 constexpr int TILE_PGS = TILE_PGX * TILE_PGY;
 constexpr uint32_t SLOT_MASK = 0x0FFFFFFFu;  // low 28 bits: tile-local slot
 constexpr int SLOT_SHIFT = 28;               // high 4 bits: in-support mask
+constexpr int PGOFF_STRIDE = 68;             // uint16 per block: 65 offsets, padded to 136 B
+constexpr int MAX_CHUNK = 32;                // tile slots per staged chunk, upper bound
 
 // ---------------------------------------------------------------------------
 // HEALPix RING scheme (Gorski et al. 2005; the partition used by the paper's
@@ -155,7 +157,7 @@ struct Plan {
     int32_t npgx = 0, npgy = 0, ntx = 0, nty = 0;
     int64_t npg = 0, ntiles = 0, npix = 0;
     int32_t tile_rings = 0, pg_rings = 0;  // max rings per tile / per pixel group
-    int32_t chunk = 64;                    // tile slots per staged chunk
+    int32_t chunk = 32;                    // tile slots per staged chunk
     int64_t total_slots = 0, ent_cap = 0, nnz_entries = 0, chunk_ptrs = 0;
     int64_t nnz = 0;  // (pixel, sample) pairs in support
     double setup_ms = 0;
@@ -173,6 +175,13 @@ struct Plan {
     DevBuf ent_w;        // float4 [ent_cap]
     DevBuf cp_base;      // int64 [ntiles+1] chunk-pointer base per tile
     DevBuf chunk_ptr;    // uint32 [chunk_ptrs] entry offset (relative to pg_base)
+    // chunk-major entry blocks: block b = (tile t, chunk c), b = tile_blk[t] + c
+    int64_t n_blocks = 0;
+    DevBuf tile_blk;     // int64 [ntiles+1] first block of each tile
+    DevBuf blk_base;     // int64 [n_blocks+1] first entry of each block
+    DevBuf blk_pgoff;    // uint16 [n_blocks][PGOFF_STRIDE] per-group offsets in the block
+    DevBuf e2_w;         // float4 [entries] weights, block order
+    DevBuf e2_s;         // uint32 [entries] slot within the chunk, block order
     DevBuf pix_count;    // int32 [npix]
     DevBuf pix_W;        // double [npix]
     DevBuf pix_Wf;       // float [npix] W rounded to FP32 (0 where count = 0)

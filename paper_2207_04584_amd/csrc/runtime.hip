@@ -133,7 +133,8 @@ namespace {
 void plan_free(Plan& P) {
     for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                       &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.slot_idx, &P.ent_slot, &P.ent_w,
-                      &P.cp_base, &P.chunk_ptr, &P.pix_count, &P.pix_W, &P.pix_Wf, &P.scratch})
+                      &P.cp_base, &P.chunk_ptr, &P.pix_count, &P.pix_W, &P.pix_Wf, &P.scratch,
+                      &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s})
         dev_free(*b);
     for (auto& e : P.ev_pending) {
         (void)hipEventDestroy(e.first);
@@ -152,7 +153,7 @@ int64_t plan_bytes(const Plan& P) {
     for (const DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                             &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.slot_idx, &P.ent_slot, &P.ent_w,
                             &P.cp_base, &P.chunk_ptr, &P.pix_count, &P.pix_W, &P.pix_Wf,
-                            &P.scratch})
+                            &P.scratch, &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -197,8 +198,8 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
             return fail(HG_ERR_UNSUPPORTED, "unknown or unsupported precision form");
         if (o->nside < 0 || o->nside > 16384 || (o->nside & (o->nside - 1)))
             return fail(HG_ERR_ARG, "nside must be 0 or a power of two <= 16384");
-        if (o->chunk != 0 && (o->chunk < 8 || o->chunk > 128 || o->chunk % 8))
-            return fail(HG_ERR_ARG, "chunk must be 0 or a multiple of 8 in [8, 128]");
+        if (o->chunk != 0 && (o->chunk < 8 || o->chunk > MAX_CHUNK || o->chunk % 8))
+            return fail(HG_ERR_ARG, "chunk must be 0 or a multiple of 8 in [8, 32]");
         if (o->device_mem_cap < 0) return fail(HG_ERR_ARG, "device_mem_cap must be >= 0");
         if (o->reserved || o->reserved2) return fail(HG_ERR_ARG, "reserved fields must be 0");
     }
@@ -249,7 +250,7 @@ int hg_grid_setup(const double* ra_deg, const double* dec_deg, int64_t n, const 
         P.r_rad = k->support_deg * kDeg;
         double sh = sin(0.5 * P.r_rad);
         P.h_r = sh * sh;
-        P.chunk = (o && o->chunk) ? o->chunk : 64;
+        P.chunk = (o && o->chunk) ? o->chunk : MAX_CHUNK;
         P.npix = (int64_t)m->nx * m->ny;
         P.npgx = (m->nx + PG - 1) / PG;
         P.npgy = (m->ny + PG - 1) / PG;
@@ -351,7 +352,7 @@ int hg_plan_stats(hg_plan* h, hg_stats* st) {
         st->n_samples = P.n;
         st->n_used = P.n_used;
         st->nnz = P.nnz;
-        st->n_entries = 0;
+        st->n_entries = P.nnz_entries;
         st->n_cells = P.n_cells;
         st->total_slots = P.total_slots;
         st->device_bytes = plan_bytes(P);
@@ -361,12 +362,6 @@ int hg_plan_stats(hg_plan* h, hg_stats* st) {
         st->last_channels_ms = P.ch_ms_last;
         st->total_channels_ms = P.ch_ms_total;
         st->channels_calls = P.ch_calls;
-        if (P.npg > 0) {
-            std::vector<uint32_t> cnt(P.npg);
-            e = hipMemcpy(cnt.data(), P.pg_cnt.p, 4 * (size_t)P.npg, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return fail_hip(e, "plan_stats");
-            for (uint32_t c : cnt) st->n_entries += c;
-        }
         return HG_OK;
     });
 }

@@ -190,33 +190,82 @@ __device__ inline void sift_down(uint32_t* v, uint32_t root, uint32_t end) {
 
 // The atomic scatter leaves each cell's samples in arbitrary order; sorting
 // them by original index makes the key (cell, index) total and the layout
-// deterministic.
-__global__ void k_cell_sort(const uint32_t* __restrict__ off, int64_t n_cells,
-                            uint32_t* __restrict__ idx) {
+// deterministic.  Cells of up to SMALL_CELL samples are sorted by one thread;
+// larger cells go to a worklist sorted one workgroup per cell.
+constexpr uint32_t SMALL_CELL = 16;
+constexpr int BIG_SORT_T = 256;
+constexpr uint32_t BIG_SORT_MAX = 4096;
+
+__global__ void k_cell_sort_small(const uint32_t* __restrict__ off, int64_t n_cells,
+                                  uint32_t* __restrict__ idx, uint32_t* __restrict__ worklist,
+                                  uint32_t* __restrict__ wl_count) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     uint32_t a = off[c], b = off[c + 1];
     uint32_t len = b - a;
     if (len < 2) return;
-    uint32_t* v = idx + a;
-    if (len <= 32) {
-        for (uint32_t t = 1; t < len; t++) {
-            uint32_t x = v[t];
-            uint32_t u = t;
-            while (u > 0 && v[u - 1] > x) {
-                v[u] = v[u - 1];
-                u--;
-            }
-            v[u] = x;
-        }
+    if (len > SMALL_CELL) {
+        worklist[atomicAdd(wl_count, 1u)] = (uint32_t)c;
         return;
     }
-    for (uint32_t st = len / 2; st-- > 0;) sift_down(v, st, len);
-    for (uint32_t end = len - 1; end > 0; end--) {
-        uint32_t t = v[0];
-        v[0] = v[end];
-        v[end] = t;
-        sift_down(v, 0, end);
+    uint32_t* v = idx + a;
+    for (uint32_t t = 1; t < len; t++) {
+        uint32_t x = v[t];
+        uint32_t u = t;
+        while (u > 0 && v[u - 1] > x) {
+            v[u] = v[u - 1];
+            u--;
+        }
+        v[u] = x;
+    }
+}
+
+// One workgroup per listed cell: bitonic sort in LDS (padded to a power of
+// two with UINT32_MAX); cells beyond BIG_SORT_MAX fall back to a heap sort.
+__global__ __launch_bounds__(BIG_SORT_T) void k_cell_sort_big(
+    const uint32_t* __restrict__ off, uint32_t* __restrict__ idx,
+    const uint32_t* __restrict__ worklist, const uint32_t* __restrict__ wl_count) {
+    __shared__ uint32_t sv[BIG_SORT_MAX];
+    uint32_t nwork = *wl_count;
+    for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        uint32_t c = worklist[w];
+        uint32_t a = off[c], len = off[c + 1] - a;
+        uint32_t* v = idx + a;
+        if (len > BIG_SORT_MAX) {
+            if (threadIdx.x == 0) {
+                for (uint32_t st = len / 2; st-- > 0;) sift_down(v, st, len);
+                for (uint32_t end = len - 1; end > 0; end--) {
+                    uint32_t t = v[0];
+                    v[0] = v[end];
+                    v[end] = t;
+                    sift_down(v, 0, end);
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        uint32_t P = 1;
+        while (P < len) P <<= 1;
+        for (uint32_t i = threadIdx.x; i < P; i += BIG_SORT_T) sv[i] = i < len ? v[i] : 0xFFFFFFFFu;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = threadIdx.x; i < P; i += BIG_SORT_T) {
+                    uint32_t pj = i ^ j;
+                    if (pj > i) {
+                        uint32_t x = sv[i], y = sv[pj];
+                        bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            sv[i] = y;
+                            sv[pj] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < len; i += BIG_SORT_T) v[i] = sv[i];
+        __syncthreads();
     }
 }
 
@@ -258,7 +307,8 @@ __global__ void k_tile_plan(const RowInfo* __restrict__ rows, int32_t ntx, int64
 
 __global__ void k_tile_prefix(int4* __restrict__ tile_piece, int64_t ntiles, int32_t tile_rings,
                               int32_t chunk, int64_t* __restrict__ tile_nslots,
-                              int64_t* __restrict__ tile_ncp, int* flag) {
+                              int64_t* __restrict__ tile_ncp, int64_t* __restrict__ tile_nch,
+                              int* flag) {
     int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
     int4* tp = tile_piece + tile * tile_rings * 2;
@@ -272,6 +322,7 @@ __global__ void k_tile_prefix(int4* __restrict__ tile_piece, int64_t ntiles, int
     if (s > (int64_t)SLOT_MASK) atomicOr(flag, 2);
     tile_nslots[tile] = s;
     tile_ncp[tile] = (int64_t)TILE_PGS * ((s + chunk - 1) / chunk + 1);
+    tile_nch[tile] = (s + chunk - 1) / chunk;
 }
 
 // Pixel-group pieces: the group's own ring / cell ranges, intersected with its
@@ -587,15 +638,99 @@ void plan_band(Plan& P, double eps) {
     P.n_cells = b.first + b.n - a.first;
 }
 
+// Chunk-major entry blocks.  For tile t and chunk c, block b = tile_blk[t] + c
+// holds the entries of all 64 pixel groups whose slots fall in the chunk,
+// group after group (local order), each group's entries in slot order.  One
+// wave per block: lane k is pixel group k of the tile.
+__device__ inline int64_t tile_of_block(const int64_t* tile_blk, int64_t ntiles, int64_t b) {
+    int64_t lo = 0, hi = ntiles - 1;  // last tile with tile_blk[t] <= b
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (tile_blk[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+struct BlockLane {
+    int64_t tile, c, src;
+    int n;
+};
+
+__device__ inline BlockLane block_lane(int64_t b, int lane, int32_t npgx, int32_t npgy, int32_t ntx,
+                                       int64_t ntiles, const int64_t* tile_blk,
+                                       const int64_t* cp_base, const uint32_t* chunk_ptr,
+                                       const int64_t* pg_base) {
+    BlockLane r;
+    r.tile = tile_of_block(tile_blk, ntiles, b);
+    r.c = b - tile_blk[r.tile];
+    int64_t nch = tile_blk[r.tile + 1] - tile_blk[r.tile];
+    int tx = (int)(r.tile % ntx), ty = (int)(r.tile / ntx);
+    int gx = tx * TILE_PGX + lane % TILE_PGX, gy = ty * TILE_PGY + lane / TILE_PGX;
+    bool valid = gx < npgx && gy < npgy;
+    const uint32_t* cp = chunk_ptr + cp_base[r.tile] + (int64_t)lane * (nch + 1);
+    r.n = valid ? (int)(cp[r.c + 1] - cp[r.c]) : 0;
+    r.src = valid ? pg_base[(int64_t)gy * npgx + gx] + cp[r.c] : 0;
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_block_meta(
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks,
+    const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
+    const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
+    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff) {
+    int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (b >= n_blocks) return;  // uniform per wave
+    BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
+                             pg_base);
+    int x = r.n;  // inclusive scan over the 64 groups
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
+    po[lane] = (uint16_t)(x - r.n);
+    if (lane == 63) {
+        po[64] = (uint16_t)x;
+        po[65] = po[66] = po[67] = 0;
+        blk_cnt[b] = x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_block_fill(
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks, int32_t chunk,
+    const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
+    const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
+    const uint32_t* __restrict__ ent_slot, const float4* __restrict__ ent_w,
+    const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
+    float4* __restrict__ e2_w, uint32_t* __restrict__ e2_s) {
+    int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (b >= n_blocks) return;
+    BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
+                             pg_base);
+    int64_t dst = blk_base[b] + blk_pgoff[b * PGOFF_STRIDE + lane];
+    uint32_t s0 = (uint32_t)(r.c * chunk);
+    for (int t = 0; t < r.n; t++) {
+        e2_w[dst + t] = ent_w[r.src + t];
+        e2_s[dst + t] = (ent_slot[r.src + t] & SLOT_MASK) - s0;
+    }
+}
+
 // small kernel: gather the totals the host needs to size the second stage
 __global__ void k_totals(const uint32_t* cell_off, int64_t n_cells, const int64_t* tile_base,
                          int64_t ntiles, const int64_t* pg_base, int64_t npg,
-                         const int64_t* cp_base, const int* flag, int64_t* out) {
+                         const int64_t* cp_base, const int64_t* tile_blk, const int* flag,
+                         int64_t* out) {
     out[0] = cell_off[n_cells];
     out[1] = tile_base[ntiles];
     out[2] = pg_base[npg];
     out[3] = cp_base[ntiles];
     out[4] = *flag;
+    out[5] = tile_blk[ntiles];
 }
 
 __global__ void k_sorted_coords_dev(const double* __restrict__ ra_deg,
@@ -629,8 +764,11 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                     std::max<int64_t>(P.npg + 1, P.ntiles + 1));
     int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
 
-    DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, pcap, totals;
+    DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, wl;
     auto cleanup = [&]() {
+        dev_free(wl);
+        dev_free(tnch);
+        dev_free(bcnt);
         dev_free(key);
         dev_free(cnt);
         dev_free(cursor);
@@ -668,6 +806,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(key, (size_t)n1 * 4));
     HG_STEP(dev_alloc(cnt, (size_t)(P.n_cells + 1) * 4));
     HG_STEP(dev_alloc(cursor, (size_t)(P.n_cells + 1) * 4));
+    HG_STEP(dev_alloc(wl, (size_t)(P.n_cells + 2) * 4));  // [0] count, then cell ids
     HG_STEP(dev_alloc(P.cell_off, (size_t)(P.n_cells + 1) * 4));
     HG_STEP(dev_alloc(P.srt_idx, (size_t)n1 * 4));
     HG_STEP(dev_alloc(P.srt_coord, (size_t)n1 * sizeof(double4)));
@@ -676,6 +815,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(P.tile_piece, sizeof(int4) * (size_t)(P.ntiles * npc_t)));
     HG_STEP(dev_alloc(tslots, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
     HG_STEP(dev_alloc(tcp, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+    HG_STEP(dev_alloc(tnch, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+    HG_STEP(dev_alloc(P.tile_blk, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
     HG_STEP(dev_alloc(P.tile_nslots, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
     HG_STEP(dev_alloc(P.cp_base, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
     HG_STEP(dev_alloc(P.pg_piece, sizeof(int4) * (size_t)(P.npg * npc_p)));
@@ -716,8 +857,14 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            (const uint32_t*)key.p, n, (uint32_t*)cursor.p, (uint32_t*)P.srt_idx.p);
         HG_STEP(hipGetLastError());
-        hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(P.n_cells, 256)), dim3(256), 0, s,
-                           (const uint32_t*)P.cell_off.p, P.n_cells, (uint32_t*)P.srt_idx.p);
+        HG_STEP(hipMemsetAsync(wl.p, 0, 4, s));
+        hipLaunchKernelGGL(k_cell_sort_small, dim3(blocks_for(P.n_cells, 256)), dim3(256), 0, s,
+                           (const uint32_t*)P.cell_off.p, P.n_cells, (uint32_t*)P.srt_idx.p,
+                           (uint32_t*)wl.p + 1, (uint32_t*)wl.p);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_cell_sort_big, dim3(1024), dim3(BIG_SORT_T), 0, s,
+                           (const uint32_t*)P.cell_off.p, (uint32_t*)P.srt_idx.p,
+                           (const uint32_t*)wl.p + 1, (const uint32_t*)wl.p);
         HG_STEP(hipGetLastError());
         hipLaunchKernelGGL(k_sorted_coords_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, ra_deg,
                            dec_deg, (const uint32_t*)P.srt_idx.p,
@@ -735,8 +882,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(hipGetLastError());
         hipLaunchKernelGGL(k_tile_prefix, dim3(blocks_for(P.ntiles, 256)), dim3(256), 0, s,
                            (int4*)P.tile_piece.p, P.ntiles, P.tile_rings, P.chunk,
-                           (int64_t*)tslots.p, (int64_t*)tcp.p, flag);
+                           (int64_t*)tslots.p, (int64_t*)tcp.p, (int64_t*)tnch.p, flag);
         HG_STEP(hipGetLastError());
+        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tnch.p, P.ntiles,
+                                                  (int64_t*)P.tile_blk.p, (int64_t*)scan_tmp, s)));
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tslots.p, P.ntiles,
                                                   (int64_t*)P.tile_nslots.p, (int64_t*)scan_tmp,
                                                   s)));
@@ -757,15 +906,17 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     }
     hipLaunchKernelGGL(k_totals, dim3(1), dim3(1), 0, s, (const uint32_t*)P.cell_off.p, P.n_cells,
                        (const int64_t*)P.tile_nslots.p, P.ntiles, (const int64_t*)P.pg_base.p,
-                       P.npg, (const int64_t*)P.cp_base.p, (const int*)flag, (int64_t*)totals.p);
+                       P.npg, (const int64_t*)P.cp_base.p, (const int64_t*)P.tile_blk.p,
+                       (const int*)flag, (int64_t*)totals.p);
     HG_STEP(hipGetLastError());
-    int64_t tot[5];
+    int64_t tot[6];
     HG_STEP(hipMemcpyAsync(tot, totals.p, sizeof tot, hipMemcpyDeviceToHost, s));
     HG_STEP(hipStreamSynchronize(s));
     P.n_used = tot[0];
     P.total_slots = tot[1];
     P.ent_cap = tot[2];
     P.chunk_ptrs = tot[3];
+    P.n_blocks = tot[5];
     if (tot[4] & 1) {
         status = HG_ERR_ARG;
         err = "sample coordinates must be finite with |dec| <= 90 degrees";
@@ -802,6 +953,9 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(P.ent_slot, (size_t)(P.ent_cap ? P.ent_cap : 1) * 4));
     HG_STEP(dev_alloc(P.ent_w, (size_t)(P.ent_cap ? P.ent_cap : 1) * 16));
     HG_STEP(dev_alloc(P.chunk_ptr, (size_t)(P.chunk_ptrs ? P.chunk_ptrs : 1) * 4));
+    HG_STEP(dev_alloc(bcnt, sizeof(int64_t) * (size_t)(P.n_blocks + 1)));
+    HG_STEP(dev_alloc(P.blk_base, sizeof(int64_t) * (size_t)(P.n_blocks + 1)));
+    HG_STEP(dev_alloc(P.blk_pgoff, sizeof(uint16_t) * PGOFF_STRIDE * (size_t)(P.n_blocks + 1)));
 
     // 5: candidate slots, neighbour gather, chunk pointers
     hipLaunchKernelGGL(k_slot_fill, dim3((unsigned)P.ntiles), dim3(256), 0, s,
@@ -825,10 +979,38 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                        (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
                        (uint32_t*)P.chunk_ptr.p);
     HG_STEP(hipGetLastError());
+    // chunk-major blocks for the channel kernels
+    if (P.n_blocks > 0) {
+        hipLaunchKernelGGL(k_block_meta, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s, P.npgx,
+                           P.npgy, P.ntx, P.ntiles, P.n_blocks, (const int64_t*)P.tile_blk.p,
+                           (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
+                           (const int64_t*)P.pg_base.p, (int64_t*)bcnt.p,
+                           (uint16_t*)P.blk_pgoff.p);
+        HG_STEP(hipGetLastError());
+    }
+    HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)bcnt.p, P.n_blocks,
+                                              (int64_t*)P.blk_base.p, (int64_t*)scan_tmp, s)));
     unsigned long long nz = 0;
+    int64_t n_ent = 0;
     HG_STEP(hipMemcpyAsync(&nz, nnz_total, sizeof nz, hipMemcpyDeviceToHost, s));
+    HG_STEP(hipMemcpyAsync(&n_ent, (int64_t*)P.blk_base.p + P.n_blocks, sizeof n_ent,
+                           hipMemcpyDeviceToHost, s));
     HG_STEP(hipStreamSynchronize(s));
     P.nnz = (int64_t)nz;
+    P.nnz_entries = n_ent;
+    HG_STEP(dev_alloc(P.e2_w, (size_t)(n_ent ? n_ent : 1) * 16));
+    HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 4));
+    if (P.n_blocks > 0) {
+        hipLaunchKernelGGL(k_block_fill, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s, P.npgx,
+                           P.npgy, P.ntx, P.ntiles, P.n_blocks, P.chunk, (const int64_t*)P.tile_blk.p,
+                           (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
+                           (const int64_t*)P.pg_base.p,
+                           (const uint32_t*)P.ent_slot.p, (const float4*)P.ent_w.p,
+                           (const int64_t*)P.blk_base.p, (const uint16_t*)P.blk_pgoff.p,
+                           (float4*)P.e2_w.p, (uint32_t*)P.e2_s.p);
+        HG_STEP(hipGetLastError());
+    }
+    HG_STEP(hipStreamSynchronize(s));
     cleanup();
     return hipSuccess;
 #undef HG_STEP

@@ -157,7 +157,7 @@ def test_small_field_parity(name):
     check_field(ra, dec, vals, m, k)
 
 
-@pytest.mark.parametrize("nside,chunk", [(64, 8), (512, 128), (16384, 64), (4096, 16)])
+@pytest.mark.parametrize("nside,chunk", [(64, 8), (512, 32), (16384, 24), (4096, 16)])
 def test_nside_and_chunk_overrides(nside, chunk):
     ra, dec, vals, m, k = rand_field(21, 2500, 26, 23, 95.0, -20.0, C=7)
     check_field(ra, dec, vals, m, k, nside=nside, chunk=chunk)
