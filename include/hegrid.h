@@ -55,7 +55,10 @@ extern "C" {
 #define HG_F16 2  /* IEEE binary16 */
 
 /* accumulation form (hg_opts.precision) */
-#define HG_PREC_FP32 0 /* FP32 weights x FP32 values, FP32 accumulation      */
+#define HG_PREC_FP32 0      /* FP32 weights x FP32 values, FP32 accumulation     */
+#define HG_PREC_MFMA_BF16 1 /* BF16 weights x BF16 values on MFMA, FP32 accumulation;
+                               W is the sum of the same BF16-rounded weights        */
+#define HG_PREC_MFMA_F16 2  /* as above with FP16 weights and values              */
 
 typedef struct hg_plan hg_plan; /* opaque; owns all device memory it allocates */
 
@@ -71,7 +74,8 @@ typedef struct {
 } hg_kernel;
 
 typedef struct {
-    int32_t precision;      /* HG_PREC_*; 0 = HG_PREC_FP32                      */
+    int32_t precision;      /* HG_PREC_*; 0 = HG_PREC_FP32.  A BF16 / FP16 plan
+                               grids values of that type only                   */
     int32_t nside;          /* HEALPix resolution of the sky cells; 0 = auto    */
     int32_t chunk;          /* tile slots staged per step: 0 (= 32), 8, 16, 24, 32 */
     int32_t reserved;       /* must be 0                                        */

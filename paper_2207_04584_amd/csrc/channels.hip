@@ -10,21 +10,21 @@
 //     groups of 2 x 2) and one block of 256 channels;
 //   * the tile's candidate samples (its slots) are processed in chunks of
 //     `chunk` slots.  For each chunk the workgroup stages, in LDS, the 256
-//     channels of every slot (one 1 KB row per sample, read from the
+//     channels of every slot (one row per sample, read from the
 //     channel-contiguous values in HBM) and the chunk's entry block (the
-//     (group, slot, four weights) entries of all 64 groups, prepared by setup);
+//     entries of all 64 groups, prepared by setup);
 //   * staging is double-buffered: the loads for chunk c+1 go straight from
-//     global memory to LDS (global_load_lds) while the waves compute chunk c;
-//   * each wave owns 4 pixel groups spread over the tile; per entry it reads one 16-byte value
-//     vector per lane and issues four FP32 MFMA 4x4x1 (16 blocks)
-//     instructions: A = the group's four weights (rows = pixels), B = one
-//     value per lane (columns = channels 4*lane + g), so one entry updates
-//     4 pixels x 256 channels with FP32 multiply-adds;
-//   * FP32 summation is two-level: each chunk's entries accumulate into a
-//     fresh MFMA tile that is then added to the group's total, so no serial
+//     global memory to LDS (global_load_lds) while the waves compute chunk c,
+//     and chunk c+2's rows are prefetched into L2;
+//   * each wave owns 4 pixel groups spread over the tile.  The MFMA rows are
+//     the group's four pixels (A = their weights) and the columns are the
+//     workgroup's channels, 4*lane + g for the g-th instruction (B = values);
+//       - FP32 form: v_mfma_f32_4x4x1_16b_f32, one sample per instruction;
+//       - BF16 / FP16 forms: v_mfma_f32_4x4x4_16b_{bf16,f16}, four samples
+//         (one group of four entries) per instruction, FP32 accumulation;
+//   * summation is two-level: each chunk's entries accumulate into a fresh
+//     MFMA tile that is then added to the group's FP32 total, so no serial
 //     FP32 chain is longer than one chunk;
-//   * while chunk c is computed, chunk c+1 is being copied and chunk c+2's
-//     rows are prefetched into L2, so the copy that follows hits in L2;
 //   * the epilogue divides by the FP32 weight sum and writes [c][j][i] as
 //     rows of 16 pixels after a transpose through LDS.
 #include "hg_common.h"
@@ -33,36 +33,45 @@ namespace hg {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int CH_WAVES = 16;
 constexpr int CH_THREADS = 64 * CH_WAVES;
-constexpr int G = 4;        // 64-channel groups per workgroup
+constexpr int G = 4;        // MFMA column blocks of 64 channels per workgroup
 constexpr int CW = 64 * G;  // channels per workgroup (256)
 constexpr int PGW = TILE_PGS / CH_WAVES;
+static_assert(TILE_PGX == 8 && TILE_PGY == 8 && CH_WAVES == 16,
+              "wave/group mapping assumes 8x8 groups, 16 waves");
 constexpr int TILE_PX = TILE_PGX * PG;  // 16 pixels per tile side
 constexpr int OUT_STRIDE = CW / 2 + 4;  // LDS floats per pixel in the output transpose
 constexpr int OUT_LDS = TILE_PX * TILE_PX * OUT_STRIDE * 4;
 constexpr int TRASH_LDS = 256;
-static_assert(TILE_PGX == 8 && TILE_PGY == 8 && CH_WAVES == 16, "wave/group mapping assumes 8x8 groups, 16 waves");
 
-__device__ inline float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+constexpr int FORM_F32 = 0;  // FP32 values in LDS, one entry per MFMA
+constexpr int FORM_M16 = 1;  // 16-bit values in LDS, groups of four entries per MFMA
 
-__device__ inline float f16_bits_to_f32(uint32_t b) {
-    _Float16 h;
-    uint16_t u = (uint16_t)b;
-    __builtin_memcpy(&h, &u, 2);
-    return (float)h;
-}
+template <int FORM>
+struct Form {
+    static constexpr int VB = FORM == FORM_F32 ? 4 : 2;   // bytes per staged value
+    static constexpr int RB = CW * VB;                     // bytes per staged row
+    static constexpr int WB = FORM == FORM_F32 ? 16 : 32;  // weight bytes per unit
+    static constexpr int SB = FORM == FORM_F32 ? 4 : 16;   // slot bytes per unit
+    static constexpr int UPS = FORM == FORM_F32 ? 1 : 4;   // entries per unit
+};
 
 struct LdsLayout {
     int vals, ew, es, po, stride;
+    template <int FORM>
     __device__ __host__ static LdsLayout make(int chunk) {
+        typedef Form<FORM> F;
+        int max_units = TILE_PGS * ((chunk + F::UPS - 1) / F::UPS);
         LdsLayout L;
         L.vals = 0;
-        L.ew = L.vals + chunk * CW * 4;
-        L.es = L.ew + TILE_PGS * chunk * 16;
-        L.po = L.es + TILE_PGS * chunk * 4;
+        L.ew = L.vals + chunk * F::RB;
+        L.es = L.ew + max_units * F::WB;
+        L.po = L.es + max_units * F::SB;
         L.stride = L.po + 144;
         return L;
     }
@@ -71,8 +80,8 @@ struct LdsLayout {
 // Direct global -> LDS copies (lane i writes bytes [i*size, (i+1)*size) after
 // the wave-uniform LDS address).  They are issued through inline assembly so
 // that the compiler does not order every later LDS read behind them: the
-// kernel itself waits for them (s_waitcnt vmcnt(0)) before the barrier that
-// hands a staged chunk to the compute loop.
+// kernel itself waits for them (s_waitcnt vmcnt) before the barrier that hands
+// a staged chunk to the compute loop.
 __device__ inline uint32_t lds_addr(const char* l) {
     return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)l);
 }
@@ -89,15 +98,24 @@ __device__ inline void dma4(const void* g, const char* l) {
                  : "memory", "m0");
 }
 
-// One staged row: channels [c_lo, c_lo + 256) of sample `row`, as FP32.
+__device__ inline float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+__device__ inline float f16_bits_to_f32(uint32_t b) {
+    _Float16 h;
+    uint16_t u = (uint16_t)b;
+    __builtin_memcpy(&h, &u, 2);
+    return (float)h;
+}
+
+// FP32 form, one staged row (1 KB): channels [c_lo, c_lo + 256) of `row` as
+// FP32; lane l writes channels 4l .. 4l+3.
 template <int DT, bool VEC>
-__device__ inline void stage_row(char* dst, const void* values, int64_t ld, int32_t nchan, int c_lo,
-                                 uint32_t row, int lane) {
+__device__ inline void stage_row_f32(char* dst, const void* values, int64_t ld, int32_t nchan,
+                                     int c_lo, uint32_t row, int lane, bool dma) {
     int c = c_lo + 4 * lane;
     if (DT == HG_F32) {
         const float* src = (const float*)values + (int64_t)row * ld;
-        if (VEC && c_lo + CW <= nchan) {
-            // wave-uniform: whole row in range, 16-byte aligned -> direct to LDS
+        if (dma) {
             dma16(src + c, dst);
             return;
         }
@@ -132,24 +150,90 @@ __device__ inline void stage_row(char* dst, const void* values, int64_t ld, int3
     }
 }
 
-__device__ inline void mfma4(v4f* part, float a, float4 v) {
+// 16-bit forms, two staged rows (512 B each, adjacent in LDS) per wave
+// instruction: lanes 0-31 copy row a, lanes 32-63 row b, 8 channels per lane.
+template <bool VEC>
+__device__ inline void stage_rows_16(char* dst, const void* values, int64_t ld, int32_t nchan,
+                                     int c_lo, uint32_t row_a, uint32_t row_b, int nrows,
+                                     int lane, bool dma) {
+    int half = lane >> 5;
+    uint32_t row = half ? row_b : row_a;
+    int c = c_lo + 8 * (lane & 31);
+    const uint16_t* src = (const uint16_t*)values + (int64_t)row * ld + c;
+    if (dma) {
+        if (half < nrows) dma16(src, dst);
+        return;
+    }
+    if (half >= nrows) return;
+    uint32_t u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (VEC && c + 7 < nchan) {
+        uint4 raw = *(const uint4*)src;
+        u[0] = raw.x & 0xFFFF;
+        u[1] = raw.x >> 16;
+        u[2] = raw.y & 0xFFFF;
+        u[3] = raw.y >> 16;
+        u[4] = raw.z & 0xFFFF;
+        u[5] = raw.z >> 16;
+        u[6] = raw.w & 0xFFFF;
+        u[7] = raw.w >> 16;
+    } else {
+        for (int k = 0; k < 8; k++)
+            if (c + k < nchan) u[k] = src[k];
+    }
+    ((uint4*)dst)[lane] = make_uint4(u[0] | (u[1] << 16), u[2] | (u[3] << 16),
+                                     u[4] | (u[5] << 16), u[6] | (u[7] << 16));
+}
+
+__device__ inline void mfma4_f32(v4f* part, float a, float4 v) {
     part[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.x, part[0], 0, 0, 0);
     part[1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.y, part[1], 0, 0, 0);
     part[2] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.z, part[2], 0, 0, 0);
     part[3] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.w, part[3], 0, 0, 0);
 }
 
-template <int DT, bool VEC>
-__global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
+// One group of four entries on the 16-bit MFMA.  a: this lane's pixel's four
+// weights (entries 0..3); v0..v3: this lane's channels 4l..4l+3 of the four
+// entries' samples.  Column block g takes channel 4l+g of each entry.
+template <int DT>
+__device__ inline void mfma4_16(v4f* part, uint2 a, uint2 v0, uint2 v1, uint2 v2, uint2 v3) {
+    // B_g = {v0[g], v1[g], v2[g], v3[g]}: gather 16-bit halves
+    uint2 b[4];
+    b[0] = make_uint2(__builtin_amdgcn_perm(v1.x, v0.x, 0x05040100u),
+                      __builtin_amdgcn_perm(v3.x, v2.x, 0x05040100u));
+    b[1] = make_uint2(__builtin_amdgcn_perm(v1.x, v0.x, 0x07060302u),
+                      __builtin_amdgcn_perm(v3.x, v2.x, 0x07060302u));
+    b[2] = make_uint2(__builtin_amdgcn_perm(v1.y, v0.y, 0x05040100u),
+                      __builtin_amdgcn_perm(v3.y, v2.y, 0x05040100u));
+    b[3] = make_uint2(__builtin_amdgcn_perm(v1.y, v0.y, 0x07060302u),
+                      __builtin_amdgcn_perm(v3.y, v2.y, 0x07060302u));
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        if (DT == HG_BF16) {
+            v4s A, B;
+            __builtin_memcpy(&A, &a, 8);
+            __builtin_memcpy(&B, &b[g], 8);
+            part[g] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A, B, part[g], 0, 0, 0);
+        } else {
+            v4h A, B;
+            __builtin_memcpy(&A, &a, 8);
+            __builtin_memcpy(&B, &b[g], 8);
+            part[g] = __builtin_amdgcn_mfma_f32_4x4x4f16(A, B, part[g], 0, 0, 0);
+        }
+    }
+}
+
+template <int FORM, int DT, bool VEC>
+__global__ __launch_bounds__(CH_THREADS) void k_channels(
     const void* __restrict__ values, int64_t ld, int32_t nchan, int32_t ncb, int32_t npgx,
     int32_t npgy, int32_t ntx, int64_t ntiles, int32_t nx, int32_t ny, int32_t chunk,
     const int64_t* __restrict__ tile_base, const uint32_t* __restrict__ slot_idx,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ blk_base,
-    const uint16_t* __restrict__ blk_pgoff, const float4* __restrict__ e2_w,
-    const uint32_t* __restrict__ e2_s, const float* __restrict__ pix_Wf, float* __restrict__ out,
+    const uint16_t* __restrict__ blk_pgoff, const void* __restrict__ ent_w,
+    const void* __restrict__ ent_s, const float* __restrict__ pix_Wf, float* __restrict__ out,
     int32_t out_vec) {
+    typedef Form<FORM> F;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const LdsLayout L = LdsLayout::make(chunk);
+    const LdsLayout L = LdsLayout::make<FORM>(chunk);
     char* trash = smem + 2 * L.stride;
 
     // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -164,8 +248,9 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int c_lo = (int)cb * CW;
-    // value rows go straight to LDS when they are FP32, aligned and complete
-    const bool dma_rows = DT == HG_F32 && VEC && c_lo + CW <= nchan;
+    // value rows go straight to LDS when they need no conversion, are aligned
+    // and are complete
+    const bool dma_rows = (FORM == FORM_F32 ? DT == HG_F32 : true) && VEC && c_lo + CW <= nchan;
 
     const int64_t s_base = tile_base[tile];
     const int64_t nslots = tile_base[tile + 1] - s_base;
@@ -185,10 +270,11 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
         pv[k] = tx * TILE_PGX + lxs[k] < npgx && ty * TILE_PGY + lys[k] < npgy;
     }
 
-    // Per chunk each wave needs its staged rows' sample indices and the entry
-    // block's range.  All indices are wave-uniform, so these are scalar loads:
-    // the vector-memory counter then only counts the asynchronous copies,
-    // which the pipeline below waits for explicitly.
+    // Per chunk each wave stages two rows: (w, w+16) in the FP32 form and the
+    // adjacent pair (2w, 2w+1) in the 16-bit forms.  All indices are
+    // wave-uniform, so the metadata comes through scalar loads and the vector
+    // memory counter only counts the asynchronous copies, which the pipeline
+    // waits for explicitly.
     struct Meta {
         uint32_t row0, row1, first;
         int nrows;
@@ -199,10 +285,12 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
         Meta m;
         int64_t s0 = ch * chunk;
         int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
+        int r0 = FORM == FORM_F32 ? wave : 2 * wave;
+        int r1 = FORM == FORM_F32 ? wave + CH_WAVES : 2 * wave + 1;
         m.first = sidx[s0];
-        m.nrows = (wave < ns) + (wave + CH_WAVES < ns);  // chunk <= 32: at most two rows
-        m.row0 = wave < ns ? sidx[s0 + wave] : m.first;
-        m.row1 = wave + CH_WAVES < ns ? sidx[s0 + wave + CH_WAVES] : m.first;
+        m.nrows = (r0 < ns) + (r1 < ns);  // chunk <= 32: at most two rows per wave
+        m.row0 = r0 < ns ? sidx[s0 + r0] : m.first;
+        m.row1 = r1 < ns ? sidx[s0 + r1] : m.first;
         m.blk = blk0 + ch;
         m.eb = blk_base[m.blk];
         m.ne = (int)(blk_base[m.blk + 1] - m.eb);
@@ -210,29 +298,46 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
     };
     auto issue = [&](const Meta& m, int buf) {
         char* base = smem + buf * L.stride;
-        if (m.nrows > 0)
-            stage_row<DT, VEC>(base + L.vals + wave * CW * 4, values, ld, nchan, c_lo, m.row0,
-                               lane);
-        if (m.nrows > 1)
-            stage_row<DT, VEC>(base + L.vals + (wave + CH_WAVES) * CW * 4, values, ld, nchan,
-                               c_lo, m.row1, lane);
-        for (int i = wave * 64; i < m.ne; i += CH_THREADS) {
-            if (i + lane < m.ne) {
-                dma16(e2_w + m.eb + i + lane, base + L.ew + i * 16);
-                dma4(e2_s + m.eb + i + lane, base + L.es + i * 4);
+        if (FORM == FORM_F32) {
+            if (m.nrows > 0)
+                stage_row_f32<DT, VEC>(base + L.vals + wave * F::RB, values, ld, nchan, c_lo,
+                                       m.row0, lane, dma_rows);
+            if (m.nrows > 1)
+                stage_row_f32<DT, VEC>(base + L.vals + (wave + CH_WAVES) * F::RB, values, ld,
+                                       nchan, c_lo, m.row1, lane, dma_rows);
+            const float4* w = (const float4*)ent_w + m.eb;
+            const uint32_t* sl = (const uint32_t*)ent_s + m.eb;
+            for (int i = wave * 64; i < m.ne; i += CH_THREADS) {
+                if (i + lane < m.ne) {
+                    dma16(w + i + lane, base + L.ew + i * 16);
+                    dma4(sl + i + lane, base + L.es + i * 4);
+                }
             }
+        } else {
+            if (m.nrows > 0)
+                stage_rows_16<VEC>(base + L.vals + 2 * wave * F::RB, values, ld, nchan, c_lo,
+                                   m.row0, m.row1, m.nrows, lane, dma_rows);
+            // a group's weights are 32 bytes (two lanes), its slots 16 bytes (one lane)
+            const char* w = (const char*)ent_w + m.eb * 32;
+            for (int i = wave * 32; i < m.ne; i += CH_WAVES * 32)
+                if (i + (lane >> 1) < m.ne)
+                    dma16(w + (int64_t)i * 32 + lane * 16, base + L.ew + i * 32);
+            const uint4* sl = (const uint4*)ent_s + m.eb;
+            for (int i = wave * 64; i < m.ne; i += CH_THREADS)
+                if (i + lane < m.ne) dma16(sl + i + lane, base + L.es + i * 16);
         }
         if (wave == CH_WAVES - 1 && lane < PGOFF_STRIDE / 2)
             dma4((const uint32_t*)(blk_pgoff + m.blk * PGOFF_STRIDE) + lane, base + L.po);
     };
     // L2 prefetch of a later chunk's rows: exactly one copy instruction per
-    // wave (lanes touch both halves of every 128-byte line of the wave's rows;
-    // the data lands in a scratch area of LDS and is never read).
+    // wave (lanes touch both halves of every 128-byte line of the wave's two
+    // rows; the data lands in a scratch area of LDS and is never read).
     auto prefetch = [&](const Meta& m) {
-        int q = lane >> 4, part = lane & 15;
+        constexpr int LINES = F::RB / 64;  // 64-byte halves per row: 16 or 8
+        int q = lane / LINES, part = lane % LINES;
         uint32_t row = q == 0 ? m.row0 : m.row1;
-        const float* src = (const float*)values + (int64_t)row * ld + c_lo + part * 16;
-        if (lane < 32 && (q < m.nrows || lane == 0)) dma4(src, trash);
+        const char* src = (const char*)values + ((int64_t)row * ld + c_lo) * F::VB + part * 64;
+        if (lane < 2 * LINES && (q < m.nrows || lane == 0)) dma4(src, trash);
     };
 
     v4f acc[PGW][G];
@@ -274,34 +379,53 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
             m2 = m3;
         }
         const char* base = smem + (ch & 1) * L.stride;
-        const float* vals = (const float*)(base + L.vals);
-        const float* ew = (const float*)(base + L.ew);
+        const char* vals = base + L.vals;
+        const char* ew = base + L.ew;
         const uint32_t* es = (const uint32_t*)(base + L.es);
         const uint16_t* po = (const uint16_t*)(base + L.po);
 #pragma unroll
         for (int k = 0; k < PGW; k++) {
             if (!pv[k]) continue;
             int lp = lys[k] * TILE_PGX + lxs[k];
-            // the group's entry range is wave-uniform: keep it in scalar registers
+            // the group's unit range is wave-uniform: keep it in scalar registers
             int e = __builtin_amdgcn_readfirstlane((int)po[lp]);
             int e1 = __builtin_amdgcn_readfirstlane((int)po[lp + 1]);
             if (e == e1) continue;
             v4f part[G];
 #pragma unroll
             for (int g = 0; g < G; g++) part[g] = (v4f){0.f, 0.f, 0.f, 0.f};
-            // The group's run of at most `chunk` (<= 64) slots is read with one
-            // coalesced LDS load, lane i holding entry e+i; each entry's slot
-            // then comes from v_readlane into a scalar register, so the value
-            // read needs no second LDS round trip.
             const int q = lane & 3;
-            const int n = e1 - e;
-            uint32_t slot_lane = es[e + (lane < n ? lane : 0)];
-            const float* ewq = ew + e * 4 + q;
-            for (int j = 0; j < n; j++) {
-                uint32_t sj = __builtin_amdgcn_readlane(slot_lane, j);
-                float a0 = ewq[j * 4];
-                float4 v0 = ((const float4*)(vals + sj * CW))[lane];
-                mfma4(part, a0, v0);
+            if (FORM == FORM_F32) {
+                // The group's run of at most `chunk` slots is read with one
+                // coalesced LDS load, lane i holding entry e+i; each entry's
+                // slot then comes from v_readlane into a scalar register, so
+                // the value read needs no second LDS round trip.
+                const int n = e1 - e;
+                uint32_t slot_lane = es[e + (lane < n ? lane : 0)];
+                const float* ewq = (const float*)ew + e * 4 + q;
+                for (int j = 0; j < n; j++) {
+                    uint32_t sj = __builtin_amdgcn_readlane(slot_lane, j);
+                    float a0 = ewq[j * 4];
+                    float4 v0 = *(const float4*)(vals + sj * F::RB + lane * 16);
+                    mfma4_f32(part, a0, v0);
+                }
+            } else {
+                // groups of four entries; their slots (at most 4 x chunk/4)
+                // are read with one coalesced load and picked by v_readlane
+                const int n = 4 * (e1 - e);
+                uint32_t slot_lane = es[4 * e + (lane < n ? lane : 0)];
+                for (int t = 0; t < e1 - e; t++) {
+                    uint32_t s0 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 0);
+                    uint32_t s1 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 1);
+                    uint32_t s2 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 2);
+                    uint32_t s3 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 3);
+                    uint2 a = *(const uint2*)(ew + (e + t) * 32 + q * 8);
+                    uint2 v0 = *(const uint2*)(vals + s0 * F::RB + lane * 8);
+                    uint2 v1 = *(const uint2*)(vals + s1 * F::RB + lane * 8);
+                    uint2 v2 = *(const uint2*)(vals + s2 * F::RB + lane * 8);
+                    uint2 v3 = *(const uint2*)(vals + s3 * F::RB + lane * 8);
+                    mfma4_16<DT>(part, a, v0, v1, v2, v3);
+                }
             }
 #pragma unroll
             for (int g = 0; g < G; g++) acc[k][g] += part[g];
@@ -315,7 +439,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
     __syncthreads();
     float* ol = (float*)smem;
     const int64_t P = (int64_t)nx * ny;
-    const int x0 = tx * TILE_PGX * PG, y0 = ty * TILE_PGY * PG;
+    const int x0 = tx * TILE_PX, y0 = ty * TILE_PX;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         if ((lane >> 5) == h) {
@@ -352,25 +476,26 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_fp32(
     }
 }
 
-template <int DT, bool VEC>
+template <int FORM, int DT, bool VEC>
 hipError_t launch_typed(Plan& P, const void* values, int64_t ld, int32_t nchan, float* out,
                         hipStream_t s) {
     int64_t ncb = (nchan + CW - 1) / CW;
     int64_t nwg = ncb * P.ntiles;
-    size_t shm = (size_t)2 * LdsLayout::make(P.chunk).stride + TRASH_LDS;
+    size_t shm = (size_t)2 * LdsLayout::make<FORM>(P.chunk).stride + TRASH_LDS;
     if (shm < (size_t)OUT_LDS) shm = OUT_LDS;
-    auto kern = k_channels_fp32<DT, VEC>;
+    auto kern = k_channels<FORM, DT, VEC>;
     if (shm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
+    const void* ew = FORM == FORM_F32 ? P.e2_w.p : P.e3_w.p;
+    const void* es = FORM == FORM_F32 ? P.e2_s.p : P.e3_s.p;
     hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(CH_THREADS), shm, s, values, ld, nchan,
                        (int32_t)ncb, P.npgx, P.npgy, P.ntx, P.ntiles, P.map.nx, P.map.ny, P.chunk,
                        (const int64_t*)P.tile_nslots.p, (const uint32_t*)P.slot_idx.p,
                        (const int64_t*)P.tile_blk.p, (const int64_t*)P.blk_base.p,
-                       (const uint16_t*)P.blk_pgoff.p, (const float4*)P.e2_w.p,
-                       (const uint32_t*)P.e2_s.p, (const float*)P.pix_Wf.p, out,
+                       (const uint16_t*)P.blk_pgoff.p, ew, es, (const float*)P.pix_Wf.p, out,
                        (int32_t)(((uintptr_t)out % 16 == 0) && (P.map.nx % 4 == 0)));
     return hipGetLastError();
 }
@@ -380,17 +505,25 @@ hipError_t launch_typed(Plan& P, const void* values, int64_t ld, int32_t nchan, 
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
                            float* out, hipStream_t s) {
     uintptr_t a = (uintptr_t)values;
+    if (P.opts.precision == HG_PREC_MFMA_BF16 || P.opts.precision == HG_PREC_MFMA_F16) {
+        bool vec = (a % 16 == 0) && (ld % 8 == 0);  // 16-byte rows of 8 values
+        if (dtype == HG_BF16)
+            return vec ? launch_typed<FORM_M16, HG_BF16, true>(P, values, ld, nchan, out, s)
+                       : launch_typed<FORM_M16, HG_BF16, false>(P, values, ld, nchan, out, s);
+        return vec ? launch_typed<FORM_M16, HG_F16, true>(P, values, ld, nchan, out, s)
+                   : launch_typed<FORM_M16, HG_F16, false>(P, values, ld, nchan, out, s);
+    }
     if (dtype == HG_F32) {
         bool vec = (a % 16 == 0) && (ld % 4 == 0);
-        return vec ? launch_typed<HG_F32, true>(P, values, ld, nchan, out, s)
-                   : launch_typed<HG_F32, false>(P, values, ld, nchan, out, s);
+        return vec ? launch_typed<FORM_F32, HG_F32, true>(P, values, ld, nchan, out, s)
+                   : launch_typed<FORM_F32, HG_F32, false>(P, values, ld, nchan, out, s);
     }
     bool vec = (a % 8 == 0) && (ld % 4 == 0);
     if (dtype == HG_BF16)
-        return vec ? launch_typed<HG_BF16, true>(P, values, ld, nchan, out, s)
-                   : launch_typed<HG_BF16, false>(P, values, ld, nchan, out, s);
-    return vec ? launch_typed<HG_F16, true>(P, values, ld, nchan, out, s)
-               : launch_typed<HG_F16, false>(P, values, ld, nchan, out, s);
+        return vec ? launch_typed<FORM_F32, HG_BF16, true>(P, values, ld, nchan, out, s)
+                   : launch_typed<FORM_F32, HG_BF16, false>(P, values, ld, nchan, out, s);
+    return vec ? launch_typed<FORM_F32, HG_F16, true>(P, values, ld, nchan, out, s)
+               : launch_typed<FORM_F32, HG_F16, false>(P, values, ld, nchan, out, s);
 }
 
 }  // namespace hg

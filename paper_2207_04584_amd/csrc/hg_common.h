@@ -182,6 +182,9 @@ struct Plan {
     DevBuf blk_pgoff;    // uint16 [n_blocks][PGOFF_STRIDE] per-group offsets in the block
     DevBuf e2_w;         // float4 [entries] weights, block order
     DevBuf e2_s;         // uint32 [entries] slot within the chunk, block order
+    // precision forms: entries in groups of four per pixel group (the MFMA K)
+    DevBuf e3_w;         // uint16 [groups][4 pixels][4 entries] BF16 / FP16 weights
+    DevBuf e3_s;         // uint4  [groups] chunk-local slots of the four entries
     DevBuf pix_count;    // int32 [npix]
     DevBuf pix_W;        // double [npix]
     DevBuf pix_Wf;       // float [npix] W rounded to FP32 (0 where count = 0)

@@ -134,7 +134,7 @@ void plan_free(Plan& P) {
     for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                       &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.slot_idx, &P.ent_slot, &P.ent_w,
                       &P.cp_base, &P.chunk_ptr, &P.pix_count, &P.pix_W, &P.pix_Wf, &P.scratch,
-                      &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s})
+                      &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s, &P.e3_w, &P.e3_s})
         dev_free(*b);
     for (auto& e : P.ev_pending) {
         (void)hipEventDestroy(e.first);
@@ -153,7 +153,8 @@ int64_t plan_bytes(const Plan& P) {
     for (const DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                             &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.slot_idx, &P.ent_slot, &P.ent_w,
                             &P.cp_base, &P.chunk_ptr, &P.pix_count, &P.pix_W, &P.pix_Wf,
-                            &P.scratch, &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s})
+                            &P.scratch, &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s,
+                            &P.e3_w, &P.e3_s})
         s += (int64_t)b->bytes;
     return s;
 }
@@ -194,7 +195,8 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
     if (!(d0 > -90.0) || !(d1 < 90.0))
         return fail(HG_ERR_ARG, "pixel centres must lie strictly between the poles");
     if (o) {
-        if (o->precision != HG_PREC_FP32)
+        if (o->precision != HG_PREC_FP32 && o->precision != HG_PREC_MFMA_BF16 &&
+            o->precision != HG_PREC_MFMA_F16)
             return fail(HG_ERR_UNSUPPORTED, "unknown or unsupported precision form");
         if (o->nside < 0 || o->nside > 16384 || (o->nside & (o->nside - 1)))
             return fail(HG_ERR_ARG, "nside must be 0 or a power of two <= 16384");
@@ -298,6 +300,10 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
         if (nchan == 0) return HG_OK;
         if (!out || (!values && P.n > 0)) return fail(HG_ERR_ARG, "values and out must not be NULL");
         if (ld < nchan) return fail(HG_ERR_ARG, "ld must be >= nchan");
+        if (P.opts.precision == HG_PREC_MFMA_BF16 && dtype != HG_BF16)
+            return fail(HG_ERR_UNSUPPORTED, "a BF16-MFMA plan grids BF16 values");
+        if (P.opts.precision == HG_PREC_MFMA_F16 && dtype != HG_F16)
+            return fail(HG_ERR_UNSUPPORTED, "an FP16-MFMA plan grids FP16 values");
         hipError_t e = hipSetDevice(P.device);
         if (e != hipSuccess) return fail_hip(e, "grid_channels");
         hipStream_t s = (hipStream_t)hip_stream;

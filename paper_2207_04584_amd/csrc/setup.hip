@@ -404,6 +404,19 @@ __global__ __launch_bounds__(256) void k_slot_fill(const int4* __restrict__ tile
 }
 
 // 5. neighbour gather -------------------------------------------------------------
+// Weights are stored in FP32; the precision forms round them to the MFMA input
+// type first (round to nearest even), so that W is the sum of exactly the
+// weights the kernels multiply by.
+__device__ inline float round_weight(float w, int32_t prec) {
+    if (prec == HG_PREC_MFMA_BF16) {
+        uint32_t u = __float_as_uint(w);
+        u += 0x7FFFu + ((u >> 16) & 1u);  // finite positive weights only
+        return __uint_as_float(u & 0xFFFF0000u);
+    }
+    if (prec == HG_PREC_MFMA_F16) return (float)(_Float16)w;
+    return w;
+}
+
 // One wave per pixel group.  Lanes walk the group's candidates in slot order;
 // each lane tests its candidate against the group's (up to) four pixels with
 // the exact FP64 haversine test, and surviving candidates are compacted in
@@ -413,7 +426,7 @@ constexpr int GATHER_WAVES = 4;
 __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     const int4* __restrict__ pg_piece, int32_t pg_rings, const int64_t* __restrict__ pg_base,
     const double4* __restrict__ srt_coord, int32_t npgx, int64_t npg, hg_map m, double h_r,
-    double two_s2, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
+    double two_s2, int32_t prec, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
     uint32_t* __restrict__ pg_cnt, int32_t* __restrict__ pix_count, double* __restrict__ pix_W,
     float* __restrict__ pix_Wf, unsigned long long* __restrict__ nnz_total) {
     extern __shared__ int sh_gather[];
@@ -479,7 +492,7 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 double h = sd * sd + pc * c.z * sa * sa;
                 if (ok && h <= h_r) {
                     double d = 2.0 * asin(fmin(1.0, sqrt(h)));
-                    float wf = (float)exp(-(d * d) / two_s2);
+                    float wf = round_weight((float)exp(-(d * d) / two_s2), prec);
                     w[k] = wf;
                     mask |= 1u << k;
                     cnt[k] += 1;
@@ -717,6 +730,79 @@ __global__ __launch_bounds__(256) void k_block_fill(
     for (int t = 0; t < r.n; t++) {
         e2_w[dst + t] = ent_w[r.src + t];
         e2_s[dst + t] = (ent_slot[r.src + t] & SLOT_MASK) - s0;
+    }
+}
+
+// Precision forms: the same blocks, counted in groups of four entries (the K
+// of the 4x4x4 MFMA).  A group holds four chunk-local slots and the 4 x 4 weights
+// [pixel][entry] as BF16 / FP16 bits; a run whose length is not a multiple of
+// four is padded with zero weights on its last slot.
+__global__ __launch_bounds__(256) void k_block_meta_g(
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks,
+    const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
+    const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
+    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff) {
+    int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (b >= n_blocks) return;
+    BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
+                             pg_base);
+    int ng = (r.n + 3) >> 2;
+    int x = ng;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
+    po[lane] = (uint16_t)(x - ng);
+    if (lane == 63) {
+        po[64] = (uint16_t)x;
+        po[65] = po[66] = po[67] = 0;
+        blk_cnt[b] = x;
+    }
+}
+
+__device__ inline uint16_t weight_bits(float w, int32_t prec) {
+    if (prec == HG_PREC_MFMA_BF16) return (uint16_t)(__float_as_uint(w) >> 16);  // already rounded
+    _Float16 h = (_Float16)w;
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
+}
+
+__global__ __launch_bounds__(256) void k_block_fill_g(
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks, int32_t chunk,
+    int32_t prec, const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
+    const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
+    const uint32_t* __restrict__ ent_slot, const float4* __restrict__ ent_w,
+    const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
+    uint16_t* __restrict__ e3_w, uint4* __restrict__ e3_s) {
+    int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (b >= n_blocks) return;
+    BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
+                             pg_base);
+    int64_t dst = blk_base[b] + blk_pgoff[b * PGOFF_STRIDE + lane];
+    uint32_t s0 = (uint32_t)(r.c * chunk);
+    int ng = (r.n + 3) >> 2;
+    for (int t = 0; t < ng; t++) {
+        uint32_t sl[4];
+        float w[4][4];  // [entry][pixel]
+        for (int k = 0; k < 4; k++) {
+            int e = 4 * t + k;
+            bool real = e < r.n;
+            int ee = real ? e : r.n - 1;
+            sl[k] = (ent_slot[r.src + ee] & SLOT_MASK) - s0;
+            float4 wv = ent_w[r.src + ee];
+            w[k][0] = real ? wv.x : 0.f;
+            w[k][1] = real ? wv.y : 0.f;
+            w[k][2] = real ? wv.z : 0.f;
+            w[k][3] = real ? wv.w : 0.f;
+        }
+        e3_s[dst + t] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
+        uint16_t* wd = e3_w + (dst + t) * 16;
+        for (int i = 0; i < 4; i++)
+            for (int k = 0; k < 4; k++) wd[i * 4 + k] = weight_bits(w[k][i], prec);
     }
 }
 
@@ -968,7 +1054,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         hipLaunchKernelGGL(k_gather, dim3(blocks_for(P.npg, GATHER_WAVES)), dim3(64 * GATHER_WAVES),
                            shm, s, (const int4*)P.pg_piece.p, P.pg_rings,
                            (const int64_t*)P.pg_base.p, (const double4*)P.srt_coord.p, P.npgx,
-                           P.npg, P.map, P.h_r, two_s2, (uint32_t*)P.ent_slot.p,
+                           P.npg, P.map, P.h_r, two_s2, P.opts.precision, (uint32_t*)P.ent_slot.p,
                            (float4*)P.ent_w.p, (uint32_t*)P.pg_cnt.p, (int32_t*)P.pix_count.p,
                            (double*)P.pix_W.p, (float*)P.pix_Wf.p, nnz_total);
         HG_STEP(hipGetLastError());
@@ -980,12 +1066,13 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                        (uint32_t*)P.chunk_ptr.p);
     HG_STEP(hipGetLastError());
     // chunk-major blocks for the channel kernels
+    const bool grouped = P.opts.precision != HG_PREC_FP32;
     if (P.n_blocks > 0) {
-        hipLaunchKernelGGL(k_block_meta, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s, P.npgx,
-                           P.npgy, P.ntx, P.ntiles, P.n_blocks, (const int64_t*)P.tile_blk.p,
-                           (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
-                           (const int64_t*)P.pg_base.p, (int64_t*)bcnt.p,
-                           (uint16_t*)P.blk_pgoff.p);
+        hipLaunchKernelGGL(grouped ? k_block_meta_g : k_block_meta, dim3(blocks_for(P.n_blocks, 4)),
+                           dim3(256), 0, s, P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks,
+                           (const int64_t*)P.tile_blk.p, (const int64_t*)P.cp_base.p,
+                           (const uint32_t*)P.chunk_ptr.p, (const int64_t*)P.pg_base.p,
+                           (int64_t*)bcnt.p, (uint16_t*)P.blk_pgoff.p);
         HG_STEP(hipGetLastError());
     }
     HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)bcnt.p, P.n_blocks,
@@ -998,17 +1085,33 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(hipStreamSynchronize(s));
     P.nnz = (int64_t)nz;
     P.nnz_entries = n_ent;
-    HG_STEP(dev_alloc(P.e2_w, (size_t)(n_ent ? n_ent : 1) * 16));
-    HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 4));
-    if (P.n_blocks > 0) {
-        hipLaunchKernelGGL(k_block_fill, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s, P.npgx,
-                           P.npgy, P.ntx, P.ntiles, P.n_blocks, P.chunk, (const int64_t*)P.tile_blk.p,
-                           (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
-                           (const int64_t*)P.pg_base.p,
-                           (const uint32_t*)P.ent_slot.p, (const float4*)P.ent_w.p,
-                           (const int64_t*)P.blk_base.p, (const uint16_t*)P.blk_pgoff.p,
-                           (float4*)P.e2_w.p, (uint32_t*)P.e2_s.p);
-        HG_STEP(hipGetLastError());
+    if (grouped) {
+        HG_STEP(dev_alloc(P.e3_w, (size_t)(n_ent ? n_ent : 1) * 32));
+        HG_STEP(dev_alloc(P.e3_s, (size_t)(n_ent ? n_ent : 1) * 16));
+        if (P.n_blocks > 0) {
+            hipLaunchKernelGGL(k_block_fill_g, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s,
+                               P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks, P.chunk,
+                               P.opts.precision, (const int64_t*)P.tile_blk.p,
+                               (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
+                               (const int64_t*)P.pg_base.p, (const uint32_t*)P.ent_slot.p,
+                               (const float4*)P.ent_w.p, (const int64_t*)P.blk_base.p,
+                               (const uint16_t*)P.blk_pgoff.p, (uint16_t*)P.e3_w.p,
+                               (uint4*)P.e3_s.p);
+            HG_STEP(hipGetLastError());
+        }
+    } else {
+        HG_STEP(dev_alloc(P.e2_w, (size_t)(n_ent ? n_ent : 1) * 16));
+        HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 4));
+        if (P.n_blocks > 0) {
+            hipLaunchKernelGGL(k_block_fill, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s,
+                               P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks, P.chunk,
+                               (const int64_t*)P.tile_blk.p, (const int64_t*)P.cp_base.p,
+                               (const uint32_t*)P.chunk_ptr.p, (const int64_t*)P.pg_base.p,
+                               (const uint32_t*)P.ent_slot.p, (const float4*)P.ent_w.p,
+                               (const int64_t*)P.blk_base.p, (const uint16_t*)P.blk_pgoff.p,
+                               (float4*)P.e2_w.p, (uint32_t*)P.e2_s.p);
+            HG_STEP(hipGetLastError());
+        }
     }
     HG_STEP(hipStreamSynchronize(s));
     cleanup();
