@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the whole gridding path on one MI355X.
 
-Workload: 1,000,000 samples on 40 drift-scan tracks over a 5 x 5 degree field,
-a 300 x 300 map at 1 arcmin, Gaussian FWHM 3 arcmin with 3 sigma support, 1024
-FP32 channels (synthetic, seeded).  One step = the whole path on that batch:
-grid_setup (FP64 binning, sort, look-up table, planner, neighbour gather) +
-grid_channels (all 1024 channels) + finish, with coordinates and values
-already resident in HBM.
+Default workload (drift): 1,000,000 samples on 40 drift-scan tracks over a
+5 x 5 degree field, a 300 x 300 map at 1 arcmin, Gaussian FWHM 3 arcmin with
+3 sigma support, 1024 FP32 channels (synthetic, seeded).  One step = the whole
+path on that batch: grid_setup (FP64 binning, sort, look-up table, planner,
+neighbour gather) + grid_channels (all 1024 channels) + finish, with
+coordinates and values already resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+--workload batch: 64 independent fields (sample counts log-uniform in
+1e4..2e6, square maps of side 32..512 at 1 arcmin, 256 / 1024 / 4096 FP16
+channels, FWHM U(2, 5) arcmin).  One step = hg_batch_create (every field's
+setup) + one batched channel launch + destroy.  --precision picks the FP16
+MFMA form (default) or the FP32 form reading the same FP16 values.
 
-Prints one JSON line.  value = N * C / (seconds per step) in G sample*channel
-updates per second.  The line also carries the roofline of the dominant
-kernel (the channel kernel; its duration from HIP events recorded around each
-launch on the stream it runs on) and the FP64 reference gridder timed on a
-bounded sample of the same workload on the host.
+    python bench.py [--workload drift|batch] [--steps K] [--warmup W] [--gpus 1]
+                    [--precision mfma|fp32] [--no-cpu-baseline]
+
+Prints one JSON line.  value = sum(N * C) / (seconds per step) in G
+sample*channel updates per second.  The line also carries the roofline of
+the dominant kernel (the channel kernel; its duration from HIP events
+recorded around each launch on the stream it runs on) and the FP64 reference
+gridder timed on a bounded sample of the same workload on the host.
 """
 import argparse
 import json
@@ -28,6 +35,7 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_F16_MFMA_TFLOPS = 2500.0
 
 
 def log(*a):
@@ -55,20 +63,63 @@ def cpu_baseline(f, vals_host, n_pix, seed=7):
                       f"{P / n_pix:.1f} to the full map"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=3000)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path "
-              "shards by channel block or field with no exchange; see DESIGN.md)",
-              file=sys.stderr)
-        sys.exit(2)
+def host_values(v):
+    """A device tensor as the reference gridder reads it: (array, dtype code)."""
+    import numpy as np
+    import torch
+    if v.dtype == torch.float32:
+        return v.cpu().numpy(), "f32"
+    code = "bf16" if v.dtype == torch.bfloat16 else "f16"
+    return v.cpu().view(torch.int16).numpy().view(np.uint16), code
 
+
+def roofline(flops, bytes_alg, ms, peak_tflops, kernel):
+    t_mfma = flops / (peak_tflops * 1e12)
+    t_hbm = bytes_alg / (PEAK_HBM_GBS * 1e9)
+    if t_mfma >= t_hbm:
+        ach = flops / (ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": peak_tflops, "unit": "TFLOP/s",
+                "frac": ach / peak_tflops, "traffic": None}
+    else:
+        ach = bytes_alg / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None}
+    roof["kernel"] = kernel
+    roof["hbm_frac"] = bytes_alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+    roof["mfma_frac"] = flops / (ms * 1e-3) / 1e12 / peak_tflops
+    return roof
+
+
+def cpu_baseline_batch(fields, vals_dev, nnz_per_field, n_pix, seed=7):
+    """The reference gridder, single-threaded, on a random subset of pixels of
+    one mid-sized field with all its channels; its rate in (neighbour pair x
+    channel) per second, applied to the whole batch's sum of nnz * C."""
+    import numpy as np
+
+    import oracle
+    order = sorted(range(len(fields)), key=lambda i: nnz_per_field[i] * fields[i]["nchan"])
+    i = order[len(order) // 2]
+    f = fields[i]
+    m = f["map"]
+    P = m["nx"] * m["ny"]
+    pix = np.sort(np.random.default_rng(seed).choice(P, min(n_pix, P), replace=False))
+    hv, code = host_values(vals_dev[i])
+    t0 = time.perf_counter()
+    _, cnt, _, _ = oracle.grid(f["ra"], f["dec"], hv, code, m, f["kernel"]["fwhm_deg"],
+                               f["kernel"]["support_deg"], pix=pix)
+    dt = time.perf_counter() - t0
+    rate = max(int(cnt.sum()), 1) * f["nchan"] / dt
+    total = sum(nnz_per_field[j] * fields[j]["nchan"] for j in range(len(fields)))
+    full_s = total / rate
+    nc = sum(len(g["ra"]) * g["nchan"] for g in fields)
+    return {"value": nc / full_s / 1e9, "unit": "G sample*channel updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"field {i} ({len(f['ra'])} samples, {m['nx']}x{m['ny']}, {f['nchan']} ch): "
+                      f"{len(pix)} pixels x all channels in {dt:.1f} s; rate per (pair x "
+                      f"channel) scaled to the batch's sum of nnz x C"}
+
+
+def run_drift(args):
     import numpy as np
     import torch
 
@@ -116,21 +167,8 @@ def main():
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; channel kernel {ch_avg:.3f} ms; "
         f"setup {np.mean(setup_ms):.2f} ms")
 
-    flops = 2.0 * nnz * C
-    bytes_alg = 4.0 * n * C + 4.0 * P * C
-    t_mfma = flops / (PEAK_FP32_MFMA_TFLOPS * 1e12)
-    t_hbm = bytes_alg / (PEAK_HBM_GBS * 1e9)
-    if t_mfma >= t_hbm:
-        ach = flops / (ch_avg * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None}
-    else:
-        ach = bytes_alg / (ch_avg * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = "k_channels_fp32"
-    roof["hbm_frac"] = bytes_alg / (ch_avg * 1e-3) / 1e9 / PEAK_HBM_GBS
-
+    roof = roofline(2.0 * nnz * C, 4.0 * n * C + 4.0 * P * C, ch_avg, PEAK_FP32_MFMA_TFLOPS,
+                    "k_channels (FP32 form, FP32 values)")
     res = {
         "metric": "G sample*channel updates/s (plain FP32 form)",
         "value": value, "unit": "G sample*channel updates/s", "n_gpus": 1,
@@ -151,6 +189,107 @@ def main():
         vals_host = vals.cpu().numpy()
         res["cpu_baseline"] = cpu_baseline(f, vals_host, args.cpu_pixels)
         log(f"cpu baseline: {res['cpu_baseline']['sample']}")
+    return res
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_2207_04584_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    fs = synth.batch_fields(args.fields, scale=args.scale)
+    mfma = args.precision == "mfma"
+    log(f"generating {len(fs)} fields on {torch.cuda.get_device_name(0)}")
+    fields, vals_dev = [], []
+    for i, f in enumerate(fs):
+        v = synth.sky_values(f, f["nchan"], device=dev, dtype="f16")
+        vals_dev.append(v)
+        fields.append({"ra": torch.from_numpy(f["ra"]).to(dev),
+                       "dec": torch.from_numpy(f["dec"]).to(dev), "map": f["map"],
+                       "kernel": f["kernel"], "values": v})
+    torch.cuda.synchronize()
+    nc = sum(f["ra"].shape[0] * f["nchan"] for f in fs)
+    pc = sum(f["map"]["nx"] * f["map"]["ny"] * f["nchan"] for f in fs)
+    log(f"sum N*C = {nc:.3e}, values {2 * nc / 1e9:.1f} GB, out {4 * pc / 1e9:.1f} GB")
+
+    run_ms, setup_ms, info, nnz_f = [], [], {}, []
+    prec = api.HG_PREC_MFMA_F16 if mfma else api.HG_PREC_FP32
+
+    def step():
+        nonlocal info
+        b = api.Batch(fields, precision=prec, time_runs=True)
+        b.run()
+        info = b.stats()
+        if not nnz_f:  # per-field nnz, for the flop count and the reference's scaling
+            nnz_f.extend(int(b.plan(i).stats()["nnz"]) for i in range(len(fields)))
+        b.close()
+        run_ms.append(info["last_run_ms"])
+        setup_ms.append(info["setup_ms"])
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup}: batch run {run_ms[-1]:.3f} ms, "
+            f"setup {setup_ms[-1]:.1f} ms")
+    run_ms.clear()
+    setup_ms.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    run_avg = float(np.mean(run_ms))
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; batched launch {run_avg:.3f} ms; "
+        f"setup {np.mean(setup_ms):.1f} ms; items {info['n_items']}")
+    nnz = info["nnz"]
+    flops = 2.0 * sum(nnz_f[i] * fs[i]["nchan"] for i in range(len(fs)))
+    bytes_alg = 2.0 * nc + 4.0 * pc
+    kname = "k_channels_batch (FP16 MFMA form)" if mfma else "k_channels_batch (FP32 form, FP16 values)"
+    roof = roofline(flops, bytes_alg, run_avg,
+                    PEAK_F16_MFMA_TFLOPS if mfma else PEAK_FP32_MFMA_TFLOPS, kname)
+    res = {
+        "metric": "G sample*channel updates/s (" + ("FP16-MFMA batched form)" if mfma else
+                                                    "plain FP32 form, batched)"),
+        "value": nc / (ms_step * 1e-3) / 1e9, "unit": "G sample*channel updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16" if mfma else "f32", "data": "synthetic",
+        "config": {"workload": f"{len(fs)} fields, samples log-uniform 1e4..2e6, maps 32..512 "
+                               "at 1 arcmin, 256/1024/4096 FP16 channels, FWHM U(2,5) arcmin; "
+                               "step = batch setup + one batched launch",
+                   "fields": len(fs), "scale": args.scale, "sum_NC": nc, "nnz": nnz,
+                   "items": info["n_items"], "form": args.precision},
+        "channels_ms": run_avg, "setup_ms": float(np.mean(setup_ms)),
+        "channels_only_value": nc / (run_avg * 1e-3) / 1e9,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_batch(fs, vals_dev, nnz_f, args.cpu_pixels // 10)
+        log(f"cpu baseline: {res['cpu_baseline']['sample']}")
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["drift", "batch"], default="drift")
+    ap.add_argument("--precision", choices=["mfma", "fp32"], default="mfma")
+    ap.add_argument("--fields", type=int, default=64)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=3000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path "
+              "shards by channel block or field with no exchange; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    res = run_drift(args) if args.workload == "drift" else run_batch(args)
     print(json.dumps(res), flush=True)
 
 

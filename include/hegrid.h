@@ -133,7 +133,41 @@ int hg_grid_setup(const double* ra_deg, const double* dec_deg, int64_t n, const 
 int hg_grid_channels(hg_plan* p, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
                      float* out, void* hip_stream);
 
-/* Synchronise the device, free everything the plan holds.  NULL is a no-op. */
+/*
+ * Grid a cube held in HOST memory, block by block of channels, with the copy
+ * of the next block in, the kernel of the current block and the copy of the
+ * previous block out overlapped on three streams (channels are independent,
+ * Sec. 4.2; pinned buffers and transfer/compute overlap as in Sec. 4.3.2).
+ *   host_values: HOST [n][ld] of dtype, channel c of sample s at s*ld + c.
+ *   host_out:    HOST FP32 [nchan][ny][nx]; fully overwritten.
+ *   block:       channels per block (0 = 4096).  The plan keeps two device
+ *                slots of n x block values and block x ny x nx maps (counted
+ *                against device_mem_cap) between calls.
+ *   If both buffers are page-locked (hipHostMalloc, or torch pin_memory) the
+ *   copies are direct; otherwise the library stages blocks through two pinned
+ *   slots of its own with host threads.
+ *   Synchronous: returns when host_out is complete.  Kernels run on
+ *   hip_stream; the copies on two streams of the plan.
+ *   info (may be NULL) receives the block count, bytes moved and the device
+ *   time of the copies and kernels.
+ */
+typedef struct {
+    int32_t blocks;       /* channel blocks processed                              */
+    int32_t pinned;       /* 1: direct copies from the caller's page-locked buffers */
+    int64_t h2d_bytes;    /* value bytes copied to the device                      */
+    int64_t d2h_bytes;    /* map bytes copied back                                 */
+    double wall_ms;       /* host time of the call                                 */
+    double kernel_ms;     /* device time of the channel kernels (sum over blocks)  */
+    double h2d_ms;        /* device time of the copies in (sum)                    */
+    double d2h_ms;        /* device time of the copies out (sum)                   */
+} hg_stream_info;
+
+int hg_grid_channels_host(hg_plan* p, const void* host_values, int64_t ld, int32_t nchan,
+                          int32_t dtype, float* host_out, int32_t block, void* hip_stream,
+                          hg_stream_info* info);
+
+/* Synchronise the device, free everything the plan holds.  NULL is a no-op.
+   A plan borrowed from a batch is refused with HG_ERR_STATE. */
 int hg_grid_finish(hg_plan* p);
 
 /* Plan statistics (host struct).  Synchronises to read channel timings. */
@@ -163,6 +197,72 @@ int hg_plan_neighbours(const hg_plan* p, int64_t* row_ptr, int64_t* idx, float* 
  */
 int hg_ang2pix_ring(int32_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
                     int64_t* pix, void* hip_stream);
+
+/*
+ * Batched form: many independent fields (each its own Eq. 1 problem with its
+ * own samples, map, kernel and channel count) gridded by ONE kernel launch,
+ * held in a HIP graph and replayed by hg_batch_run.  This stands where the
+ * paper runs channels and fields through a CPU multi-process x GPU
+ * multi-stream pipeline with FIFO scheduling (Sec. 4.2.2): here each field is
+ * set up once on the device (as hg_grid_setup) and the launch covers every
+ * (field, 16x16-pixel tile, 256-channel block) item, placed longest first over
+ * the XCDs so that the hardware dispatcher balances the work.
+ */
+typedef struct hg_batch hg_batch; /* opaque; owns its fields' plans */
+
+typedef struct {
+    const double* ra_deg;  /* DEVICE, n FP64 (degrees); read during hg_batch_create only */
+    const double* dec_deg; /* DEVICE, n FP64 (degrees)                                   */
+    int64_t n;             /* samples, 0 <= n < 2^31                                     */
+    hg_kernel kernel;
+    hg_map map;
+    const void* values;    /* DEVICE [n][ld] of the batch dtype; read by every run       */
+    int64_t ld;            /* row stride in elements, >= nchan                           */
+    int32_t nchan;         /* channels, >= 0 (0: the field is set up but not gridded)    */
+    int32_t reserved;      /* must be 0                                                  */
+    float* out;            /* DEVICE FP32 [nchan][ny][nx]; written by every run          */
+} hg_field;
+
+typedef struct {
+    int32_t n_fields;
+    int32_t reserved;
+    int64_t n_items;      /* (field, tile, channel block) work items                   */
+    int64_t n_workgroups; /* launch size, including idle padding items                 */
+    int64_t n_samples, nnz, n_entries;
+    int64_t device_bytes; /* plans plus the batch's descriptors                        */
+    double setup_ms;      /* wall time of hg_batch_create (all field setups)           */
+    double last_run_ms;   /* device time of the last run (HG_FLAG_TIME_CHANNELS)       */
+    double total_run_ms;
+    int64_t runs;
+} hg_batch_info;
+
+/*
+ * Set up every field and build the batched launch.
+ *   fields:  HOST array of nfields >= 1 descriptors (copied); the device
+ *            buffers they point to stay owned by the caller.  values and out
+ *            are bound now: every hg_batch_run reads and writes them.
+ *   dtype:   HG_F32 / HG_BF16 / HG_F16, common to all fields; must match a
+ *            BF16 / FP16 MFMA precision (else HG_ERR_UNSUPPORTED).
+ *   o:       options for every field (precision, nside, chunk, device_mem_cap
+ *            per field, HG_FLAG_TIME_CHANNELS times each run); may be NULL.
+ *   Synchronises hip_stream.  On failure nothing is kept, *out = NULL and the
+ *   error text names the field.
+ */
+int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, const hg_opts* o,
+                    void* hip_stream, hg_batch** out);
+
+/* Grid every field (asynchronous on hip_stream; one graph launch). */
+int hg_batch_run(hg_batch* b, void* hip_stream);
+
+/* Synchronise the device and free the batch and its plans.  NULL is a no-op. */
+int hg_batch_destroy(hg_batch* b);
+
+/* Batch statistics (host struct).  Synchronises to read run timings. */
+int hg_batch_stats(hg_batch* b, hg_batch_info* s);
+
+/* Borrow field i's plan (for hg_plan_counts, hg_plan_neighbours, hg_grid_channels
+   ...); it stays owned by the batch, and hg_grid_finish on it fails. */
+int hg_batch_plan(hg_batch* b, int32_t i, hg_plan** out);
 
 /* Text of the last failure on this thread ("" if none); valid until the next
    call on the same thread. */

@@ -16,12 +16,13 @@ LIB_PATH = os.path.join(PKG, "libhegrid.so")
 HG_OK, HG_ERR_ARG, HG_ERR_STATE, HG_ERR_NOMEM, HG_ERR_DEVICE, HG_ERR_UNSUPPORTED, \
     HG_ERR_INTERNAL = range(7)
 HG_F32, HG_BF16, HG_F16 = 0, 1, 2
-HG_PREC_FP32 = 0
+HG_PREC_FP32, HG_PREC_MFMA_BF16, HG_PREC_MFMA_F16 = 0, 1, 2
 HG_FLAG_TIME_CHANNELS = 1
 
 ABI_FUNCTIONS = ("hg_grid_setup", "hg_grid_channels", "hg_grid_finish", "hg_plan_stats",
                  "hg_plan_counts", "hg_plan_weight_sums", "hg_plan_neighbours",
-                 "hg_ang2pix_ring", "hg_last_error")
+                 "hg_ang2pix_ring", "hg_grid_channels_host", "hg_batch_create", "hg_batch_run", "hg_batch_destroy",
+                 "hg_batch_stats", "hg_batch_plan", "hg_last_error")
 
 
 class HegridError(RuntimeError):
@@ -57,6 +58,29 @@ class hg_stats(ctypes.Structure):
                 ("channels_calls", ctypes.c_int64)]
 
 
+class hg_stream_info(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int32), ("pinned", ctypes.c_int32),
+                ("h2d_bytes", ctypes.c_int64), ("d2h_bytes", ctypes.c_int64),
+                ("wall_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("h2d_ms", ctypes.c_double), ("d2h_ms", ctypes.c_double)]
+
+
+class hg_field(ctypes.Structure):
+    _fields_ = [("ra_deg", ctypes.c_void_p), ("dec_deg", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("kernel", hg_kernel), ("map", hg_map), ("values", ctypes.c_void_p),
+                ("ld", ctypes.c_int64), ("nchan", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("out", ctypes.c_void_p)]
+
+
+class hg_batch_info(ctypes.Structure):
+    _fields_ = [("n_fields", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_items", ctypes.c_int64), ("n_workgroups", ctypes.c_int64),
+                ("n_samples", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("n_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("setup_ms", ctypes.c_double), ("last_run_ms", ctypes.c_double),
+                ("total_run_ms", ctypes.c_double), ("runs", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -79,6 +103,14 @@ def lib():
     L.hg_plan_weight_sums.argtypes = [P, P]
     L.hg_plan_neighbours.argtypes = [P, P, P, P, i64, ctypes.POINTER(ctypes.c_int64)]
     L.hg_ang2pix_ring.argtypes = [i32, P, P, i64, P, P]
+    L.hg_grid_channels_host.argtypes = [P, P, i64, i32, i32, P, i32, P,
+                                        ctypes.POINTER(hg_stream_info)]
+    L.hg_batch_create.argtypes = [ctypes.POINTER(hg_field), i32, i32, ctypes.POINTER(hg_opts), P,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    L.hg_batch_run.argtypes = [P, P]
+    L.hg_batch_destroy.argtypes = [P]
+    L.hg_batch_stats.argtypes = [P, ctypes.POINTER(hg_batch_info)]
+    L.hg_batch_plan.argtypes = [P, i32, ctypes.POINTER(ctypes.c_void_p)]
     for f in ABI_FUNCTIONS[:-1]:
         getattr(L, f).restype = ctypes.c_int
     L.hg_last_error.argtypes = []
@@ -171,23 +203,49 @@ class Plan:
         """values: cuda tensor [n][C] (float32 / bfloat16 / float16, unit
         channel stride); returns float32 [C][ny][nx] on the same device."""
         torch = _torch()
-        if values.dim() == 1:
-            values = values.reshape(-1, 1)
-        if values.shape[0] != self.n or values.stride(1) != 1 or values.device.type != "cuda":
-            raise HegridError(HG_ERR_ARG, "values must be a cuda tensor [n][C] with unit "
-                              "channel stride")
+        values, ld = _values_arg(values, self.n)
         nchan = values.shape[1]
         ny, nx = self.shape
         if out is None:
             out = torch.empty((nchan, ny, nx), dtype=torch.float32, device=values.device)
         if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != nchan * ny * nx:
             raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 [C][ny][nx] tensor")
-        ld = values.stride(0) if values.shape[0] > 1 else nchan
         rc = lib().hg_grid_channels(self._handle(), ctypes.c_void_p(values.data_ptr()), ld, nchan,
                                     _dtype_code(values), ctypes.c_void_p(out.data_ptr()),
                                     _stream_ptr(stream))
         _check(rc, "hg_grid_channels")
         return out
+
+    def grid_host(self, values, out=None, block=0, stream=None):
+        """values: host (CPU) tensor [n][C] of float32 / bfloat16 / float16
+        with unit channel stride, pageable or pinned; streamed to the GPU in
+        blocks of `block` channels (0 = 4096).  Returns (out, info): out a
+        float32 host tensor [C][ny][nx] (allocated pinned if not given), info
+        the call's hg_stream_info as a dict."""
+        torch = _torch()
+        if values.dim() == 1:
+            values = values.reshape(-1, 1)
+        if values.device.type != "cpu" or values.shape[0] != self.n or (
+                self.n > 0 and values.stride(1) != 1):
+            raise HegridError(HG_ERR_ARG, "values must be a host tensor [n][C] with unit "
+                              "channel stride")
+        nchan = values.shape[1]
+        ld = values.stride(0) if values.shape[0] > 1 else nchan
+        ny, nx = self.shape
+        if out is None:
+            out = torch.empty((nchan, ny, nx), dtype=torch.float32, pin_memory=True)
+        if (out.dtype != torch.float32 or out.device.type != "cpu" or not out.is_contiguous()
+                or out.numel() != nchan * ny * nx):
+            raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 host tensor "
+                              "[C][ny][nx]")
+        info = hg_stream_info()
+        rc = lib().hg_grid_channels_host(self._handle(),
+                                         ctypes.c_void_p(values.data_ptr() if self.n else 0),
+                                         ld, nchan, _dtype_code(values),
+                                         ctypes.c_void_p(out.data_ptr()), int(block),
+                                         _stream_ptr(stream), ctypes.byref(info))
+        _check(rc, "hg_grid_channels_host")
+        return out, {f: getattr(info, f) for f, _ in hg_stream_info._fields_}
 
     def stats(self):
         st = hg_stats()
@@ -224,10 +282,127 @@ class Plan:
                                     ctypes.byref(nnz)), "hg_plan_neighbours")
         return row_ptr, idx[:nnz.value], w[:nnz.value]
 
+    @classmethod
+    def _borrowed(cls, handle, map, kernel, n, owner):
+        p = cls.__new__(cls)
+        p.map, p.kernel, p.n = dict(map), dict(kernel), int(n)
+        p._h = handle
+        p._owner = owner  # keeps the batch (which frees the plan) alive
+        return p
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._h, self._owner = ctypes.c_void_p(), None
+            return
         if self._h:
             h, self._h = self._h, ctypes.c_void_p()
             _check(lib().hg_grid_finish(h), "hg_grid_finish")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _values_arg(values, n):
+    if values.dim() == 1:
+        values = values.reshape(-1, 1)
+    if values.dim() == 2 and values.shape[0] == n == 0 and values.device.type == "cuda":
+        return values, values.shape[1]  # nothing is read
+    if values.shape[0] != n or values.stride(1) != 1 or values.device.type != "cuda":
+        raise HegridError(HG_ERR_ARG, "values must be a cuda tensor [n][C] with unit channel "
+                          "stride")
+    return values, (values.stride(0) if values.shape[0] > 1 else values.shape[1])
+
+
+class Batch:
+    """Many fields gridded by one graph-held launch (hg_batch_create /
+    hg_batch_run / hg_batch_destroy).
+
+    fields: list of dicts with 'ra', 'dec' (degrees), 'map', 'kernel',
+    'values' (cuda tensor [n][C], all of one dtype, or None for C = 0) and an
+    optional 'out' (float32 cuda [C][ny][nx]; allocated if absent).  The
+    tensors are bound at creation and kept alive by the batch; run() grids all
+    of them and returns the list of outputs."""
+
+    def __init__(self, fields, precision=HG_PREC_FP32, nside=0, chunk=0, device_mem_cap=0,
+                 time_runs=False, stream=None):
+        torch = _torch()
+        L = lib()
+        self._keep = []
+        self.outs = []
+        self.fields = []
+        arr = (hg_field * len(fields))()
+        dtype = None
+        for i, f in enumerate(fields):
+            ra, dec = _dev_f64(f["ra"]), _dev_f64(f["dec"])
+            n = ra.shape[0]
+            m, k = f["map"], f["kernel"]
+            vals, out, ld, nchan = f.get("values"), f.get("out"), 0, 0
+            if vals is not None:
+                vals, ld = _values_arg(vals, n)
+                nchan = vals.shape[1]
+                code = _dtype_code(vals)
+                if dtype is None:
+                    dtype = code
+                elif code != dtype:
+                    raise HegridError(HG_ERR_ARG, "all fields of a batch share one dtype")
+                if out is None:
+                    out = torch.empty((nchan, m["ny"], m["nx"]), dtype=torch.float32,
+                                      device=vals.device)
+                if (out.dtype != torch.float32 or not out.is_contiguous()
+                        or out.numel() != nchan * m["ny"] * m["nx"]):
+                    raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 "
+                                      "[C][ny][nx] tensor")
+            self._keep += [ra, dec, vals, out]
+            self.outs.append(out)
+            self.fields.append({"map": dict(m), "kernel": dict(k), "n": n, "nchan": nchan})
+            arr[i] = hg_field(ra.data_ptr() if n else None, dec.data_ptr() if n else None, n,
+                              make_kernel(k), make_map(m),
+                              vals.data_ptr() if vals is not None and n else None, ld, nchan, 0,
+                              out.data_ptr() if out is not None else None)
+        if dtype is None:
+            dtype = {1: HG_BF16, 2: HG_F16}.get(int(precision), HG_F32)
+        self.dtype = dtype
+        self._o = hg_opts(int(precision), int(nside), int(chunk), 0, int(device_mem_cap),
+                          HG_FLAG_TIME_CHANNELS if time_runs else 0, 0)
+        self._h = ctypes.c_void_p()
+        _check(L.hg_batch_create(arr, len(fields), dtype, ctypes.byref(self._o),
+                                 _stream_ptr(stream), ctypes.byref(self._h)), "hg_batch_create")
+
+    def _handle(self):
+        if not self._h:
+            raise HegridError(HG_ERR_STATE, "batch is closed")
+        return self._h
+
+    def run(self, stream=None):
+        _check(lib().hg_batch_run(self._handle(), _stream_ptr(stream)), "hg_batch_run")
+        return self.outs
+
+    def stats(self):
+        st = hg_batch_info()
+        _check(lib().hg_batch_stats(self._handle(), ctypes.byref(st)), "hg_batch_stats")
+        return {f: getattr(st, f) for f, _ in hg_batch_info._fields_}
+
+    def plan(self, i):
+        """Field i's plan, borrowed (counts, weight sums, neighbours, grid)."""
+        h = ctypes.c_void_p()
+        _check(lib().hg_batch_plan(self._handle(), int(i), ctypes.byref(h)), "hg_batch_plan")
+        f = self.fields[i]
+        return Plan._borrowed(h, f["map"], f["kernel"], f["n"], self)
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, ctypes.c_void_p()
+            _check(lib().hg_batch_destroy(h), "hg_batch_destroy")
+            self._keep = []
 
     def __enter__(self):
         return self

@@ -26,6 +26,7 @@ SOURCES = {
     "setup.hip": ["-ffp-contract=off"],
     "channels.hip": [],
     "runtime.hip": [],
+    "stream.hip": [],
 }
 
 

@@ -36,6 +36,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
+#define CONST_AS __attribute__((address_space(4)))
 
 constexpr int CH_WAVES = 16;
 constexpr int CH_THREADS = 64 * CH_WAVES;
@@ -97,6 +98,26 @@ __device__ inline void dma4(const void* g, const char* l) {
                  : "v"(g), "s"(lds_addr(l))
                  : "memory", "m0");
 }
+// Same with a wave-uniform 64-bit base in scalar registers and a 32-bit
+// per-lane byte offset, so the lane part of the address costs one VGPR.
+__device__ inline const void* uniform_ptr(const void* p) {
+    uint64_t u = (uint64_t)(uintptr_t)p;
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (const void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline void dma16s(const void* base, uint32_t voff, const char* l) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 1\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :
+                 : "v"(voff), "s"(uniform_ptr(base)), "s"(lds_addr(l))
+                 : "memory", "m0");
+}
+__device__ inline void dma4s(const void* base, uint32_t voff, const char* l) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 1\n\tglobal_load_lds_dword %0, %1"
+                 :
+                 : "v"(voff), "s"(uniform_ptr(base)), "s"(lds_addr(l))
+                 : "memory", "m0");
+}
 
 __device__ inline float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
@@ -116,7 +137,7 @@ __device__ inline void stage_row_f32(char* dst, const void* values, int64_t ld, 
     if (DT == HG_F32) {
         const float* src = (const float*)values + (int64_t)row * ld;
         if (dma) {
-            dma16(src + c, dst);
+            dma16s(src + c_lo, 16u * lane, dst);
             return;
         }
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -150,8 +171,8 @@ __device__ inline void stage_row_f32(char* dst, const void* values, int64_t ld, 
     }
 }
 
-// 16-bit forms, two staged rows (512 B each, adjacent in LDS) per wave
-// instruction: lanes 0-31 copy row a, lanes 32-63 row b, 8 channels per lane.
+// 16-bit forms, two staged rows (512 B each, adjacent in LDS): lanes 0-31
+// copy row a, lanes 32-63 row b, 8 channels per lane.
 template <bool VEC>
 __device__ inline void stage_rows_16(char* dst, const void* values, int64_t ld, int32_t nchan,
                                      int c_lo, uint32_t row_a, uint32_t row_b, int nrows,
@@ -161,7 +182,12 @@ __device__ inline void stage_rows_16(char* dst, const void* values, int64_t ld, 
     int c = c_lo + 8 * (lane & 31);
     const uint16_t* src = (const uint16_t*)values + (int64_t)row * ld + c;
     if (dma) {
-        if (half < nrows) dma16(src, dst);
+        // one copy per row: lanes 0-31 fetch row a, lanes 32-63 row b, each
+        // lane landing at its own 16-byte slot of the adjacent LDS rows
+        const uint32_t voff = 16u * (lane & 31);
+        const uint16_t* base = (const uint16_t*)values + c_lo;
+        if (half == 0) dma16s(base + (int64_t)row_a * ld, voff, dst);
+        else if (nrows > 1) dma16s(base + (int64_t)row_b * ld, voff, dst);
         return;
     }
     if (half >= nrows) return;
@@ -223,27 +249,17 @@ __device__ inline void mfma4_16(v4f* part, uint2 a, uint2 v0, uint2 v1, uint2 v2
 }
 
 template <int FORM, int DT, bool VEC>
-__global__ __launch_bounds__(CH_THREADS) void k_channels(
-    const void* __restrict__ values, int64_t ld, int32_t nchan, int32_t ncb, int32_t npgx,
-    int32_t npgy, int32_t ntx, int64_t ntiles, int32_t nx, int32_t ny, int32_t chunk,
-    const int64_t* __restrict__ tile_base, const uint32_t* __restrict__ slot_idx,
-    const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ blk_base,
-    const uint16_t* __restrict__ blk_pgoff, const void* __restrict__ ent_w,
-    const void* __restrict__ ent_s, const float* __restrict__ pix_Wf, float* __restrict__ out,
-    int32_t out_vec) {
+__device__ __attribute__((always_inline)) inline void grid_item(
+    const void* __restrict__ values, int64_t ld, int32_t nchan, int32_t npgx, int32_t npgy,
+    int32_t ntx, int32_t nx, int32_t ny, int32_t chunk, const int64_t* __restrict__ tile_base,
+    const uint32_t* __restrict__ slot_idx, const int64_t* __restrict__ tile_blk,
+    const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
+    const void* __restrict__ ent_w, const void* __restrict__ ent_s,
+    const float* __restrict__ pix_Wf, float* __restrict__ out, int32_t out_vec, int64_t tile,
+    int64_t cb, char* smem) {
     typedef Form<FORM> F;
-    extern __shared__ __attribute__((aligned(16))) char smem[];
     const LdsLayout L = LdsLayout::make<FORM>(chunk);
     char* trash = smem + 2 * L.stride;
-
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous run of (tile, channel block) so that a tile's channel blocks
-    // (which share its entry blocks) and neighbouring tiles (which share halo
-    // samples) meet in the same L2.
-    int64_t nwg = gridDim.x, b = blockIdx.x;
-    int64_t q8 = nwg / 8, r8 = nwg % 8, xcd = b % 8, idx = b / 8;
-    int64_t logical = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
-    int64_t tile = logical / ncb, cb = logical % ncb;
     int tx = (int)(tile % ntx), ty = (int)(tile / ntx);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -276,10 +292,9 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
     // memory counter only counts the asynchronous copies, which the pipeline
     // waits for explicitly.
     struct Meta {
-        uint32_t row0, row1, first;
-        int nrows;
+        uint32_t row0, row1;
+        int nrows, ne;
         int64_t blk, eb;
-        int ne;
     };
     auto load_meta = [&](int64_t ch) {
         Meta m;
@@ -287,10 +302,11 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
         int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
         int r0 = FORM == FORM_F32 ? wave : 2 * wave;
         int r1 = FORM == FORM_F32 ? wave + CH_WAVES : 2 * wave + 1;
-        m.first = sidx[s0];
-        m.nrows = (r0 < ns) + (r1 < ns);  // chunk <= 32: at most two rows per wave
-        m.row0 = r0 < ns ? sidx[s0 + r0] : m.first;
-        m.row1 = r1 < ns ? sidx[s0 + r1] : m.first;
+        // chunk <= 32: at most two rows per wave; absent rows repeat a valid
+        // one so that the prefetch always has an address
+        m.nrows = (r0 < ns) + (r1 < ns);
+        m.row0 = sidx[s0 + (r0 < ns ? r0 : 0)];
+        m.row1 = r1 < ns ? sidx[s0 + r1] : m.row0;
         m.blk = blk0 + ch;
         m.eb = blk_base[m.blk];
         m.ne = (int)(blk_base[m.blk + 1] - m.eb);
@@ -309,8 +325,8 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
             const uint32_t* sl = (const uint32_t*)ent_s + m.eb;
             for (int i = wave * 64; i < m.ne; i += CH_THREADS) {
                 if (i + lane < m.ne) {
-                    dma16(w + i + lane, base + L.ew + i * 16);
-                    dma4(sl + i + lane, base + L.es + i * 4);
+                    dma16s(w + i, 16u * lane, base + L.ew + i * 16);
+                    dma4s(sl + i, 4u * lane, base + L.es + i * 4);
                 }
             }
         } else {
@@ -321,13 +337,13 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
             const char* w = (const char*)ent_w + m.eb * 32;
             for (int i = wave * 32; i < m.ne; i += CH_WAVES * 32)
                 if (i + (lane >> 1) < m.ne)
-                    dma16(w + (int64_t)i * 32 + lane * 16, base + L.ew + i * 32);
+                    dma16s(w + (int64_t)i * 32, 16u * lane, base + L.ew + i * 32);
             const uint4* sl = (const uint4*)ent_s + m.eb;
             for (int i = wave * 64; i < m.ne; i += CH_THREADS)
-                if (i + lane < m.ne) dma16(sl + i + lane, base + L.es + i * 16);
+                if (i + lane < m.ne) dma16s(sl + i, 16u * lane, base + L.es + i * 16);
         }
         if (wave == CH_WAVES - 1 && lane < PGOFF_STRIDE / 2)
-            dma4((const uint32_t*)(blk_pgoff + m.blk * PGOFF_STRIDE) + lane, base + L.po);
+            dma4s(blk_pgoff + m.blk * PGOFF_STRIDE, 4u * lane, base + L.po);
     };
     // L2 prefetch of a later chunk's rows: exactly one copy instruction per
     // wave (lanes touch both halves of every 128-byte line of the wave's two
@@ -477,53 +493,157 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
 }
 
 template <int FORM, int DT, bool VEC>
-hipError_t launch_typed(Plan& P, const void* values, int64_t ld, int32_t nchan, float* out,
-                        hipStream_t s) {
-    int64_t ncb = (nchan + CW - 1) / CW;
-    int64_t nwg = ncb * P.ntiles;
-    size_t shm = (size_t)2 * LdsLayout::make<FORM>(P.chunk).stride + TRASH_LDS;
-    if (shm < (size_t)OUT_LDS) shm = OUT_LDS;
+__global__ __launch_bounds__(CH_THREADS) void k_channels(
+    const void* __restrict__ values, int64_t ld, int32_t nchan, int32_t ncb, int32_t npgx,
+    int32_t npgy, int32_t ntx, int32_t nx, int32_t ny, int32_t chunk,
+    const int64_t* __restrict__ tile_base, const uint32_t* __restrict__ slot_idx,
+    const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ blk_base,
+    const uint16_t* __restrict__ blk_pgoff, const void* __restrict__ ent_w,
+    const void* __restrict__ ent_s, const float* __restrict__ pix_Wf, float* __restrict__ out,
+    int32_t out_vec) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of (tile, channel block) so that a tile's channel blocks
+    // (which share its entry blocks) and neighbouring tiles (which share halo
+    // samples) meet in the same L2.
+    int64_t nwg = gridDim.x, b = blockIdx.x;
+    int64_t q8 = nwg / 8, r8 = nwg % 8, xcd = b % 8, idx = b / 8;
+    int64_t logical = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    grid_item<FORM, DT, VEC>(values, ld, nchan, npgx, npgy, ntx, nx, ny, chunk, tile_base,
+                             slot_idx, tile_blk, blk_base, blk_pgoff, ent_w, ent_s, pix_Wf, out,
+                             out_vec, logical / ncb, logical % ncb, smem);
+}
+
+// Batched form: one launch over the (field, tile, channel block) items of many
+// fields.  Workgroup b takes item b.  The host lays the items out so that the
+// hardware's in-order, round-robin dispatch does the scheduling: position b
+// runs on XCD b mod 8, each XCD's items were assigned by longest-processing-
+// time-first over the 8 XCDs with a tile's channel blocks kept together (one
+// L2), and within an XCD they are ordered by decreasing cost, so a CU that
+// frees up always takes the largest item left.  Padding items (field < 0)
+// return at once.
+template <int FORM, int DT, bool VEC>
+__global__ __launch_bounds__(CH_THREADS) void k_channels_batch(
+    const FieldDesc* __restrict__ fields, const BatchItem* __restrict__ items) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    // descriptors and items are never written by the kernel: reading them
+    // through the constant address space keeps them in scalar registers
+    const CONST_AS BatchItem* it = (const CONST_AS BatchItem*)items + blockIdx.x;
+    const int32_t f = it->field;
+    if (f < 0) return;
+    const CONST_AS FieldDesc& d = ((const CONST_AS FieldDesc*)fields)[f];
+    grid_item<FORM, DT, VEC>(d.values, d.ld, d.nchan, d.npgx, d.npgy, d.ntx, d.nx, d.ny, d.chunk,
+                             d.tile_base, d.slot_idx, d.tile_blk, d.blk_base, d.blk_pgoff,
+                             d.ent_w, d.ent_s, d.pix_Wf, d.out, d.out_vec, it->tile, it->cb,
+                             smem);
+}
+
+size_t lds_bytes(bool m16, int chunk) {
+    size_t st = m16 ? LdsLayout::make<FORM_M16>(chunk).stride
+                    : LdsLayout::make<FORM_F32>(chunk).stride;
+    size_t shm = 2 * st + TRASH_LDS;
+    return shm < (size_t)OUT_LDS ? (size_t)OUT_LDS : shm;
+}
+
+template <int FORM, int DT, bool VEC>
+hipError_t launch_typed(const FieldDesc& d, int64_t ntiles, hipStream_t s) {
+    int64_t nwg = (int64_t)d.ncb * ntiles;
+    size_t shm = lds_bytes(FORM == FORM_M16, d.chunk);
     auto kern = k_channels<FORM, DT, VEC>;
     if (shm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
-    const void* ew = FORM == FORM_F32 ? P.e2_w.p : P.e3_w.p;
-    const void* es = FORM == FORM_F32 ? P.e2_s.p : P.e3_s.p;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(CH_THREADS), shm, s, values, ld, nchan,
-                       (int32_t)ncb, P.npgx, P.npgy, P.ntx, P.ntiles, P.map.nx, P.map.ny, P.chunk,
-                       (const int64_t*)P.tile_nslots.p, (const uint32_t*)P.slot_idx.p,
-                       (const int64_t*)P.tile_blk.p, (const int64_t*)P.blk_base.p,
-                       (const uint16_t*)P.blk_pgoff.p, ew, es, (const float*)P.pix_Wf.p, out,
-                       (int32_t)(((uintptr_t)out % 16 == 0) && (P.map.nx % 4 == 0)));
+    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(CH_THREADS), shm, s, d.values, d.ld,
+                       d.nchan, d.ncb, d.npgx, d.npgy, d.ntx, d.nx, d.ny, d.chunk, d.tile_base,
+                       d.slot_idx, d.tile_blk, d.blk_base, d.blk_pgoff, d.ent_w, d.ent_s,
+                       d.pix_Wf, d.out, d.out_vec);
     return hipGetLastError();
 }
 
+// One function pointer per (form, dtype, vec) for the two launch forms.
+template <template <int, int, bool> class K>
+const void* pick(bool m16, int32_t dtype, bool vec) {
+    if (m16) {
+        if (dtype == HG_BF16)
+            return vec ? K<FORM_M16, HG_BF16, true>::f() : K<FORM_M16, HG_BF16, false>::f();
+        return vec ? K<FORM_M16, HG_F16, true>::f() : K<FORM_M16, HG_F16, false>::f();
+    }
+    if (dtype == HG_F32)
+        return vec ? K<FORM_F32, HG_F32, true>::f() : K<FORM_F32, HG_F32, false>::f();
+    if (dtype == HG_BF16)
+        return vec ? K<FORM_F32, HG_BF16, true>::f() : K<FORM_F32, HG_BF16, false>::f();
+    return vec ? K<FORM_F32, HG_F16, true>::f() : K<FORM_F32, HG_F16, false>::f();
+}
+template <int FORM, int DT, bool VEC>
+struct BatchKernel {
+    static const void* f() { return (const void*)k_channels_batch<FORM, DT, VEC>; }
+};
+
 }  // namespace
+
+bool values_vec(const Plan& P, const void* values, int64_t ld, int32_t dtype) {
+    uintptr_t a = (uintptr_t)values;
+    if (P.opts.precision != HG_PREC_FP32) return a % 16 == 0 && ld % 8 == 0;
+    if (dtype == HG_F32) return a % 16 == 0 && ld % 4 == 0;
+    return a % 8 == 0 && ld % 4 == 0;
+}
+
+FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out) {
+    FieldDesc d{};
+    bool m16 = P.opts.precision != HG_PREC_FP32;
+    d.values = values;
+    d.ld = ld;
+    d.nchan = nchan;
+    d.ncb = (nchan + CW - 1) / CW;
+    d.npgx = P.npgx;
+    d.npgy = P.npgy;
+    d.ntx = P.ntx;
+    d.nx = P.map.nx;
+    d.ny = P.map.ny;
+    d.chunk = P.chunk;
+    d.out_vec = ((uintptr_t)out % 16 == 0) && (P.map.nx % 4 == 0);
+    d.tile_base = (const int64_t*)P.tile_nslots.p;
+    d.slot_idx = (const uint32_t*)P.slot_idx.p;
+    d.tile_blk = (const int64_t*)P.tile_blk.p;
+    d.blk_base = (const int64_t*)P.blk_base.p;
+    d.blk_pgoff = (const uint16_t*)P.blk_pgoff.p;
+    d.ent_w = m16 ? P.e3_w.p : P.e2_w.p;
+    d.ent_s = m16 ? P.e3_s.p : P.e2_s.p;
+    d.pix_Wf = (const float*)P.pix_Wf.p;
+    d.out = out;
+    return d;
+}
 
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
                            float* out, hipStream_t s) {
-    uintptr_t a = (uintptr_t)values;
-    if (P.opts.precision == HG_PREC_MFMA_BF16 || P.opts.precision == HG_PREC_MFMA_F16) {
-        bool vec = (a % 16 == 0) && (ld % 8 == 0);  // 16-byte rows of 8 values
+    bool vec = values_vec(P, values, ld, dtype);
+    FieldDesc d = field_desc(P, values, ld, nchan, out);
+    if (P.opts.precision != HG_PREC_FP32) {
         if (dtype == HG_BF16)
-            return vec ? launch_typed<FORM_M16, HG_BF16, true>(P, values, ld, nchan, out, s)
-                       : launch_typed<FORM_M16, HG_BF16, false>(P, values, ld, nchan, out, s);
-        return vec ? launch_typed<FORM_M16, HG_F16, true>(P, values, ld, nchan, out, s)
-                   : launch_typed<FORM_M16, HG_F16, false>(P, values, ld, nchan, out, s);
+            return vec ? launch_typed<FORM_M16, HG_BF16, true>(d, P.ntiles, s)
+                       : launch_typed<FORM_M16, HG_BF16, false>(d, P.ntiles, s);
+        return vec ? launch_typed<FORM_M16, HG_F16, true>(d, P.ntiles, s)
+                   : launch_typed<FORM_M16, HG_F16, false>(d, P.ntiles, s);
     }
-    if (dtype == HG_F32) {
-        bool vec = (a % 16 == 0) && (ld % 4 == 0);
-        return vec ? launch_typed<FORM_F32, HG_F32, true>(P, values, ld, nchan, out, s)
-                   : launch_typed<FORM_F32, HG_F32, false>(P, values, ld, nchan, out, s);
-    }
-    bool vec = (a % 8 == 0) && (ld % 4 == 0);
+    if (dtype == HG_F32)
+        return vec ? launch_typed<FORM_F32, HG_F32, true>(d, P.ntiles, s)
+                   : launch_typed<FORM_F32, HG_F32, false>(d, P.ntiles, s);
     if (dtype == HG_BF16)
-        return vec ? launch_typed<FORM_F32, HG_BF16, true>(P, values, ld, nchan, out, s)
-                   : launch_typed<FORM_F32, HG_BF16, false>(P, values, ld, nchan, out, s);
-    return vec ? launch_typed<FORM_F32, HG_F16, true>(P, values, ld, nchan, out, s)
-               : launch_typed<FORM_F32, HG_F16, false>(P, values, ld, nchan, out, s);
+        return vec ? launch_typed<FORM_F32, HG_BF16, true>(d, P.ntiles, s)
+                   : launch_typed<FORM_F32, HG_BF16, false>(d, P.ntiles, s);
+    return vec ? launch_typed<FORM_F32, HG_F16, true>(d, P.ntiles, s)
+               : launch_typed<FORM_F32, HG_F16, false>(d, P.ntiles, s);
+}
+
+BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, int32_t chunk) {
+    BatchKernelInfo k;
+    k.main = pick<BatchKernel>(m16, dtype, vec);
+    k.shm = lds_bytes(m16, chunk);
+    k.threads = CH_THREADS;
+    k.channels_per_block = CW;
+    return k;
 }
 
 }  // namespace hg

@@ -143,6 +143,21 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Rings for host-streamed channel blocks (hg_grid_channels_host): two device
+// slots of values and maps, two pinned host slots for callers whose buffers
+// are pageable, and the two copy streams.  Kept by the plan across calls.
+constexpr int RING_SLOTS = 2;
+struct HostRing {
+    DevBuf vals[RING_SLOTS], out[RING_SLOTS];
+    void* pin_in[RING_SLOTS] = {nullptr, nullptr};
+    void* pin_out[RING_SLOTS] = {nullptr, nullptr};
+    size_t pin_in_bytes = 0, pin_out_bytes = 0;
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    hipEvent_t ev_h2d[RING_SLOTS] = {nullptr, nullptr};
+    hipEvent_t ev_ker[RING_SLOTS] = {nullptr, nullptr};
+    hipEvent_t ev_d2h[RING_SLOTS] = {nullptr, nullptr};
+};
+
 struct Plan {
     int device = 0;
     // geometry and kernel constants (row a1)
@@ -195,6 +210,38 @@ struct Plan {
     int64_t ch_calls = 0, ch_timed_calls = 0;
     double ch_ms_total = 0, ch_ms_last = 0;
     bool finished = false;
+    HostRing ring;
+};
+
+// Everything the channel kernel needs to grid one field: the plan's device
+// arrays plus the call's values and output (device pointers).
+struct FieldDesc {
+    const void* values;
+    int64_t ld;
+    const int64_t* tile_base;
+    const uint32_t* slot_idx;
+    const int64_t* tile_blk;
+    const int64_t* blk_base;
+    const uint16_t* blk_pgoff;
+    const void* ent_w;
+    const void* ent_s;
+    const float* pix_Wf;
+    float* out;
+    int32_t nchan, ncb, npgx, npgy, ntx, nx, ny, chunk, out_vec, pad;
+};
+
+// One work item of the batched launch: (field, tile, channel block); field < 0
+// marks a padding item that does nothing.
+struct BatchItem {
+    int32_t field, cb;
+    int64_t tile;
+};
+
+struct BatchKernelInfo {
+    const void* main;  // k_channels_batch(fields, items): one workgroup per item
+    size_t shm;        // dynamic LDS bytes
+    int threads;        // threads per workgroup of the main kernel
+    int channels_per_block;
 };
 
 // kernel launchers (setup.hip, channels.hip)
@@ -202,10 +249,19 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                         std::string& err, int& status);
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
                            float* out, hipStream_t s);
+FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out);
+bool values_vec(const Plan& P, const void* values, int64_t ld, int32_t dtype);
+BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, int32_t chunk);
 hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
                           int64_t* pix, hipStream_t s);
 
 void plan_band(Plan& P, double eps);
+
+// host-streamed channel blocks (stream.hip)
+int grid_channels_host(Plan& P, const void* host_values, int64_t ld, int32_t nchan, int32_t dtype,
+                       float* host_out, int32_t block, hipStream_t s, hg_stream_info* info,
+                       std::string& err);
+void ring_free(HostRing& R);
 
 // device memory (runtime.hip)
 hipError_t dev_alloc(DevBuf& b, size_t bytes);

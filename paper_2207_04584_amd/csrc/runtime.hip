@@ -1,6 +1,7 @@
 // Host runtime of libhegrid: the C ABI declared in include/hegrid.h, argument
 // validation, plan construction (geometry and kernel constants), a caching
 // device allocator, channel-kernel timing and the parity exports.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <exception>
@@ -12,6 +13,21 @@
 
 struct hg_plan {
     hg::Plan P;
+    bool owned_by_batch = false;  // plans of a batch are freed by hg_batch_destroy
+};
+
+struct hg_batch {
+    std::vector<hg_plan*> plans;
+    int device = 0;
+    int32_t dtype = 0;
+    hg_opts opts{};
+    hg::DevBuf descs, items;
+    int64_t n_items = 0, n_positions = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
+    int64_t runs = 0, timed_runs = 0;
+    double run_ms_last = 0, run_ms_total = 0, setup_ms = 0;
 };
 
 namespace hg {
@@ -136,6 +152,7 @@ void plan_free(Plan& P) {
                       &P.cp_base, &P.chunk_ptr, &P.pix_count, &P.pix_W, &P.pix_Wf, &P.scratch,
                       &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s, &P.e3_w, &P.e3_s})
         dev_free(*b);
+    ring_free(P.ring);
     for (auto& e : P.ev_pending) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -156,6 +173,7 @@ int64_t plan_bytes(const Plan& P) {
                             &P.scratch, &P.tile_blk, &P.blk_base, &P.blk_pgoff, &P.e2_w, &P.e2_s,
                             &P.e3_w, &P.e3_s})
         s += (int64_t)b->bytes;
+    for (int k = 0; k < RING_SLOTS; k++) s += (int64_t)(P.ring.vals[k].bytes + P.ring.out[k].bytes);
     return s;
 }
 
@@ -208,6 +226,134 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
     return HG_OK;
 }
 
+// Setup proper, after validation (shared by hg_grid_setup and hg_batch_create).
+int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_kernel* k,
+              const hg_map* m, const hg_opts* o, hipStream_t s, hg_plan** out) {
+    auto t0 = std::chrono::steady_clock::now();
+    hg_plan* h = new hg_plan();
+    Plan& P = h->P;
+    P.device = cur_device();
+    P.map = *m;
+    P.kern = *k;
+    if (o) P.opts = *o;
+    P.n = n;
+    P.sigma = k->fwhm_deg * kDeg / sqrt(8.0 * log(2.0));
+    P.r_rad = k->support_deg * kDeg;
+    double sh = sin(0.5 * P.r_rad);
+    P.h_r = sh * sh;
+    P.chunk = (o && o->chunk) ? o->chunk : MAX_CHUNK;
+    P.npix = (int64_t)m->nx * m->ny;
+    P.npgx = (m->nx + PG - 1) / PG;
+    P.npgy = (m->ny + PG - 1) / PG;
+    P.npg = (int64_t)P.npgx * P.npgy;
+    P.ntx = (P.npgx + TILE_PGX - 1) / TILE_PGX;
+    P.nty = (P.npgy + TILE_PGY - 1) / TILE_PGY;
+    P.ntiles = (int64_t)P.ntx * P.nty;
+    P.nside = choose_nside(P);
+    plan_band(P, 1e-9);
+    if (P.n_cells > ((int64_t)1 << 28)) {
+        delete h;
+        return fail(HG_ERR_UNSUPPORTED, "nside too fine for this field (over 2^28 cells)");
+    }
+    std::string err;
+    int status = HG_OK;
+    hipError_t e = launch_setup(P, ra_deg, dec_deg, s, err, status);
+    if (e != hipSuccess) {
+        plan_free(P);
+        delete h;
+        return fail_hip(e, "grid_setup");
+    }
+    if (status != HG_OK) {
+        plan_free(P);
+        delete h;
+        return fail(status, err);
+    }
+    P.setup_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return HG_OK;
+}
+
+void batch_free(hg_batch* b) {
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto& e : b->ev_pending) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    for (auto& e : b->ev_free) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    dev_free(b->descs);
+    dev_free(b->items);
+    for (hg_plan* h : b->plans) {
+        plan_free(h->P);
+        delete h;
+    }
+    delete b;
+}
+
+hipError_t resolve_batch_timing(hg_batch* b) {
+    for (auto& e : b->ev_pending) {
+        hipError_t r = hipEventSynchronize(e.second);
+        if (r != hipSuccess) return r;
+        float ms = 0.f;
+        r = hipEventElapsedTime(&ms, e.first, e.second);
+        if (r != hipSuccess) return r;
+        b->run_ms_total += ms;
+        b->run_ms_last = ms;
+        b->timed_runs++;
+        b->ev_free.push_back(e);
+    }
+    b->ev_pending.clear();
+    return hipSuccess;
+}
+
+// Work layout of the batched launch.  The unit of placement is a tile with all
+// of its channel blocks (they read the same entry blocks and sample rows, so
+// they should share one XCD's L2); its cost is (channel blocks) x (staged
+// chunks + 2), the 2 standing for the fixed per-item work of the epilogue.
+// Units go, largest first, to the XCD with the least work so far (longest
+// processing time first); each XCD's items keep that order, and position
+// 8 i + x of the launch holds the i-th item of XCD x (the dispatcher sends
+// workgroup b to XCD b mod 8 and starts an XCD's workgroups in order).
+std::vector<BatchItem> plan_batch_items(const std::vector<std::vector<int64_t>>& tile_blk,
+                                        const std::vector<int32_t>& ncb, int64_t& n_items) {
+    constexpr int NX = 8;
+    struct Unit {
+        int64_t cost, tile;
+        int32_t field;
+    };
+    std::vector<Unit> units;
+    for (size_t f = 0; f < tile_blk.size(); f++) {
+        if (ncb[f] == 0) continue;
+        for (size_t t = 0; t + 1 < tile_blk[f].size(); t++) {
+            int64_t nch = tile_blk[f][t + 1] - tile_blk[f][t];
+            units.push_back({ncb[f] * (nch + 2), (int64_t)t, (int32_t)f});
+        }
+    }
+    std::stable_sort(units.begin(), units.end(),
+                     [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+    std::vector<std::vector<BatchItem>> lists(NX);
+    std::vector<int64_t> load(NX, 0);
+    n_items = 0;
+    for (const Unit& u : units) {
+        int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += u.cost;
+        for (int32_t cb = 0; cb < ncb[u.field]; cb++) lists[x].push_back({u.field, cb, u.tile});
+        n_items += ncb[u.field];
+    }
+    size_t depth = 0;
+    for (auto& l : lists) depth = std::max(depth, l.size());
+    std::vector<BatchItem> pos(depth * NX, BatchItem{-1, 0, 0});
+    for (int x = 0; x < NX; x++)
+        for (size_t i = 0; i < lists[x].size(); i++) pos[i * NX + x] = lists[x][i];
+    return pos;
+}
+
 template <typename F>
 int guarded(F&& f) {
     try {
@@ -240,50 +386,7 @@ int hg_grid_setup(const double* ra_deg, const double* dec_deg, int64_t n, const 
         if (rc) return rc;
         rc = ensure_device();
         if (rc) return rc;
-        auto t0 = std::chrono::steady_clock::now();
-        hg_plan* h = new hg_plan();
-        Plan& P = h->P;
-        P.device = cur_device();
-        P.map = *m;
-        P.kern = *k;
-        if (o) P.opts = *o;
-        P.n = n;
-        P.sigma = k->fwhm_deg * kDeg / sqrt(8.0 * log(2.0));
-        P.r_rad = k->support_deg * kDeg;
-        double sh = sin(0.5 * P.r_rad);
-        P.h_r = sh * sh;
-        P.chunk = (o && o->chunk) ? o->chunk : MAX_CHUNK;
-        P.npix = (int64_t)m->nx * m->ny;
-        P.npgx = (m->nx + PG - 1) / PG;
-        P.npgy = (m->ny + PG - 1) / PG;
-        P.npg = (int64_t)P.npgx * P.npgy;
-        P.ntx = (P.npgx + TILE_PGX - 1) / TILE_PGX;
-        P.nty = (P.npgy + TILE_PGY - 1) / TILE_PGY;
-        P.ntiles = (int64_t)P.ntx * P.nty;
-        P.nside = choose_nside(P);
-        plan_band(P, 1e-9);
-        if (P.n_cells > ((int64_t)1 << 28)) {
-            delete h;
-            return fail(HG_ERR_UNSUPPORTED, "nside too fine for this field (over 2^28 cells)");
-        }
-        hipStream_t s = (hipStream_t)hip_stream;
-        std::string err;
-        int status = HG_OK;
-        hipError_t e = launch_setup(P, ra_deg, dec_deg, s, err, status);
-        if (e != hipSuccess) {
-            plan_free(P);
-            delete h;
-            return fail_hip(e, "grid_setup");
-        }
-        if (status != HG_OK) {
-            plan_free(P);
-            delete h;
-            return fail(status, err);
-        }
-        P.setup_ms =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        *out = h;
-        return HG_OK;
+        return make_plan(ra_deg, dec_deg, n, k, m, o, (hipStream_t)hip_stream, out);
     });
 }
 
@@ -333,10 +436,43 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
     });
 }
 
+int hg_grid_channels_host(hg_plan* h, const void* host_values, int64_t ld, int32_t nchan,
+                          int32_t dtype, float* host_out, int32_t block, void* hip_stream,
+                          hg_stream_info* info) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!h) return fail(HG_ERR_ARG, "plan must not be NULL");
+        Plan& P = h->P;
+        if (P.finished) return fail(HG_ERR_STATE, "plan already finished");
+        if (nchan < 0) return fail(HG_ERR_ARG, "nchan must be >= 0");
+        if (dtype != HG_F32 && dtype != HG_BF16 && dtype != HG_F16)
+            return fail(HG_ERR_ARG, "unknown dtype");
+        if (block < 0) return fail(HG_ERR_ARG, "block must be >= 0");
+        if (info) std::memset(info, 0, sizeof *info);
+        if (nchan == 0) return HG_OK;
+        if (!host_out || (!host_values && P.n > 0))
+            return fail(HG_ERR_ARG, "values and out must not be NULL");
+        if (ld < nchan) return fail(HG_ERR_ARG, "ld must be >= nchan");
+        if (P.opts.precision == HG_PREC_MFMA_BF16 && dtype != HG_BF16)
+            return fail(HG_ERR_UNSUPPORTED, "a BF16-MFMA plan grids BF16 values");
+        if (P.opts.precision == HG_PREC_MFMA_F16 && dtype != HG_F16)
+            return fail(HG_ERR_UNSUPPORTED, "an FP16-MFMA plan grids FP16 values");
+        hipError_t e = hipSetDevice(P.device);
+        if (e != hipSuccess) return fail_hip(e, "grid_channels_host");
+        std::string err;
+        int rc = grid_channels_host(P, host_values, ld, nchan, dtype, host_out,
+                                    block ? block : 4096, (hipStream_t)hip_stream, info, err);
+        if (rc) return fail(rc, err);
+        return HG_OK;
+    });
+}
+
 int hg_grid_finish(hg_plan* h) {
     return guarded([&]() -> int {
         g_err.clear();
         if (!h) return HG_OK;
+        if (h->owned_by_batch)
+            return fail(HG_ERR_STATE, "plan belongs to a batch; hg_batch_destroy frees it");
         Plan& P = h->P;
         (void)hipSetDevice(P.device);
         hipError_t e = hipDeviceSynchronize();
@@ -454,6 +590,194 @@ int hg_plan_neighbours(const hg_plan* h, int64_t* row_ptr, int64_t* idx, float* 
             if (idx) idx[t] = tmp[t].first;
             if (w) w[t] = tmp[t].second;
         }
+        return HG_OK;
+    });
+}
+
+int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, const hg_opts* o,
+                    void* hip_stream, hg_batch** out) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!out) return fail(HG_ERR_ARG, "out must not be NULL");
+        *out = nullptr;
+        if (!fields || nfields <= 0) return fail(HG_ERR_ARG, "need at least one field");
+        if (dtype != HG_F32 && dtype != HG_BF16 && dtype != HG_F16)
+            return fail(HG_ERR_ARG, "unknown dtype");
+        int32_t prec = o ? o->precision : HG_PREC_FP32;
+        if (prec == HG_PREC_MFMA_BF16 && dtype != HG_BF16)
+            return fail(HG_ERR_UNSUPPORTED, "a BF16-MFMA batch grids BF16 values");
+        if (prec == HG_PREC_MFMA_F16 && dtype != HG_F16)
+            return fail(HG_ERR_UNSUPPORTED, "an FP16-MFMA batch grids FP16 values");
+        for (int32_t i = 0; i < nfields; i++) {
+            const hg_field& f = fields[i];
+            int rc = validate_setup(f.ra_deg, f.dec_deg, f.n, &f.kernel, &f.map, o);
+            if (!rc && (f.nchan < 0 || f.reserved)) rc = fail(HG_ERR_ARG, "nchan must be >= 0 and reserved 0");
+            if (!rc && f.nchan > 0 && (!f.out || (!f.values && f.n > 0)))
+                rc = fail(HG_ERR_ARG, "values and out must not be NULL");
+            if (!rc && f.nchan > 0 && f.ld < f.nchan) rc = fail(HG_ERR_ARG, "ld must be >= nchan");
+            if (rc) return fail(rc, "field " + std::to_string(i) + ": " + g_err);
+        }
+        int rc = ensure_device();
+        if (rc) return rc;
+        auto t0 = std::chrono::steady_clock::now();
+        hg_batch* b = new hg_batch();
+        b->device = cur_device();
+        b->dtype = dtype;
+        if (o) b->opts = *o;
+        hg_opts po = b->opts;
+        po.flags &= ~HG_FLAG_TIME_CHANNELS;
+        hipStream_t s = (hipStream_t)hip_stream;
+        std::vector<FieldDesc> descs;
+        std::vector<std::vector<int64_t>> tile_blk;
+        std::vector<int32_t> ncb;
+        bool vec = true;
+        for (int32_t i = 0; i < nfields; i++) {
+            const hg_field& f = fields[i];
+            hg_plan* h = nullptr;
+            rc = make_plan(f.ra_deg, f.dec_deg, f.n, &f.kernel, &f.map, &po, s, &h);
+            if (rc) {
+                std::string msg = "field " + std::to_string(i) + ": " + g_err;
+                batch_free(b);
+                return fail(rc, msg);
+            }
+            h->owned_by_batch = true;
+            b->plans.push_back(h);
+            const Plan& P = h->P;
+            descs.push_back(field_desc(P, f.values, f.ld, f.nchan, f.out));
+            ncb.push_back(descs.back().ncb);
+            if (f.nchan > 0 && f.n > 0) vec = vec && values_vec(P, f.values, f.ld, dtype);
+            std::vector<int64_t> tb((size_t)P.ntiles + 1);
+            hipError_t e = hipMemcpy(tb.data(), P.tile_blk.p, 8 * tb.size(), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                batch_free(b);
+                return fail_hip(e, "batch_create");
+            }
+            tile_blk.push_back(std::move(tb));
+        }
+        std::vector<BatchItem> pos = plan_batch_items(tile_blk, ncb, b->n_items);
+        b->n_positions = (int64_t)pos.size();
+        if (b->n_items > 0) {
+            if (b->n_positions >= ((int64_t)1 << 31)) {
+                batch_free(b);
+                return fail(HG_ERR_UNSUPPORTED, "batch has too many work items");
+            }
+            hipError_t e = dev_alloc(b->descs, sizeof(FieldDesc) * descs.size());
+            if (e == hipSuccess) e = dev_alloc(b->items, sizeof(BatchItem) * pos.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(b->descs.p, descs.data(), sizeof(FieldDesc) * descs.size(),
+                              hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(b->items.p, pos.data(), sizeof(BatchItem) * pos.size(),
+                              hipMemcpyHostToDevice);
+            BatchKernelInfo ki =
+                batch_kernel(b->opts.precision != HG_PREC_FP32, dtype, vec, b->plans[0]->P.chunk);
+            if (e == hipSuccess && ki.shm > 65536)
+                e = hipFuncSetAttribute(ki.main, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)ki.shm);
+            // the whole batch is one kernel node of a graph, replayed by hg_batch_run
+            if (e == hipSuccess) e = hipGraphCreate(&b->graph, 0);
+            if (e == hipSuccess) {
+                void* d_descs = b->descs.p;
+                void* d_items = b->items.p;
+                void* args[] = {&d_descs, &d_items};
+                hipKernelNodeParams kp{};
+                kp.func = const_cast<void*>(ki.main);
+                kp.gridDim = dim3((unsigned)b->n_positions);
+                kp.blockDim = dim3((unsigned)ki.threads);
+                kp.sharedMemBytes = (unsigned)ki.shm;
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                hipGraphNode_t node;
+                e = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                batch_free(b);
+                return fail_hip(e, "batch_create");
+            }
+        }
+        b->setup_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = b;
+        return HG_OK;
+    });
+}
+
+int hg_batch_run(hg_batch* b, void* hip_stream) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!b) return fail(HG_ERR_ARG, "batch must not be NULL");
+        if (!b->exec) return HG_OK;  // no channels to grid
+        hipError_t e = hipSetDevice(b->device);
+        if (e != hipSuccess) return fail_hip(e, "batch_run");
+        hipStream_t s = (hipStream_t)hip_stream;
+        bool timed = (b->opts.flags & HG_FLAG_TIME_CHANNELS) != 0;
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (timed) {
+            if (!b->ev_free.empty()) {
+                ev = b->ev_free.back();
+                b->ev_free.pop_back();
+            } else {
+                e = hipEventCreate(&ev.first);
+                if (e == hipSuccess) e = hipEventCreate(&ev.second);
+                if (e != hipSuccess) return fail_hip(e, "batch_run (events)");
+            }
+            e = hipEventRecord(ev.first, s);
+            if (e != hipSuccess) return fail_hip(e, "batch_run (events)");
+        }
+        e = hipGraphLaunch(b->exec, s);
+        if (e != hipSuccess) return fail_hip(e, "batch_run");
+        if (timed) {
+            e = hipEventRecord(ev.second, s);
+            if (e != hipSuccess) return fail_hip(e, "batch_run (events)");
+            b->ev_pending.push_back(ev);
+        }
+        b->runs++;
+        return HG_OK;
+    });
+}
+
+int hg_batch_destroy(hg_batch* b) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!b) return HG_OK;
+        batch_free(b);
+        return HG_OK;
+    });
+}
+
+int hg_batch_stats(hg_batch* b, hg_batch_info* st) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!b || !st) return fail(HG_ERR_ARG, "NULL argument");
+        hipError_t e = resolve_batch_timing(b);
+        if (e != hipSuccess) return fail_hip(e, "batch_stats");
+        std::memset(st, 0, sizeof *st);
+        st->n_fields = (int32_t)b->plans.size();
+        st->n_items = b->n_items;
+        st->n_workgroups = b->n_positions;
+        for (hg_plan* h : b->plans) {
+            st->n_samples += h->P.n;
+            st->nnz += h->P.nnz;
+            st->n_entries += h->P.nnz_entries;
+            st->device_bytes += plan_bytes(h->P);
+        }
+        st->device_bytes += (int64_t)(b->descs.bytes + b->items.bytes);
+        st->setup_ms = b->setup_ms;
+        st->last_run_ms = b->run_ms_last;
+        st->total_run_ms = b->run_ms_total;
+        st->runs = b->runs;
+        return HG_OK;
+    });
+}
+
+int hg_batch_plan(hg_batch* b, int32_t i, hg_plan** out) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!b || !out) return fail(HG_ERR_ARG, "NULL argument");
+        *out = nullptr;
+        if (i < 0 || i >= (int32_t)b->plans.size()) return fail(HG_ERR_ARG, "field index out of range");
+        *out = b->plans[i];
         return HG_OK;
     });
 }

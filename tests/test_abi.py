@@ -41,6 +41,8 @@ PROBE = r"""
 int main(void) {
   printf("hg_map size %zu\nhg_kernel size %zu\nhg_opts size %zu\nhg_stats size %zu\n",
          sizeof(hg_map), sizeof(hg_kernel), sizeof(hg_opts), sizeof(hg_stats));
+  printf("hg_field size %zu\nhg_batch_info size %zu\nhg_stream_info size %zu\n",
+         sizeof(hg_field), sizeof(hg_batch_info), sizeof(hg_stream_info));
   %FIELDS%
   return 0;
 }
@@ -50,7 +52,8 @@ int main(void) {
 def test_struct_layouts_match_header(tmp_path):
     lines = []
     structs = {"hg_map": api.hg_map, "hg_kernel": api.hg_kernel, "hg_opts": api.hg_opts,
-               "hg_stats": api.hg_stats}
+               "hg_stats": api.hg_stats, "hg_field": api.hg_field,
+               "hg_batch_info": api.hg_batch_info, "hg_stream_info": api.hg_stream_info}
     for cname, cls in structs.items():
         for f, _ in cls._fields_:
             lines.append(f"F({cname}, {f})")
@@ -137,6 +140,7 @@ def test_channels_and_finish_state_rules():
     assert L.hg_plan_stats(None, ctypes.byref(st)) == api.HG_ERR_ARG
     assert L.hg_plan_counts(None, None) == api.HG_ERR_ARG
     assert L.hg_ang2pix_ring(0, None, None, 1, None, None) == api.HG_ERR_ARG
+    assert L.hg_grid_channels_host(None, None, 1, 1, 0, None, 0, None, None) == api.HG_ERR_ARG
     assert L.hg_ang2pix_ring(8, None, None, 0, None, None) == api.HG_OK  # nothing to do
 
 
@@ -154,3 +158,84 @@ def test_valid_setup_without_device_reports_device_error():
     rc, h = _setup(k=k, m=m, o=api.hg_opts())
     assert rc == api.HG_ERR_DEVICE
     assert "device" in api.last_error()
+
+
+def _field(n=0, nchan=0):
+    k, m = good()
+    return api.hg_field(None, None, n, k, m, None, nchan, nchan, 0, None)
+
+
+def _batch(fields, nfields=None, dtype=api.HG_F32, o=None, out=True):
+    L = api.lib()
+    h = ctypes.c_void_p(123)
+    arr = None
+    if fields is not None:
+        arr = (api.hg_field * max(len(fields), 1))(*fields)
+    rc = L.hg_batch_create(arr, len(fields) if nfields is None else nfields, dtype,
+                           ctypes.byref(o) if o else None, None,
+                           ctypes.byref(h) if out else None)
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["null_out", "null_fields", "zero_fields", "dtype", "map",
+                                  "nchan", "reserved", "null_out_buf", "ld", "null_values",
+                                  "chunk"])
+def test_batch_create_rejects_bad_arguments_without_a_device(case):
+    fields, kw = [_field()], {}
+    f = fields[0]
+    if case == "null_out":
+        kw["out"] = False
+    elif case == "null_fields":
+        fields, kw["nfields"] = None, 1
+    elif case == "zero_fields":
+        kw["nfields"] = 0
+    elif case == "dtype":
+        kw["dtype"] = 7
+    elif case == "map":
+        f.map.nx = 0
+    elif case == "nchan":
+        f.nchan = -1
+    elif case == "reserved":
+        f.reserved = 2
+    elif case == "null_out_buf":
+        f.nchan, f.ld, f.values = 4, 4, 1
+    elif case == "ld":
+        f.nchan, f.ld, f.values, f.out = 4, 3, 1, 1
+    elif case == "null_values":
+        f.n, f.ra_deg, f.dec_deg, f.nchan, f.ld, f.out = 5, 1, 1, 4, 4, 1
+    elif case == "chunk":
+        kw["o"] = api.hg_opts(chunk=12)
+    if fields is None:
+        L = api.lib()
+        h = ctypes.c_void_p(123)
+        rc = L.hg_batch_create(None, 1, 0, None, None, ctypes.byref(h))
+    else:
+        rc, h = _batch(fields, **kw)
+    assert rc == api.HG_ERR_ARG, api.last_error()
+    if case in ("map", "nchan", "reserved", "null_out_buf", "ld", "null_values", "chunk"):
+        assert api.last_error().startswith("field 0: "), api.last_error()
+    if case != "null_out":
+        assert not h.value
+
+
+def test_batch_precision_must_match_dtype():
+    for prec, dtype in ((1, api.HG_F32), (1, api.HG_F16), (2, api.HG_BF16)):
+        rc, h = _batch([_field()], dtype=dtype, o=api.hg_opts(precision=prec))
+        assert rc == api.HG_ERR_UNSUPPORTED, (prec, dtype)
+
+
+def test_batch_null_handles():
+    L = api.lib()
+    assert L.hg_batch_destroy(None) == api.HG_OK
+    assert L.hg_batch_run(None, None) == api.HG_ERR_ARG
+    info = api.hg_batch_info()
+    assert L.hg_batch_stats(None, ctypes.byref(info)) == api.HG_ERR_ARG
+    h = ctypes.c_void_p()
+    assert L.hg_batch_plan(None, 0, ctypes.byref(h)) == api.HG_ERR_ARG
+
+
+@pytest.mark.skipif(_gpu_present(), reason="checks the no-device path")
+def test_valid_batch_without_device_reports_device_error():
+    rc, h = _batch([_field(), _field()])
+    assert rc == api.HG_ERR_DEVICE
+    assert not h.value

@@ -1,0 +1,174 @@
+"""GPU tests of the batched form (hg_batch_*): many fields in one graph-held
+launch.
+
+  * The batched launch runs the same per-item arithmetic as hg_grid_channels,
+    so its maps must equal the single-field maps bit for bit (NaN included).
+  * Against the FP64 reference, on the batching workload's geometry scaled
+    down (log-uniform sample counts, square maps 32..512, FWHM U(2, 5)
+    arcmin, FP16 values): counts bit-exact on every pixel, maps within 1e-6
+    (FP32 form) or 2e-3 (FP16 MFMA form) on sampled channels.
+  * Graph replays, with eager work on the same buffers in between, reproduce
+    the first run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_04584_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2207_04584_amd import api  # noqa: E402
+from parity_util import norm_err, to_host_values  # noqa: E402
+
+ARC = 1.0 / 60.0
+DEV = "cuda:0"
+
+
+def mixed_fields(dtype=torch.float32):
+    """Fields of uneven shapes: ragged maps, a channel count that spills one
+    sample past a 256-channel block, no samples, no channels, samples mostly
+    outside the map, a map across RA = 0."""
+    specs = [  # (seed, n, nx, ny, ra0, dec0, fwhm, C, spread)
+        (1, 3000, 40, 37, 150.0, 20.0, 3.0, 300, 1.3),
+        (2, 0, 16, 16, 10.0, -5.0, 3.0, 5, 1.0),
+        (3, 500, 70, 20, 200.0, 45.0, 2.5, 0, 1.3),
+        (4, 2000, 33, 65, 0.2, -30.0, 4.0, 7, 1.3),
+        (5, 1500, 16, 16, 80.0, 60.0, 3.0, 256, 3.0),
+        (6, 4000, 100, 8, 300.0, 10.0, 2.0, 513, 1.2),
+        (7, 800, 5, 3, 45.0, 0.0, 5.0, 33, 1.5),
+    ]
+    fields = []
+    for seed, n, nx, ny, ra0, dec0, fwhm, C, spread in specs:
+        rng = np.random.default_rng(1000 + seed)
+        ra = np.mod(ra0 + (rng.random(n) - 0.5) * nx * ARC * spread, 360.0)
+        dec = dec0 + (rng.random(n) - 0.5) * ny * ARC * spread
+        vals = None
+        if C > 0:
+            vals = torch.from_numpy(rng.normal(2.0, 1.0, size=(n, C)).astype(np.float32))
+            vals = vals.to(dtype).to(DEV)
+        fields.append({"ra": ra, "dec": dec, "map": synth.make_map(ra0, dec0, nx, ny),
+                       "kernel": synth.make_kernel(fwhm), "values": vals})
+    return fields
+
+
+def expected_items(fields):
+    total = 0
+    for f in fields:
+        if f["values"] is None:
+            continue
+        ntx = math.ceil(math.ceil(f["map"]["nx"] / 2) / 8)
+        nty = math.ceil(math.ceil(f["map"]["ny"] / 2) / 8)
+        total += ntx * nty * math.ceil(f["values"].shape[1] / 256)
+    return total
+
+
+@pytest.mark.parametrize("chunk", [0, 16])
+def test_batch_equals_single_plans_bitwise(chunk):
+    fields = mixed_fields()
+    print(f"\n  {len(fields)} mixed fields, chunk={chunk}", flush=True)
+    with api.Batch(fields, chunk=chunk, time_runs=True) as b:
+        outs = [o.clone() if o is not None else None for o in b.run()]
+        st = b.stats()
+        assert st["n_fields"] == len(fields)
+        assert st["n_items"] == expected_items(fields)
+        assert st["n_workgroups"] % 8 == 0 and st["n_workgroups"] >= st["n_items"]
+        assert st["runs"] == 1 and st["last_run_ms"] > 0
+        for i, f in enumerate(fields):
+            p = b.plan(i)
+            cnt_b = p.counts()
+            with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"], chunk=chunk) as q:
+                np.testing.assert_array_equal(cnt_b, q.counts())
+                if f["values"] is None:
+                    continue
+                ref = q.grid(f["values"]).cpu().numpy()
+            got = outs[i].cpu().numpy()
+            assert np.array_equal(got, ref, equal_nan=True), f"field {i} differs"
+        nnz = sum(int(b.plan(i).counts().sum()) for i in range(len(fields)))
+        assert st["nnz"] == nnz
+
+
+def test_batch_graph_replays_with_eager_work_between():
+    fields = mixed_fields()
+    with api.Batch(fields) as b:
+        first = [o.clone() for o in b.run() if o is not None]
+        for rep in range(3):
+            for o in b.outs:
+                if o is not None:
+                    o.fill_(-7.0)  # eager kernels on the bound buffers
+            torch.cuda.synchronize()
+            again = [o.clone() for o in b.run() if o is not None]
+            torch.cuda.synchronize()
+            for a, c in zip(first, again):
+                assert torch.equal(torch.nan_to_num(a, nan=1e30), torch.nan_to_num(c, nan=1e30)), rep
+        assert b.stats()["runs"] == 4
+
+
+def test_batch_plan_is_borrowed():
+    fields = mixed_fields()[:2]
+    b = api.Batch(fields)
+    p = b.plan(0)
+    L = api.lib()
+    assert L.hg_grid_finish(p._h) == api.HG_ERR_STATE
+    assert "batch" in api.last_error()
+    out = p.grid(fields[0]["values"])  # a borrowed plan still grids
+    assert out.shape == (fields[0]["values"].shape[1], 37, 40)
+    p.close()  # releases the borrow only
+    b.run()
+    b.close()
+    with pytest.raises(api.HegridError):
+        b.plan(0)
+
+
+def test_batch_mixed_dtypes_rejected():
+    fields = mixed_fields()[:2]
+    fields[1]["values"] = torch.zeros((0, 5), dtype=torch.float16, device=DEV)
+    with pytest.raises(api.HegridError):
+        api.Batch(fields)
+
+
+def scaled_workload(scale, n_fields):
+    fs = synth.batch_fields(n_fields, scale=scale)
+    out = []
+    for f in fs:
+        vals = synth.sky_values(f, f["nchan"], device=DEV, dtype="f16")
+        out.append({"ra": f["ra"], "dec": f["dec"], "map": f["map"], "kernel": f["kernel"],
+                    "values": vals})
+    return out
+
+
+@pytest.mark.parametrize("precision,tol", [(api.HG_PREC_FP32, 1e-6), (2, 2e-3)])
+def test_batch_workload_against_reference(precision, tol):
+    fields = scaled_workload(0.02, 64)
+    print(f"\n  64 fields, n {min(len(f['ra']) for f in fields)}..{max(len(f['ra']) for f in fields)}"
+          f", precision {precision}", flush=True)
+    worst = 0.0
+    with api.Batch(fields, precision=precision, time_runs=True) as b:
+        outs = b.run()
+        torch.cuda.synchronize()
+        st = b.stats()
+        print(f"  items {st['n_items']} nnz {st['nnz']} run {st['last_run_ms']:.3f} ms "
+              f"setup {st['setup_ms']:.1f} ms", flush=True)
+        for i, f in enumerate(fields):
+            C = f["values"].shape[1]
+            chans = np.array(sorted({0, C // 2, C - 1}))
+            hv, code = to_host_values(f["values"])
+            Vr, cr, Wr, margin = oracle.grid(f["ra"], f["dec"], hv, code, f["map"],
+                                             f["kernel"]["fwhm_deg"],
+                                             f["kernel"]["support_deg"], chans=chans)
+            assert margin > 1e-12, f"field {i}: closest call {margin:g}"
+            p = b.plan(i)
+            np.testing.assert_array_equal(p.counts(), cr, err_msg=f"field {i}")
+            V = outs[i].cpu().numpy().reshape(C, -1)[chans]
+            ok = cr > 0
+            np.testing.assert_array_equal(np.isnan(V), np.isnan(Vr), err_msg=f"field {i}")
+            e_max, _ = norm_err(V, Vr, ok)
+            worst = max(worst, e_max)
+            assert e_max <= tol, f"field {i}: e_max {e_max:g} > {tol:g}"
+    print(f"  worst e_max {worst:.3g}", flush=True)

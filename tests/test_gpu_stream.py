@@ -1,0 +1,125 @@
+"""GPU tests of the host-streamed channel phase (hg_grid_channels_host).
+
+The streamed call runs the channel kernel of hg_grid_channels on blocks of
+channels copied in from host memory, so its cube must equal the device-path
+cube bit for bit, for pageable and page-locked buffers, ragged last blocks,
+strided rows and the 16-bit MFMA form; on the large-cube geometry (19-beam
+drift scan, BF16 channels) scaled down, sampled channels of every block are
+also checked against the FP64 reference.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_04584_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2207_04584_amd import api  # noqa: E402
+from parity_util import norm_err, to_host_values  # noqa: E402
+
+DEV = "cuda:0"
+ARC = 1.0 / 60.0
+
+
+def field(n=6000, nx=45, ny=38, C=700, seed=3, dtype=torch.float32, ld=None):
+    rng = np.random.default_rng(seed)
+    ra = 120.0 + (rng.random(n) - 0.5) * nx * ARC * 1.2
+    dec = -10.0 + (rng.random(n) - 0.5) * ny * ARC * 1.2
+    ld = C if ld is None else ld
+    full = torch.from_numpy(rng.normal(1.0, 1.0, size=(n, ld)).astype(np.float32)).to(dtype)
+    return ra, dec, full[:, :C], synth.make_map(120.0, -10.0, nx, ny), synth.make_kernel(3.0)
+
+
+@pytest.mark.parametrize("pinned", [False, True])
+@pytest.mark.parametrize("block", [256, 300, 0])
+def test_streamed_equals_device_path(pinned, block):
+    ra, dec, vals, m, k = field()
+    if pinned:
+        vals = vals.contiguous().pin_memory()
+    out = torch.empty((vals.shape[1], m["ny"], m["nx"]), dtype=torch.float32,
+                      pin_memory=pinned)
+    with api.Plan(ra, dec, m, k) as p:
+        got, info = p.grid_host(vals, out=out, block=block)
+        ref = p.grid(vals.to(DEV)).cpu()
+    nb = -(-vals.shape[1] // (block or 4096))
+    print(f"\n  pinned={pinned} block={block}: {info}", flush=True)
+    assert info["blocks"] == nb and info["pinned"] == int(pinned)
+    assert info["h2d_bytes"] == vals.numel() * 4 and info["d2h_bytes"] == out.numel() * 4
+    assert info["kernel_ms"] > 0
+    assert torch.equal(torch.nan_to_num(got, nan=1e30), torch.nan_to_num(ref, nan=1e30))
+
+
+def test_streamed_strided_rows_and_repeat_calls():
+    ra, dec, vals, m, k = field(C=333, ld=520)  # rows of 520 channels, 333 used
+    assert vals.stride(0) == 520
+    with api.Plan(ra, dec, m, k) as p:
+        ref = p.grid(vals.contiguous().to(DEV)).cpu()
+        for block in (128, 100):  # the ring grows or is reused between calls
+            got, info = p.grid_host(vals, block=block)
+            assert info["pinned"] == 0  # the view of pageable rows is staged
+            assert torch.equal(torch.nan_to_num(got, nan=1e30), torch.nan_to_num(ref, nan=1e30))
+
+
+@pytest.mark.parametrize("dtype,prec", [(torch.bfloat16, api.HG_PREC_MFMA_BF16),
+                                        (torch.float16, api.HG_PREC_MFMA_F16),
+                                        (torch.bfloat16, api.HG_PREC_FP32)])
+def test_streamed_16bit_forms(dtype, prec):
+    ra, dec, vals, m, k = field(C=520, dtype=dtype)
+    with api.Plan(ra, dec, m, k, precision=prec) as p:
+        got, _ = p.grid_host(vals, block=256)
+        ref = p.grid(vals.to(DEV)).cpu()
+    assert torch.equal(torch.nan_to_num(got, nan=1e30), torch.nan_to_num(ref, nan=1e30))
+
+
+def test_streamed_empty_field_and_no_channels():
+    m, k = synth.make_map(10.0, 0.0, 20, 20), synth.make_kernel(3.0)
+    with api.Plan(np.zeros(0), np.zeros(0), m, k) as p:
+        out, info = p.grid_host(torch.zeros((0, 9)), block=4)
+        assert info["blocks"] == 3 and torch.isnan(out).all()
+    ra, dec, vals, m, k = field(C=1)
+    with api.Plan(ra, dec, m, k) as p:
+        out, info = p.grid_host(vals[:, :0])
+        assert info["blocks"] == 0 and out.numel() == 0
+
+
+def test_streamed_ring_respects_memory_cap():
+    ra, dec, vals, m, k = field(C=64)
+    with api.Plan(ra, dec, m, k) as p:
+        plan_bytes = p.stats()["device_bytes"]
+    with api.Plan(ra, dec, m, k, device_mem_cap=plan_bytes + 4096) as p:
+        with pytest.raises(api.HegridError) as ei:
+            p.grid_host(vals, block=64)
+        assert ei.value.status == api.HG_ERR_NOMEM
+
+
+def test_streamed_cube_against_reference():
+    """Large-cube geometry (19 interleaved drift-scan beams, BF16 values,
+    continuum + line sources), scaled to 40,000 samples on a 60 x 60 map and
+    4 blocks of 512 channels; 4 channels of every block checked."""
+    f = synth.config("cfg5")
+    keep = np.random.default_rng(5).choice(f["ra"].shape[0], 40000, replace=False)
+    keep.sort()
+    ra, dec = f["ra"][keep], f["dec"][keep]
+    sub = dict(f, ra=ra, dec=dec, map=synth.make_map(180.0, 30.0, 60, 60))
+    C, block = 2048, 512
+    vals = synth.sky_values(sub, C, device=DEV, dtype="bf16").cpu()
+    with api.Plan(ra, dec, sub["map"], f["kernel"], precision=api.HG_PREC_MFMA_BF16) as p:
+        out, info = p.grid_host(vals, block=block)
+        cnt = p.counts()
+    print(f"\n  cube: {info}", flush=True)
+    chans = np.array([b * block + o for b in range(C // block) for o in (0, 77, 300, 511)])
+    hv, code = to_host_values(vals)
+    Vr, cr, _, margin = oracle.grid(ra, dec, hv, code, sub["map"], f["kernel"]["fwhm_deg"],
+                                    f["kernel"]["support_deg"], chans=chans)
+    assert margin > 1e-12
+    np.testing.assert_array_equal(cnt, cr)
+    V = out.numpy().reshape(C, -1)[chans]
+    np.testing.assert_array_equal(np.isnan(V), np.isnan(Vr))
+    e_max, e_rms = norm_err(V, Vr, cr > 0)
+    print(f"  e_max={e_max:.3g} e_rms={e_rms:.3g}", flush=True)
+    assert e_max <= 2e-3
