@@ -14,8 +14,7 @@
 //     channel-contiguous values in HBM) and the chunk's entry block (the
 //     entries of all 64 groups, prepared by setup);
 //   * staging is double-buffered: the loads for chunk c+1 go straight from
-//     global memory to LDS (global_load_lds) while the waves compute chunk c,
-//     and chunk c+2's rows are prefetched into L2;
+//     global memory to LDS (global_load_lds) while the waves compute chunk c;
 //   * each wave owns 4 pixel groups spread over the tile.  The MFMA rows are
 //     the group's four pixels (A = their weights) and the columns are the
 //     workgroup's channels, 4*lane + g for the g-th instruction (B = values);
@@ -48,7 +47,6 @@ static_assert(TILE_PGX == 8 && TILE_PGY == 8 && CH_WAVES == 16,
 constexpr int TILE_PX = TILE_PGX * PG;  // 16 pixels per tile side
 constexpr int OUT_STRIDE = CW / 2 + 4;  // LDS floats per pixel in the output transpose
 constexpr int OUT_LDS = TILE_PX * TILE_PX * OUT_STRIDE * 4;
-constexpr int TRASH_LDS = 256;
 
 constexpr int FORM_F32 = 0;  // FP32 values in LDS, one entry per MFMA
 constexpr int FORM_M16 = 1;  // 16-bit values in LDS, groups of four entries per MFMA
@@ -62,17 +60,23 @@ struct Form {
     static constexpr int UPS = FORM == FORM_F32 ? 1 : 4;   // entries per unit
 };
 
+// One staged chunk in LDS: `chunk` value rows, then the entry block (weights,
+// slots) for up to `ucap` units, then the 65 per-group offsets.  ucap is the
+// plan's largest block (a multiple of 4), so a chunk takes what the plan needs
+// rather than the 64 x chunk worst case, and more chunks fit in flight.
+constexpr int LDS_BYTES = 160 * 1024;
+constexpr int MAX_NBUF = 4;
+
 struct LdsLayout {
     int vals, ew, es, po, stride;
     template <int FORM>
-    __device__ __host__ static LdsLayout make(int chunk) {
+    __device__ __host__ static LdsLayout make(int chunk, int ucap) {
         typedef Form<FORM> F;
-        int max_units = TILE_PGS * ((chunk + F::UPS - 1) / F::UPS);
         LdsLayout L;
         L.vals = 0;
         L.ew = L.vals + chunk * F::RB;
-        L.es = L.ew + max_units * F::WB;
-        L.po = L.es + max_units * F::SB;
+        L.es = L.ew + ucap * F::WB;
+        L.po = L.es + ucap * F::SB;
         L.stride = L.po + 144;
         return L;
     }
@@ -86,20 +90,8 @@ struct LdsLayout {
 __device__ inline uint32_t lds_addr(const char* l) {
     return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)l);
 }
-__device__ inline void dma16(const void* g, const char* l) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 1\n\tglobal_load_lds_dwordx4 %0, off"
-                 :
-                 : "v"(g), "s"(lds_addr(l))
-                 : "memory", "m0");
-}
-__device__ inline void dma4(const void* g, const char* l) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 1\n\tglobal_load_lds_dword %0, off"
-                 :
-                 : "v"(g), "s"(lds_addr(l))
-                 : "memory", "m0");
-}
-// Same with a wave-uniform 64-bit base in scalar registers and a 32-bit
-// per-lane byte offset, so the lane part of the address costs one VGPR.
+// The global address is a wave-uniform 64-bit base in scalar registers plus a
+// 32-bit per-lane byte offset, so the lane part of the address costs one VGPR.
 __device__ inline const void* uniform_ptr(const void* p) {
     uint64_t u = (uint64_t)(uintptr_t)p;
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
@@ -248,6 +240,23 @@ __device__ inline void mfma4_16(v4f* part, uint2 a, uint2 v0, uint2 v1, uint2 v2
     }
 }
 
+// s_waitcnt vmcnt(k) for a wave-uniform k (the counter field is an
+// immediate): vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left open.
+__device__ inline void wait_copies(int k) {
+#define HG_WAIT_CASE(n) \
+    case n:             \
+        __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15) | (((n) >> 4) << 14)); \
+        break;
+    switch (k) {
+        HG_WAIT_CASE(1) HG_WAIT_CASE(2) HG_WAIT_CASE(3) HG_WAIT_CASE(4) HG_WAIT_CASE(5)
+        HG_WAIT_CASE(6) HG_WAIT_CASE(7) HG_WAIT_CASE(8) HG_WAIT_CASE(9) HG_WAIT_CASE(10)
+        HG_WAIT_CASE(11) HG_WAIT_CASE(12) HG_WAIT_CASE(13) HG_WAIT_CASE(14) HG_WAIT_CASE(15)
+        default:
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    }
+#undef HG_WAIT_CASE
+}
+
 template <int FORM, int DT, bool VEC>
 __device__ __attribute__((always_inline)) inline void grid_item(
     const void* __restrict__ values, int64_t ld, int32_t nchan, int32_t npgx, int32_t npgy,
@@ -255,11 +264,10 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     const uint32_t* __restrict__ slot_idx, const int64_t* __restrict__ tile_blk,
     const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
     const void* __restrict__ ent_w, const void* __restrict__ ent_s,
-    const float* __restrict__ pix_Wf, float* __restrict__ out, int32_t out_vec, int64_t tile,
-    int64_t cb, char* smem) {
+    const float* __restrict__ pix_Wf, float* __restrict__ out, int32_t out_vec, int32_t ucap,
+    int32_t nbuf, int64_t tile, int64_t cb, char* smem) {
     typedef Form<FORM> F;
-    const LdsLayout L = LdsLayout::make<FORM>(chunk);
-    char* trash = smem + 2 * L.stride;
+    const LdsLayout L = LdsLayout::make<FORM>(chunk, ucap);
     int tx = (int)(tile % ntx), ty = (int)(tile / ntx);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -302,11 +310,10 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
         int r0 = FORM == FORM_F32 ? wave : 2 * wave;
         int r1 = FORM == FORM_F32 ? wave + CH_WAVES : 2 * wave + 1;
-        // chunk <= 32: at most two rows per wave; absent rows repeat a valid
-        // one so that the prefetch always has an address
+        // chunk <= 32: at most two rows per wave
         m.nrows = (r0 < ns) + (r1 < ns);
-        m.row0 = sidx[s0 + (r0 < ns ? r0 : 0)];
-        m.row1 = r1 < ns ? sidx[s0 + r1] : m.row0;
+        m.row0 = r0 < ns ? sidx[s0 + r0] : 0u;
+        m.row1 = r1 < ns ? sidx[s0 + r1] : 0u;
         m.blk = blk0 + ch;
         m.eb = blk_base[m.blk];
         m.ne = (int)(blk_base[m.blk + 1] - m.eb);
@@ -345,56 +352,64 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         if (wave == CH_WAVES - 1 && lane < PGOFF_STRIDE / 2)
             dma4s(blk_pgoff + m.blk * PGOFF_STRIDE, 4u * lane, base + L.po);
     };
-    // L2 prefetch of a later chunk's rows: exactly one copy instruction per
-    // wave (lanes touch both halves of every 128-byte line of the wave's two
-    // rows; the data lands in a scratch area of LDS and is never read).
-    auto prefetch = [&](const Meta& m) {
-        constexpr int LINES = F::RB / 64;  // 64-byte halves per row: 16 or 8
-        int q = lane / LINES, part = lane % LINES;
-        uint32_t row = q == 0 ? m.row0 : m.row1;
-        const char* src = (const char*)values + ((int64_t)row * ld + c_lo) * F::VB + part * 64;
-        if (lane < 2 * LINES && (q < m.nrows || lane == 0)) dma4(src, trash);
+    // Copy instructions issue() is certain to start for this wave (each
+    // counted one has at least one active lane).  Copies whose lanes may all
+    // be off are left out, which only makes the waits below stricter.
+    auto copies = [&](const Meta& m) {
+        int k = 0;
+        if (FORM == FORM_F32) {
+            if (dma_rows) k += m.nrows;
+            if (m.ne > wave * 64) k += 2 * ((m.ne - wave * 64 + CH_THREADS - 1) / CH_THREADS);
+        } else {
+            if (dma_rows && m.nrows > 0) k += m.nrows;
+            if (m.ne > wave * 32) k += (m.ne - wave * 32 + CH_WAVES * 32 - 1) / (CH_WAVES * 32);
+            if (m.ne > wave * 64) k += (m.ne - wave * 64 + CH_THREADS - 1) / CH_THREADS;
+        }
+        if (wave == CH_WAVES - 1) k += 1;
+        return k;
     };
-
     v4f acc[PGW][G];
 #pragma unroll
     for (int k = 0; k < PGW; k++)
 #pragma unroll
         for (int g = 0; g < G; g++) acc[k][g] = (v4f){0.f, 0.f, 0.f, 0.f};
 
-    Meta m1{}, m2{};
-    bool pf = false;  // a prefetch is the youngest outstanding copy
-    if (nch > 0) {
-        Meta m0 = load_meta(0);
-        if (nch > 1) m1 = load_meta(1);
-        if (nch > 2) m2 = load_meta(2);
-        issue(m0, 0);
-        if (dma_rows && nch > 1) {
-            prefetch(m1);
-            pf = true;
-        }
+    // nbuf chunks are resident: while chunk ch is computed, chunks up to
+    // ch + nbuf - 2 are in flight and chunk ch + nbuf - 1 is issued into the
+    // buffer chunk ch - 1 used.  A chunk's metadata is read one chunk before
+    // its copies are issued, so the scalar loads are back by then.
+    // k1, k2: this wave's copies for chunks ch + 1 and ch + 2 (those may
+    // still be outstanding when chunk ch is waited for).
+    Meta mn{};
+    int k1 = 0, k2 = 0;
+    for (int i = 0; i < nbuf - 1 && i < nch; i++) {
+        Meta m = load_meta(i);
+        issue(m, i);
+        if (i == 1) k1 = copies(m);
+        if (i == 2) k2 = copies(m);
     }
+    if (nbuf - 1 < nch) mn = load_meta(nbuf - 1);
+    int cur = 0;  // ch mod nbuf
     for (int64_t ch = 0; ch < nch; ch++) {
-        // Chunk ch's copies are complete (only the prefetch, if any, may still
-        // be in flight); the barrier makes every wave's copies visible and
-        // retires all reads of the other buffer.
-        if (pf)
-            __builtin_amdgcn_s_waitcnt(0x3F71);  // vmcnt(1) expcnt(7) lgkmcnt(15)
-        else
-            __builtin_amdgcn_s_waitcnt(0);
+        // Wait for this wave's copies of chunk ch (later chunks may stay in
+        // flight); the barrier then makes every wave's copies visible and
+        // retires all reads of chunk ch - 1's buffer.
+        wait_copies(k1 + k2);
         __syncthreads();
-        pf = false;
-        if (ch + 1 < nch) {
-            Meta m3 = (ch + 3 < nch) ? load_meta(ch + 3) : m2;
-            issue(m1, (int)((ch + 1) & 1));
-            if (dma_rows && ch + 2 < nch) {
-                prefetch(m2);
-                pf = true;
-            }
-            m1 = m2;
-            m2 = m3;
+        int kn = 0;
+        if (ch + nbuf - 1 < nch) {
+            kn = copies(mn);
+            issue(mn, cur == 0 ? nbuf - 1 : cur - 1);
+            if (ch + nbuf < nch) mn = load_meta(ch + nbuf);
         }
-        const char* base = smem + (ch & 1) * L.stride;
+        if (nbuf == 4) {
+            k1 = k2;
+            k2 = kn;
+        } else if (nbuf == 3) {
+            k1 = kn;
+        }
+        const char* base = smem + cur * L.stride;
+        cur = cur + 1 == nbuf ? 0 : cur + 1;
         const char* vals = base + L.vals;
         const char* ew = base + L.ew;
         const uint32_t* es = (const uint32_t*)(base + L.es);
@@ -416,13 +431,36 @@ __device__ __attribute__((always_inline)) inline void grid_item(
                 // coalesced LDS load, lane i holding entry e+i; each entry's
                 // slot then comes from v_readlane into a scalar register, so
                 // the value read needs no second LDS round trip.
+                // Entries go four at a time so that the eight LDS reads of a
+                // step are in flight together ahead of its sixteen MFMAs.
                 const int n = e1 - e;
                 uint32_t slot_lane = es[e + (lane < n ? lane : 0)];
                 const float* ewq = (const float*)ew + e * 4 + q;
-                for (int j = 0; j < n; j++) {
+                const char* vl = vals + lane * 16;
+                int j = 0;
+                for (; j + 4 <= n; j += 4) {
+                    uint32_t s0 = __builtin_amdgcn_readlane(slot_lane, j);
+                    uint32_t s1 = __builtin_amdgcn_readlane(slot_lane, j + 1);
+                    uint32_t s2 = __builtin_amdgcn_readlane(slot_lane, j + 2);
+                    uint32_t s3 = __builtin_amdgcn_readlane(slot_lane, j + 3);
+                    float a0 = ewq[j * 4], a1 = ewq[j * 4 + 4], a2 = ewq[j * 4 + 8],
+                          a3 = ewq[j * 4 + 12];
+                    float4 v0 = *(const float4*)(vl + s0 * F::RB);
+                    float4 v1 = *(const float4*)(vl + s1 * F::RB);
+                    float4 v2 = *(const float4*)(vl + s2 * F::RB);
+                    float4 v3 = *(const float4*)(vl + s3 * F::RB);
+                    mfma4_f32(part, a0, v0);
+                    mfma4_f32(part, a1, v1);
+                    mfma4_f32(part, a2, v2);
+                    mfma4_f32(part, a3, v3);
+                    // schedule: all LDS reads of the step, then its MFMAs
+                    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+                }
+                for (; j < n; j++) {
                     uint32_t sj = __builtin_amdgcn_readlane(slot_lane, j);
                     float a0 = ewq[j * 4];
-                    float4 v0 = *(const float4*)(vals + sj * F::RB + lane * 16);
+                    float4 v0 = *(const float4*)(vl + sj * F::RB);
                     mfma4_f32(part, a0, v0);
                 }
             } else {
@@ -500,7 +538,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ blk_base,
     const uint16_t* __restrict__ blk_pgoff, const void* __restrict__ ent_w,
     const void* __restrict__ ent_s, const float* __restrict__ pix_Wf, float* __restrict__ out,
-    int32_t out_vec) {
+    int32_t out_vec, int32_t ucap, int32_t nbuf) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
     // contiguous run of (tile, channel block) so that a tile's channel blocks
@@ -511,7 +549,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
     int64_t logical = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
     grid_item<FORM, DT, VEC>(values, ld, nchan, npgx, npgy, ntx, nx, ny, chunk, tile_base,
                              slot_idx, tile_blk, blk_base, blk_pgoff, ent_w, ent_s, pix_Wf, out,
-                             out_vec, logical / ncb, logical % ncb, smem);
+                             out_vec, ucap, nbuf, logical / ncb, logical % ncb, smem);
 }
 
 // Batched form: one launch over the (field, tile, channel block) items of many
@@ -534,21 +572,33 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_batch(
     const CONST_AS FieldDesc& d = ((const CONST_AS FieldDesc*)fields)[f];
     grid_item<FORM, DT, VEC>(d.values, d.ld, d.nchan, d.npgx, d.npgy, d.ntx, d.nx, d.ny, d.chunk,
                              d.tile_base, d.slot_idx, d.tile_blk, d.blk_base, d.blk_pgoff,
-                             d.ent_w, d.ent_s, d.pix_Wf, d.out, d.out_vec, it->tile, it->cb,
-                             smem);
+                             d.ent_w, d.ent_s, d.pix_Wf, d.out, d.out_vec, d.ucap, d.nbuf,
+                             it->tile, it->cb, smem);
 }
 
-size_t lds_bytes(bool m16, int chunk) {
-    size_t st = m16 ? LdsLayout::make<FORM_M16>(chunk).stride
-                    : LdsLayout::make<FORM_F32>(chunk).stride;
-    size_t shm = 2 * st + TRASH_LDS;
+// LDS plan of a field: entry capacity, resident chunks and dynamic LDS bytes
+// (the output transpose of the epilogue reuses the same space).
+size_t lds_stride(bool m16, int chunk, int ucap) {
+    return m16 ? LdsLayout::make<FORM_M16>(chunk, ucap).stride
+               : LdsLayout::make<FORM_F32>(chunk, ucap).stride;
+}
+
+void lds_plan(bool m16, int chunk, int blk_max, int32_t& ucap, int32_t& nbuf) {
+    ucap = (blk_max < 4 ? 4 : (blk_max + 3) / 4 * 4);
+    nbuf = (int32_t)(LDS_BYTES / lds_stride(m16, chunk, ucap));
+    if (nbuf > MAX_NBUF) nbuf = MAX_NBUF;
+    if (nbuf < 2) nbuf = 2;  // not reached: a block holds at most 64 x chunk entries
+}
+
+size_t lds_shm(bool m16, int chunk, int ucap, int nbuf) {
+    size_t shm = (size_t)nbuf * lds_stride(m16, chunk, ucap);
     return shm < (size_t)OUT_LDS ? (size_t)OUT_LDS : shm;
 }
 
 template <int FORM, int DT, bool VEC>
 hipError_t launch_typed(const FieldDesc& d, int64_t ntiles, hipStream_t s) {
     int64_t nwg = (int64_t)d.ncb * ntiles;
-    size_t shm = lds_bytes(FORM == FORM_M16, d.chunk);
+    size_t shm = lds_shm(FORM == FORM_M16, d.chunk, d.ucap, d.nbuf);
     auto kern = k_channels<FORM, DT, VEC>;
     if (shm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -558,7 +608,7 @@ hipError_t launch_typed(const FieldDesc& d, int64_t ntiles, hipStream_t s) {
     hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(CH_THREADS), shm, s, d.values, d.ld,
                        d.nchan, d.ncb, d.npgx, d.npgy, d.ntx, d.nx, d.ny, d.chunk, d.tile_base,
                        d.slot_idx, d.tile_blk, d.blk_base, d.blk_pgoff, d.ent_w, d.ent_s,
-                       d.pix_Wf, d.out, d.out_vec);
+                       d.pix_Wf, d.out, d.out_vec, d.ucap, d.nbuf);
     return hipGetLastError();
 }
 
@@ -603,6 +653,7 @@ FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t ncha
     d.nx = P.map.nx;
     d.ny = P.map.ny;
     d.chunk = P.chunk;
+    lds_plan(m16, P.chunk, P.blk_max, d.ucap, d.nbuf);
     d.out_vec = ((uintptr_t)out % 16 == 0) && (P.map.nx % 4 == 0);
     d.tile_base = (const int64_t*)P.tile_nslots.p;
     d.slot_idx = (const uint32_t*)P.slot_idx.p;
@@ -637,10 +688,14 @@ hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t ncha
                : launch_typed<FORM_F32, HG_F16, false>(d, P.ntiles, s);
 }
 
-BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, int32_t chunk) {
+size_t field_lds_bytes(const FieldDesc& d, bool m16) {
+    return lds_shm(m16, d.chunk, d.ucap, d.nbuf);
+}
+
+BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm) {
     BatchKernelInfo k;
     k.main = pick<BatchKernel>(m16, dtype, vec);
-    k.shm = lds_bytes(m16, chunk);
+    k.shm = shm;
     k.threads = CH_THREADS;
     k.channels_per_block = CW;
     return k;

@@ -192,6 +192,7 @@ struct Plan {
     DevBuf chunk_ptr;    // uint32 [chunk_ptrs] entry offset (relative to pg_base)
     // chunk-major entry blocks: block b = (tile t, chunk c), b = tile_blk[t] + c
     int64_t n_blocks = 0;
+    int32_t blk_max = 0;  // most units (entries, or groups of four) in one block
     DevBuf tile_blk;     // int64 [ntiles+1] first block of each tile
     DevBuf blk_base;     // int64 [n_blocks+1] first entry of each block
     DevBuf blk_pgoff;    // uint16 [n_blocks][PGOFF_STRIDE] per-group offsets in the block
@@ -227,7 +228,10 @@ struct FieldDesc {
     const void* ent_s;
     const float* pix_Wf;
     float* out;
-    int32_t nchan, ncb, npgx, npgy, ntx, nx, ny, chunk, out_vec, pad;
+    int32_t nchan, ncb, npgx, npgy, ntx, nx, ny, chunk, out_vec;
+    int32_t ucap;  // LDS capacity in units per staged block (>= the plan's blk_max)
+    int32_t nbuf;  // staged chunks resident in LDS (2..4)
+    int32_t pad;
 };
 
 // One work item of the batched launch: (field, tile, channel block); field < 0
@@ -251,7 +255,8 @@ hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t ncha
                            float* out, hipStream_t s);
 FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out);
 bool values_vec(const Plan& P, const void* values, int64_t ld, int32_t dtype);
-BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, int32_t chunk);
+BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm);
+size_t field_lds_bytes(const FieldDesc& d, bool m16);
 hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
                           int64_t* pix, hipStream_t s);
 

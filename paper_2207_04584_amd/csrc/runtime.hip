@@ -669,8 +669,10 @@ int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, cons
             if (e == hipSuccess)
                 e = hipMemcpy(b->items.p, pos.data(), sizeof(BatchItem) * pos.size(),
                               hipMemcpyHostToDevice);
-            BatchKernelInfo ki =
-                batch_kernel(b->opts.precision != HG_PREC_FP32, dtype, vec, b->plans[0]->P.chunk);
+            const bool m16 = b->opts.precision != HG_PREC_FP32;
+            size_t shm = 0;
+            for (const FieldDesc& d : descs) shm = std::max(shm, field_lds_bytes(d, m16));
+            BatchKernelInfo ki = batch_kernel(m16, dtype, vec, shm);
             if (e == hipSuccess && ki.shm > 65536)
                 e = hipFuncSetAttribute(ki.main, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)ki.shm);

@@ -733,6 +733,21 @@ __global__ __launch_bounds__(256) void k_block_fill(
     }
 }
 
+// max over a[0..n) (values below 2^31) into *out, which starts at 0: a
+// grid-stride pass, a workgroup reduction, one atomic per workgroup
+__global__ __launch_bounds__(256) void k_max_count(const int64_t* __restrict__ a, int64_t n,
+                                                   int* __restrict__ out) {
+    __shared__ int red[4];
+    int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (int)a[i]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(out, max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
 // Precision forms: the same blocks, counted in groups of four entries (the K
 // of the 4x4x4 MFMA).  A group holds four chunk-local slots and the 4 x 4 weights
 // [pixel][entry] as BF16 / FP16 bits; a run whose length is not a multiple of
@@ -915,6 +930,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
 
     int* flag = (int*)P.scratch.p;
     unsigned long long* nnz_total = (unsigned long long*)((char*)P.scratch.p + 8);
+    int* blk_max = (int*)((char*)P.scratch.p + 16);  // most units in one block
     void* scan_tmp = (char*)P.scratch.p + 64;
 
     HG_STEP(hipMemsetAsync(P.scratch.p, 0, 64, s));
@@ -1074,6 +1090,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const uint32_t*)P.chunk_ptr.p, (const int64_t*)P.pg_base.p,
                            (int64_t*)bcnt.p, (uint16_t*)P.blk_pgoff.p);
         HG_STEP(hipGetLastError());
+        // the largest block sizes the channel kernel's LDS entry area
+        hipLaunchKernelGGL(k_max_count, dim3(256), dim3(256), 0, s, (const int64_t*)bcnt.p,
+                           P.n_blocks, blk_max);
+        HG_STEP(hipGetLastError());
     }
     HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)bcnt.p, P.n_blocks,
                                               (int64_t*)P.blk_base.p, (int64_t*)scan_tmp, s)));
@@ -1082,9 +1102,12 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(hipMemcpyAsync(&nz, nnz_total, sizeof nz, hipMemcpyDeviceToHost, s));
     HG_STEP(hipMemcpyAsync(&n_ent, (int64_t*)P.blk_base.p + P.n_blocks, sizeof n_ent,
                            hipMemcpyDeviceToHost, s));
+    int bmax = 0;
+    HG_STEP(hipMemcpyAsync(&bmax, blk_max, sizeof bmax, hipMemcpyDeviceToHost, s));
     HG_STEP(hipStreamSynchronize(s));
     P.nnz = (int64_t)nz;
     P.nnz_entries = n_ent;
+    P.blk_max = bmax;
     if (grouped) {
         HG_STEP(dev_alloc(P.e3_w, (size_t)(n_ent ? n_ent : 1) * 32));
         HG_STEP(dev_alloc(P.e3_s, (size_t)(n_ent ? n_ent : 1) * 16));
