@@ -66,6 +66,11 @@ struct Form {
 // rather than the 64 x chunk worst case, and more chunks fit in flight.
 constexpr int LDS_BYTES = 160 * 1024;
 constexpr int MAX_NBUF = 4;
+// Chunk metadata ring: two halves of 16 chunks, each chunk's staged-row sample
+// indices (MAX_CHUNK x uint32) and the 17 entry-block offsets of a half.
+constexpr int META_RUN = 16;
+constexpr int META_ROWS = 2 * META_RUN * MAX_CHUNK * 4;
+constexpr int META_LDS = META_ROWS + 2 * (META_RUN + 1) * 8;
 
 struct LdsLayout {
     int vals, ew, es, po, stride;
@@ -240,21 +245,19 @@ __device__ inline void mfma4_16(v4f* part, uint2 a, uint2 v0, uint2 v1, uint2 v2
     }
 }
 
-// s_waitcnt vmcnt(k) for a wave-uniform k (the counter field is an
-// immediate): vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left open.
+// Wait until at most k of this wave's copies are outstanding, for a
+// wave-uniform k.  The counter field of s_waitcnt is an immediate, so k is
+// rounded down to 0, 2, 4 or 8 (waiting for a little more than needed) to
+// keep the choice to three scalar branches.
 __device__ inline void wait_copies(int k) {
-#define HG_WAIT_CASE(n) \
-    case n:             \
-        __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15) | (((n) >> 4) << 14)); \
-        break;
-    switch (k) {
-        HG_WAIT_CASE(1) HG_WAIT_CASE(2) HG_WAIT_CASE(3) HG_WAIT_CASE(4) HG_WAIT_CASE(5)
-        HG_WAIT_CASE(6) HG_WAIT_CASE(7) HG_WAIT_CASE(8) HG_WAIT_CASE(9) HG_WAIT_CASE(10)
-        HG_WAIT_CASE(11) HG_WAIT_CASE(12) HG_WAIT_CASE(13) HG_WAIT_CASE(14) HG_WAIT_CASE(15)
-        default:
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    }
-#undef HG_WAIT_CASE
+    if (k >= 8)
+        __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8), expcnt and lgkmcnt open
+    else if (k >= 4)
+        __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4)
+    else if (k >= 2)
+        __builtin_amdgcn_s_waitcnt(0x0F72);  // vmcnt(2)
+    else
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 }
 
 template <int FORM, int DT, bool VEC>
@@ -295,29 +298,64 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     }
 
     // Per chunk each wave stages two rows: (w, w+16) in the FP32 form and the
-    // adjacent pair (2w, 2w+1) in the 16-bit forms.  All indices are
-    // wave-uniform, so the metadata comes through scalar loads and the vector
-    // memory counter only counts the asynchronous copies, which the pipeline
-    // waits for explicitly.
+    // adjacent pair (2w, 2w+1) in the 16-bit forms.  The chunk metadata (the
+    // rows' sample indices and the entry block's extent) reaches LDS through
+    // the same asynchronous copies as the data, sixteen chunks at a time into
+    // one half of a two-half ring, long before it is read; the loop issues no
+    // scalar loads, whose latency the LDS waits of the compute phase would
+    // otherwise absorb.  The vector memory counter thus only counts copies,
+    // which the pipeline waits for explicitly.
+    char* ring_rows = smem + nbuf * L.stride;
+    char* ring_blk = ring_rows + META_ROWS;
     struct Meta {
         uint32_t row0, row1;
         int nrows, ne;
         int64_t blk, eb;
     };
-    auto load_meta = [&](int64_t ch) {
+    auto rd64 = [&](const char* p) {
+        uint32_t lo = __builtin_amdgcn_readfirstlane(*(const uint32_t*)p);
+        uint32_t hi = __builtin_amdgcn_readfirstlane(*(const uint32_t*)(p + 4));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
+    auto meta_of = [&](int64_t ch) {
         Meta m;
+        const int h = (int)((ch / META_RUN) & 1), j = (int)(ch % META_RUN);
+        const uint32_t* rr = (const uint32_t*)(ring_rows) + (h * META_RUN + j) * MAX_CHUNK;
+        const char* bb = ring_blk + (h * (META_RUN + 1) + j) * 8;
         int64_t s0 = ch * chunk;
         int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
         int r0 = FORM == FORM_F32 ? wave : 2 * wave;
         int r1 = FORM == FORM_F32 ? wave + CH_WAVES : 2 * wave + 1;
         // chunk <= 32: at most two rows per wave
         m.nrows = (r0 < ns) + (r1 < ns);
-        m.row0 = r0 < ns ? sidx[s0 + r0] : 0u;
-        m.row1 = r1 < ns ? sidx[s0 + r1] : 0u;
+        m.row0 = r0 < ns ? __builtin_amdgcn_readfirstlane(rr[r0]) : 0u;
+        m.row1 = r1 < ns ? __builtin_amdgcn_readfirstlane(rr[r1]) : 0u;
         m.blk = blk0 + ch;
-        m.eb = blk_base[m.blk];
-        m.ne = (int)(blk_base[m.blk + 1] - m.eb);
+        m.eb = rd64(bb);
+        m.ne = (int)(rd64(bb + 8) - m.eb);
         return m;
+    };
+    // Copy the metadata of chunks [c0, c0 + 16) into ring half h: wave w the
+    // row indices of chunk c0 + w, wave 0 also the 17 block offsets.  Returns
+    // the copies this wave issued (each has at least one active lane).
+    auto refill = [&](int64_t c0, int h) {
+        int k = 0;
+        const int64_t c = c0 + wave;
+        if (c < nch) {
+            const int64_t s0 = c * chunk;
+            const int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
+            if (lane < ns)
+                dma4s(sidx + s0, 4u * lane,
+                      ring_rows + (h * META_RUN + wave) * MAX_CHUNK * 4);
+            k++;
+        }
+        if (wave == 0) {
+            // blk_base[blk0 + c0 + t] for t <= 16 while c0 + t <= nch
+            if (c0 + (lane >> 1) <= nch && lane < 2 * (META_RUN + 1))
+                dma4s(blk_base + blk0 + c0, 4u * lane, ring_blk + h * (META_RUN + 1) * 8);
+            k++;
+        }
+        return k;
     };
     auto issue = [&](const Meta& m, int buf) {
         char* base = smem + buf * L.stride;
@@ -376,19 +414,27 @@ __device__ __attribute__((always_inline)) inline void grid_item(
 
     // nbuf chunks are resident: while chunk ch is computed, chunks up to
     // ch + nbuf - 2 are in flight and chunk ch + nbuf - 1 is issued into the
-    // buffer chunk ch - 1 used.  A chunk's metadata is read one chunk before
-    // its copies are issued, so the scalar loads are back by then.
+    // buffer chunk ch - 1 used.  Metadata half h holds chunks [16 t, 16 t + 16)
+    // for t = h mod 2; the half of chunks [i + 16, i + 32) is refilled at
+    // iteration i (i a multiple of 16), before that iteration's data copies,
+    // and first read nbuf - 1 iterations before chunk i + 16, by which time
+    // the data copies issued after it have been waited for.
     // k1, k2: this wave's copies for chunks ch + 1 and ch + 2 (those may
-    // still be outstanding when chunk ch is waited for).
-    Meta mn{};
+    // still be outstanding when chunk ch is waited for), a refill counted
+    // with the chunk issued right after it.
+    if (nch > 0) {
+        refill(0, 0);
+        if (nch > META_RUN) refill(META_RUN, 1);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        __syncthreads();
+    }
     int k1 = 0, k2 = 0;
     for (int i = 0; i < nbuf - 1 && i < nch; i++) {
-        Meta m = load_meta(i);
+        Meta m = meta_of(i);
         issue(m, i);
         if (i == 1) k1 = copies(m);
         if (i == 2) k2 = copies(m);
     }
-    if (nbuf - 1 < nch) mn = load_meta(nbuf - 1);
     int cur = 0;  // ch mod nbuf
     for (int64_t ch = 0; ch < nch; ch++) {
         // Wait for this wave's copies of chunk ch (later chunks may stay in
@@ -397,16 +443,20 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         wait_copies(k1 + k2);
         __syncthreads();
         int kn = 0;
+        if (ch % META_RUN == 0 && ch >= META_RUN && ch + META_RUN < nch)
+            kn += refill(ch + META_RUN, (int)(((ch / META_RUN) + 1) & 1));
         if (ch + nbuf - 1 < nch) {
-            kn = copies(mn);
+            Meta mn = meta_of(ch + nbuf - 1);
+            kn += copies(mn);
             issue(mn, cur == 0 ? nbuf - 1 : cur - 1);
-            if (ch + nbuf < nch) mn = load_meta(ch + nbuf);
         }
         if (nbuf == 4) {
             k1 = k2;
             k2 = kn;
         } else if (nbuf == 3) {
             k1 = kn;
+        } else {
+            k1 = 0;
         }
         const char* base = smem + cur * L.stride;
         cur = cur + 1 == nbuf ? 0 : cur + 1;
@@ -414,27 +464,39 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         const char* ew = base + L.ew;
         const uint32_t* es = (const uint32_t*)(base + L.es);
         const uint16_t* po = (const uint16_t*)(base + L.po);
+        // The wave's four groups: their unit ranges (all 65 offsets come in
+        // with one read, lane l holding offset l) and their slot runs (at most
+        // `chunk` slots each, lane i holding the run's i-th), all read before
+        // any is used so that the LDS latency is paid once per chunk.  Ranges
+        // and slots are wave-uniform and go to scalar registers by v_readlane.
+        const uint32_t po_lane = po[lane];
+        const int po_end = __builtin_amdgcn_readfirstlane((int)po[TILE_PGS]);
+        int eK[PGW], e1K[PGW];
+        uint32_t slK[PGW];
+#pragma unroll
+        for (int k = 0; k < PGW; k++) {
+            const int lp = lys[k] * TILE_PGX + lxs[k];
+            eK[k] = (int)__builtin_amdgcn_readlane(po_lane, lp);
+            e1K[k] = lp + 1 < TILE_PGS ? (int)__builtin_amdgcn_readlane(po_lane, lp + 1) : po_end;
+            const int n = (FORM == FORM_F32 ? 1 : 4) * (e1K[k] - eK[k]);
+            slK[k] = es[(FORM == FORM_F32 ? 1 : 4) * eK[k] + (lane < n ? lane : 0)];
+        }
 #pragma unroll
         for (int k = 0; k < PGW; k++) {
             if (!pv[k]) continue;
-            int lp = lys[k] * TILE_PGX + lxs[k];
-            // the group's unit range is wave-uniform: keep it in scalar registers
-            int e = __builtin_amdgcn_readfirstlane((int)po[lp]);
-            int e1 = __builtin_amdgcn_readfirstlane((int)po[lp + 1]);
+            const int e = eK[k], e1 = e1K[k];
             if (e == e1) continue;
             v4f part[G];
 #pragma unroll
             for (int g = 0; g < G; g++) part[g] = (v4f){0.f, 0.f, 0.f, 0.f};
             const int q = lane & 3;
             if (FORM == FORM_F32) {
-                // The group's run of at most `chunk` slots is read with one
-                // coalesced LDS load, lane i holding entry e+i; each entry's
-                // slot then comes from v_readlane into a scalar register, so
-                // the value read needs no second LDS round trip.
+                // Each entry's slot comes from v_readlane into a scalar
+                // register, so the value read needs no second LDS round trip.
                 // Entries go four at a time so that the eight LDS reads of a
                 // step are in flight together ahead of its sixteen MFMAs.
                 const int n = e1 - e;
-                uint32_t slot_lane = es[e + (lane < n ? lane : 0)];
+                const uint32_t slot_lane = slK[k];
                 const float* ewq = (const float*)ew + e * 4 + q;
                 const char* vl = vals + lane * 16;
                 int j = 0;
@@ -464,10 +526,8 @@ __device__ __attribute__((always_inline)) inline void grid_item(
                     mfma4_f32(part, a0, v0);
                 }
             } else {
-                // groups of four entries; their slots (at most 4 x chunk/4)
-                // are read with one coalesced load and picked by v_readlane
-                const int n = 4 * (e1 - e);
-                uint32_t slot_lane = es[4 * e + (lane < n ? lane : 0)];
+                // groups of four entries, slots picked by v_readlane
+                const uint32_t slot_lane = slK[k];
                 for (int t = 0; t < e1 - e; t++) {
                     uint32_t s0 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 0);
                     uint32_t s1 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 1);
@@ -585,13 +645,13 @@ size_t lds_stride(bool m16, int chunk, int ucap) {
 
 void lds_plan(bool m16, int chunk, int blk_max, int32_t& ucap, int32_t& nbuf) {
     ucap = (blk_max < 4 ? 4 : (blk_max + 3) / 4 * 4);
-    nbuf = (int32_t)(LDS_BYTES / lds_stride(m16, chunk, ucap));
+    nbuf = (int32_t)((LDS_BYTES - META_LDS) / lds_stride(m16, chunk, ucap));
     if (nbuf > MAX_NBUF) nbuf = MAX_NBUF;
     if (nbuf < 2) nbuf = 2;  // not reached: a block holds at most 64 x chunk entries
 }
 
 size_t lds_shm(bool m16, int chunk, int ucap, int nbuf) {
-    size_t shm = (size_t)nbuf * lds_stride(m16, chunk, ucap);
+    size_t shm = (size_t)nbuf * lds_stride(m16, chunk, ucap) + META_LDS;
     return shm < (size_t)OUT_LDS ? (size_t)OUT_LDS : shm;
 }
 
