@@ -63,6 +63,21 @@ def cpu_baseline(f, vals_host, n_pix, seed=7):
                       f"{P / n_pix:.1f} to the full map"}
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    record in profiles/, or None when there is none or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_channels_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec["kernel_source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def host_values(v):
     """A device tensor as the reference gridder reads it: (array, dtype code)."""
     import numpy as np
@@ -169,6 +184,7 @@ def run_drift(args):
 
     roof = roofline(2.0 * nnz * C, 4.0 * n * C + 4.0 * P * C, ch_avg, PEAK_FP32_MFMA_TFLOPS,
                     "k_channels (FP32 form, FP32 values)")
+    roof["traffic"] = measured_traffic("drift")
     res = {
         "metric": "G sample*channel updates/s (plain FP32 form)",
         "value": value, "unit": "G sample*channel updates/s", "n_gpus": 1,
@@ -283,12 +299,22 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=3000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain elementwise pass over 1 GiB (read 1 GiB, write "
+                         "1 GiB) so that hardware byte counters can be scaled against it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path "
               "shards by channel block or field with no exchange; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.mul(src, 2.0)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
+        del src, dst
     res = run_drift(args) if args.workload == "drift" else run_batch(args)
     print(json.dumps(res), flush=True)
 
