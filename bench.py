@@ -65,16 +65,17 @@ def cpu_baseline(f, vals_host, n_pix, seed=7):
 
 def measured_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed PMC
-    record in profiles/, or None when there is none or the kernel source has
-    changed since the counters were taken."""
+    record in profiles/, or None when there is none or the sources it was
+    taken on (the kernel, and the setup that lays out its work) have changed
+    since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_channels_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, rec["kernel_source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
-        return None
+    for src, digest in rec["sources_sha256"].items():
+        if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != digest:
+            return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 

@@ -572,6 +572,67 @@ __global__ __launch_bounds__(256) void k_chunk_ptr(
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Slot compaction.  A tile's slots are every sample of its candidate cell runs;
+// those no pixel of the tile has in its support are dropped, so that the
+// channel kernel stages only samples it uses.  Slot order (ring, cell,
+// index) is kept, so each group's entries stay in ascending slot order.
+__device__ inline int64_t pg_tile(int64_t pg, int32_t npgx, int32_t ntx) {
+    int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
+    return (int64_t)(gy / TILE_PGY) * ntx + gx / TILE_PGX;
+}
+
+__global__ __launch_bounds__(256) void k_mark_used(
+    int32_t npgx, int64_t npg, int32_t ntx, const int64_t* __restrict__ tile_base,
+    const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ pg_cnt,
+    const uint32_t* __restrict__ ent_slot, uint32_t* __restrict__ used) {
+    int64_t pg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pg >= npg) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t tb = tile_base[pg_tile(pg, npgx, ntx)];
+    const uint32_t* es = ent_slot + pg_base[pg];
+    for (uint32_t t = lane; t < pg_cnt[pg]; t += 64) used[tb + (es[t] & SLOT_MASK)] = 1u;
+}
+
+__global__ void k_tile_rebase(const int64_t* __restrict__ tile_base, int64_t ntiles,
+                              const int64_t* __restrict__ newpos, int32_t chunk,
+                              int64_t* __restrict__ tile_base2, int64_t* __restrict__ tile_ncp,
+                              int64_t* __restrict__ tile_nch) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    tile_base2[t] = newpos[tile_base[t]];
+    if (t == ntiles) return;
+    int64_t ns = newpos[tile_base[t + 1]] - newpos[tile_base[t]];
+    tile_ncp[t] = (int64_t)TILE_PGS * ((ns + chunk - 1) / chunk + 1);
+    tile_nch[t] = (ns + chunk - 1) / chunk;
+}
+
+__global__ __launch_bounds__(256) void k_remap_entries(
+    int32_t npgx, int64_t npg, int32_t ntx, const int64_t* __restrict__ tile_base,
+    const int64_t* __restrict__ tile_base2, const int64_t* __restrict__ pg_base,
+    const uint32_t* __restrict__ pg_cnt, const int64_t* __restrict__ newpos,
+    uint32_t* __restrict__ ent_slot) {
+    int64_t pg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pg >= npg) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = pg_tile(pg, npgx, ntx);
+    const int64_t tb = tile_base[tile], tb2 = tile_base2[tile];
+    uint32_t* es = ent_slot + pg_base[pg];
+    for (uint32_t t = lane; t < pg_cnt[pg]; t += 64) {
+        uint32_t w = es[t];
+        uint32_t slot = (uint32_t)(newpos[tb + (w & SLOT_MASK)] - tb2);
+        es[t] = slot | (w & ~SLOT_MASK);
+    }
+}
+
+__global__ void k_compact_slots(const uint32_t* __restrict__ used,
+                                const int64_t* __restrict__ newpos, int64_t n,
+                                const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n && used[g]) dst[newpos[g]] = src[g];
+}
+
+
+
 // host-side ring band of a declination range [d0, d1] (radians) widened by r
 void ring_range(int64_t nside, double d0, double d1, double r, double eps, int32_t* lo,
                 int32_t* cnt) {
@@ -866,7 +927,13 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
 
     DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, wl;
+    DevBuf used, newpos, ctmp, tbase2, slot2;
     auto cleanup = [&]() {
+        dev_free(used);
+        dev_free(newpos);
+        dev_free(ctmp);
+        dev_free(tbase2);
+        dev_free(slot2);
         dev_free(wl);
         dev_free(tnch);
         dev_free(bcnt);
@@ -1038,7 +1105,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         return hipSuccess;
     }
     if (P.opts.device_mem_cap > 0) {
-        size_t need = (size_t)P.total_slots * 4 + (size_t)P.ent_cap * 20 + (size_t)P.chunk_ptrs * 4;
+        // slot list, entries, chunk pointers, and the slot compaction's
+        // transient arrays (flag, new position, compacted list: 16 B a slot)
+        size_t need = (size_t)P.total_slots * (4 + 16) + (size_t)P.ent_cap * 20 +
+                      (size_t)P.chunk_ptrs * 4;
         size_t have = 0;
         for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                           &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.cp_base, &P.pix_count, &P.pix_W,
@@ -1074,6 +1144,60 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (float4*)P.ent_w.p, (uint32_t*)P.pg_cnt.p, (int32_t*)P.pix_count.p,
                            (double*)P.pix_W.p, (float*)P.pix_Wf.p, nnz_total);
         HG_STEP(hipGetLastError());
+    }
+    // 5b: drop the slots no pixel of their tile uses, then recount chunks
+    if (P.total_slots > 0) {
+        const int64_t ts = P.total_slots;
+        HG_STEP(dev_alloc(used, (size_t)ts * 4));
+        HG_STEP(dev_alloc(newpos, (size_t)(ts + 1) * 8));
+        HG_STEP(dev_alloc(ctmp, (size_t)((ts + SCAN_B - 1) / SCAN_B + 1) * 8));
+        HG_STEP(dev_alloc(tbase2, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+        HG_STEP(dev_alloc(slot2, (size_t)ts * 4));
+        HG_STEP(hipMemsetAsync(used.p, 0, (size_t)ts * 4, s));
+        hipLaunchKernelGGL(k_mark_used, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
+                           P.ntx, (const int64_t*)P.tile_nslots.p, (const int64_t*)P.pg_base.p,
+                           (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
+                           (uint32_t*)used.p);
+        HG_STEP(hipGetLastError());
+        HG_STEP((scan_exclusive<uint32_t, int64_t>((const uint32_t*)used.p, ts,
+                                                   (int64_t*)newpos.p, (int64_t*)ctmp.p, s)));
+        hipLaunchKernelGGL(k_tile_rebase, dim3(blocks_for(P.ntiles + 1, 256)), dim3(256), 0, s,
+                           (const int64_t*)P.tile_nslots.p, P.ntiles, (const int64_t*)newpos.p,
+                           P.chunk, (int64_t*)tbase2.p, (int64_t*)tcp.p, (int64_t*)tnch.p);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_remap_entries, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx,
+                           P.npg, P.ntx, (const int64_t*)P.tile_nslots.p,
+                           (const int64_t*)tbase2.p, (const int64_t*)P.pg_base.p,
+                           (const uint32_t*)P.pg_cnt.p, (const int64_t*)newpos.p,
+                           (uint32_t*)P.ent_slot.p);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_compact_slots, dim3(blocks_for(ts, 256)), dim3(256), 0, s,
+                           (const uint32_t*)used.p, (const int64_t*)newpos.p, ts,
+                           (const uint32_t*)P.slot_idx.p, (uint32_t*)slot2.p);
+        HG_STEP(hipGetLastError());
+        std::swap(P.slot_idx, slot2);
+        HG_STEP(hipMemcpyAsync(P.tile_nslots.p, tbase2.p, sizeof(int64_t) * (size_t)(P.ntiles + 1),
+                               hipMemcpyDeviceToDevice, s));
+        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tnch.p, P.ntiles,
+                                                  (int64_t*)P.tile_blk.p, (int64_t*)scan_tmp, s)));
+        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tcp.p, P.ntiles,
+                                                  (int64_t*)P.cp_base.p, (int64_t*)scan_tmp, s)));
+        int64_t t3[3];
+        HG_STEP(hipMemcpyAsync(&t3[0], (int64_t*)tbase2.p + P.ntiles, 8, hipMemcpyDeviceToHost, s));
+        HG_STEP(hipMemcpyAsync(&t3[1], (int64_t*)P.tile_blk.p + P.ntiles, 8, hipMemcpyDeviceToHost,
+                               s));
+        HG_STEP(hipMemcpyAsync(&t3[2], (int64_t*)P.cp_base.p + P.ntiles, 8, hipMemcpyDeviceToHost,
+                               s));
+        HG_STEP(hipStreamSynchronize(s));
+        // the later buffers were sized for the counts before compaction, which bound these
+        P.total_slots = t3[0];
+        P.n_blocks = t3[1];
+        P.chunk_ptrs = t3[2];
+        dev_free(slot2);
+        dev_free(used);
+        dev_free(newpos);
+        dev_free(ctmp);
+        dev_free(tbase2);
     }
     hipLaunchKernelGGL(k_chunk_ptr, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
                        P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
