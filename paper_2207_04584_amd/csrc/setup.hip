@@ -417,6 +417,16 @@ __device__ inline float round_weight(float w, int32_t prec) {
     return w;
 }
 
+// Squared angular distance d^2 = (2 asin(sqrt h))^2 from the haversine h.  For
+// h < 1e-4 (d < 1.15 deg) the Maclaurin series of asin^2(x) in x^2 = h,
+// h (1 + h/3 + 8 h^2/45 + 4 h^3/35 + ...), cut after the h^3 term, is exact to
+// FP64 rounding (the next term is below 1e-17 relative); larger h takes asin.
+__device__ inline double dist2(double h) {
+    if (h < 1e-4) return 4.0 * h * (1.0 + h * (1.0 / 3.0 + h * (8.0 / 45.0 + h * (4.0 / 35.0))));
+    double d = 2.0 * asin(fmin(1.0, sqrt(h)));
+    return d * d;
+}
+
 // One wave per pixel group.  Lanes walk the group's candidates in slot order;
 // each lane tests its candidate against the group's (up to) four pixels with
 // the exact FP64 haversine test, and surviving candidates are compacted in
@@ -491,8 +501,7 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 double pc = (k >> 1) ? pcos1 : pcos0;
                 double h = sd * sd + pc * c.z * sa * sa;
                 if (ok && h <= h_r) {
-                    double d = 2.0 * asin(fmin(1.0, sqrt(h)));
-                    float wf = round_weight((float)exp(-(d * d) / two_s2), prec);
+                    float wf = round_weight((float)exp(-dist2(h) / two_s2), prec);
                     w[k] = wf;
                     mask |= 1u << k;
                     cnt[k] += 1;
@@ -774,6 +783,22 @@ __global__ __launch_bounds__(256) void k_block_meta(
     }
 }
 
+// Index of the group holding unit i of a block: the last l with po[l] <= i
+// (po: the block's 65 non-decreasing group offsets, po[64] > i).
+__device__ inline int group_of_unit(const uint16_t* po, int i) {
+    int lo = 0, hi = TILE_PGS - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if ((int)po[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// One wave per block: lane l knows group l's run (first entry, count); the
+// block's units are then copied flat, lane i taking unit i (coalesced writes).
 __global__ __launch_bounds__(256) void k_block_fill(
     int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks, int32_t chunk,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
@@ -783,14 +808,24 @@ __global__ __launch_bounds__(256) void k_block_fill(
     float4* __restrict__ e2_w, uint32_t* __restrict__ e2_s) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
-    if (b >= n_blocks) return;
+    if (b >= n_blocks) return;  // uniform per wave
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
-    int64_t dst = blk_base[b] + blk_pgoff[b * PGOFF_STRIDE + lane];
-    uint32_t s0 = (uint32_t)(r.c * chunk);
-    for (int t = 0; t < r.n; t++) {
-        e2_w[dst + t] = ent_w[r.src + t];
-        e2_s[dst + t] = (ent_slot[r.src + t] & SLOT_MASK) - s0;
+    const uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
+    const int64_t base = blk_base[b];
+    const int ne = (int)(blk_base[b + 1] - base);
+    const uint32_t s0 = (uint32_t)(r.c * chunk);
+    const uint32_t src_lo = (uint32_t)r.src, src_hi = (uint32_t)((uint64_t)r.src >> 32);
+    for (int i0 = 0; i0 < ne; i0 += 64) {  // same trip count on every lane
+        const int i = i0 + lane;
+        const int lp = i < ne ? group_of_unit(po, i) : 0;
+        const int64_t src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)src_hi, lp, 64) << 32) |
+                                      (uint32_t)__shfl((int)src_lo, lp, 64)) +
+                            (i - (int)po[lp]);
+        if (i < ne) {
+            e2_w[base + i] = ent_w[src];
+            e2_s[base + i] = (ent_slot[src] & SLOT_MASK) - s0;
+        }
     }
 }
 
@@ -855,30 +890,39 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
     uint16_t* __restrict__ e3_w, uint4* __restrict__ e3_s) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
-    if (b >= n_blocks) return;
+    if (b >= n_blocks) return;  // uniform per wave
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
-    int64_t dst = blk_base[b] + blk_pgoff[b * PGOFF_STRIDE + lane];
-    uint32_t s0 = (uint32_t)(r.c * chunk);
-    int ng = (r.n + 3) >> 2;
-    for (int t = 0; t < ng; t++) {
+    const uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
+    const int64_t base = blk_base[b];
+    const int ng_blk = (int)(blk_base[b + 1] - base);
+    const uint32_t s0 = (uint32_t)(r.c * chunk);
+    const uint32_t src_lo = (uint32_t)r.src, src_hi = (uint32_t)((uint64_t)r.src >> 32);
+    for (int i0 = 0; i0 < ng_blk; i0 += 64) {  // lane i: group of four entries i
+        const int i = i0 + lane;
+        const int lp = i < ng_blk ? group_of_unit(po, i) : 0;
+        const int64_t src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)src_hi, lp, 64) << 32) |
+                                      (uint32_t)__shfl((int)src_lo, lp, 64));
+        const int n = __shfl(r.n, lp, 64);
+        if (i >= ng_blk) continue;
+        const int t = i - (int)po[lp];  // group index within the run
         uint32_t sl[4];
         float w[4][4];  // [entry][pixel]
         for (int k = 0; k < 4; k++) {
             int e = 4 * t + k;
-            bool real = e < r.n;
-            int ee = real ? e : r.n - 1;
-            sl[k] = (ent_slot[r.src + ee] & SLOT_MASK) - s0;
-            float4 wv = ent_w[r.src + ee];
+            bool real = e < n;
+            int ee = real ? e : n - 1;
+            sl[k] = (ent_slot[src + ee] & SLOT_MASK) - s0;
+            float4 wv = ent_w[src + ee];
             w[k][0] = real ? wv.x : 0.f;
             w[k][1] = real ? wv.y : 0.f;
             w[k][2] = real ? wv.z : 0.f;
             w[k][3] = real ? wv.w : 0.f;
         }
-        e3_s[dst + t] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
-        uint16_t* wd = e3_w + (dst + t) * 16;
-        for (int i = 0; i < 4; i++)
-            for (int k = 0; k < 4; k++) wd[i * 4 + k] = weight_bits(w[k][i], prec);
+        e3_s[base + i] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
+        uint16_t* wd = e3_w + (base + i) * 16;
+        for (int q = 0; q < 4; q++)
+            for (int k = 0; k < 4; k++) wd[q * 4 + k] = weight_bits(w[k][q], prec);
     }
 }
 
