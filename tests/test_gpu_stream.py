@@ -88,13 +88,19 @@ def test_streamed_empty_field_and_no_channels():
 
 
 def test_streamed_ring_respects_memory_cap():
-    ra, dec, vals, m, k = field(C=64)
+    # the ring for 2000-channel blocks (two slots of 6000 x 2000 values and
+    # 2000 maps, about 120 MB) cannot fit a cap of three times the plan (setup
+    # itself needs some transient room beyond the plan)
+    ra, dec, vals, m, k = field(C=2000)
     with api.Plan(ra, dec, m, k) as p:
         plan_bytes = p.stats()["device_bytes"]
-    with api.Plan(ra, dec, m, k, device_mem_cap=plan_bytes + 4096) as p:
+    assert 3 * plan_bytes < 100e6
+    with api.Plan(ra, dec, m, k, device_mem_cap=3 * plan_bytes) as p:
         with pytest.raises(api.HegridError) as ei:
-            p.grid_host(vals, block=64)
+            p.grid_host(vals, block=2000)
         assert ei.value.status == api.HG_ERR_NOMEM
+        out, info = p.grid_host(vals[:, :8], block=8)  # a small ring still fits
+        assert info["blocks"] == 1
 
 
 def test_streamed_cube_against_reference():
