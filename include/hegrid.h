@@ -77,7 +77,11 @@ typedef struct {
     int32_t precision;      /* HG_PREC_*; 0 = HG_PREC_FP32.  A BF16 / FP16 plan
                                grids values of that type only                   */
     int32_t nside;          /* HEALPix resolution of the sky cells; 0 = auto    */
-    int32_t chunk;          /* tile slots staged per step: 0 (= 32), 8, 16, 24, 32 */
+    int32_t chunk;          /* tile slots staged per step, a multiple of 8 up to 64;
+                               0 = the longest that fits (48 for the FP32 form, 64 for
+                               the 16-bit forms, shorter for very dense fields).  An
+                               explicit chunk whose densest entry block would not fit
+                               two staged chunks in LDS fails (HG_ERR_UNSUPPORTED)  */
     int32_t reserved;       /* must be 0                                        */
     int64_t device_mem_cap; /* bytes; 0 = none.  Setup fails with HG_ERR_NOMEM
                                before any allocation beyond it                  */

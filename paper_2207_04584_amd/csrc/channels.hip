@@ -297,8 +297,9 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         pv[k] = tx * TILE_PGX + lxs[k] < npgx && ty * TILE_PGY + lys[k] < npgy;
     }
 
-    // Per chunk each wave stages two rows: (w, w+16) in the FP32 form and the
-    // adjacent pair (2w, 2w+1) in the 16-bit forms.  The chunk metadata (the
+    // Per chunk each wave stages up to four rows: w + 16 t in the FP32 form,
+    // the adjacent pairs (2w, 2w+1) and (2w+32, 2w+33) in the 16-bit forms
+    // (the rows that exist are always the first nrows of these).  The chunk metadata (the
     // rows' sample indices and the entry block's extent) reaches LDS through
     // the same asynchronous copies as the data, sixteen chunks at a time into
     // one half of a two-half ring, long before it is read; the loop issues no
@@ -308,9 +309,12 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     char* ring_rows = smem + nbuf * L.stride;
     char* ring_blk = ring_rows + META_ROWS;
     struct Meta {
-        uint32_t row0, row1;
+        uint32_t row0, row1, row2, row3;
         int nrows, ne;
         int64_t blk, eb;
+    };
+    auto row_slot = [&](int t) {
+        return FORM == FORM_F32 ? wave + CH_WAVES * t : 2 * wave + 32 * (t >> 1) + (t & 1);
     };
     auto rd64 = [&](const char* p) {
         uint32_t lo = __builtin_amdgcn_readfirstlane(*(const uint32_t*)p);
@@ -324,12 +328,12 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         const char* bb = ring_blk + (h * (META_RUN + 1) + j) * 8;
         int64_t s0 = ch * chunk;
         int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
-        int r0 = FORM == FORM_F32 ? wave : 2 * wave;
-        int r1 = FORM == FORM_F32 ? wave + CH_WAVES : 2 * wave + 1;
-        // chunk <= 32: at most two rows per wave
-        m.nrows = (r0 < ns) + (r1 < ns);
+        const int r0 = row_slot(0), r1 = row_slot(1), r2 = row_slot(2), r3 = row_slot(3);
+        m.nrows = (r0 < ns) + (r1 < ns) + (r2 < ns) + (r3 < ns);  // chunk <= 64
         m.row0 = r0 < ns ? __builtin_amdgcn_readfirstlane(rr[r0]) : 0u;
         m.row1 = r1 < ns ? __builtin_amdgcn_readfirstlane(rr[r1]) : 0u;
+        m.row2 = r2 < ns ? __builtin_amdgcn_readfirstlane(rr[r2]) : 0u;
+        m.row3 = r3 < ns ? __builtin_amdgcn_readfirstlane(rr[r3]) : 0u;
         m.blk = blk0 + ch;
         m.eb = rd64(bb);
         m.ne = (int)(rd64(bb + 8) - m.eb);
@@ -361,11 +365,17 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         char* base = smem + buf * L.stride;
         if (FORM == FORM_F32) {
             if (m.nrows > 0)
-                stage_row_f32<DT, VEC>(base + L.vals + wave * F::RB, values, ld, nchan, c_lo,
-                                       m.row0, lane, dma_rows);
+                stage_row_f32<DT, VEC>(base + L.vals + row_slot(0) * F::RB, values, ld, nchan,
+                                       c_lo, m.row0, lane, dma_rows);
             if (m.nrows > 1)
-                stage_row_f32<DT, VEC>(base + L.vals + (wave + CH_WAVES) * F::RB, values, ld,
-                                       nchan, c_lo, m.row1, lane, dma_rows);
+                stage_row_f32<DT, VEC>(base + L.vals + row_slot(1) * F::RB, values, ld, nchan,
+                                       c_lo, m.row1, lane, dma_rows);
+            if (m.nrows > 2)
+                stage_row_f32<DT, VEC>(base + L.vals + row_slot(2) * F::RB, values, ld, nchan,
+                                       c_lo, m.row2, lane, dma_rows);
+            if (m.nrows > 3)
+                stage_row_f32<DT, VEC>(base + L.vals + row_slot(3) * F::RB, values, ld, nchan,
+                                       c_lo, m.row3, lane, dma_rows);
             const float4* w = (const float4*)ent_w + m.eb;
             const uint32_t* sl = (const uint32_t*)ent_s + m.eb;
             for (int i = wave * 64; i < m.ne; i += CH_THREADS) {
@@ -376,8 +386,11 @@ __device__ __attribute__((always_inline)) inline void grid_item(
             }
         } else {
             if (m.nrows > 0)
-                stage_rows_16<VEC>(base + L.vals + 2 * wave * F::RB, values, ld, nchan, c_lo,
-                                   m.row0, m.row1, m.nrows, lane, dma_rows);
+                stage_rows_16<VEC>(base + L.vals + row_slot(0) * F::RB, values, ld, nchan, c_lo,
+                                   m.row0, m.row1, m.nrows < 2 ? m.nrows : 2, lane, dma_rows);
+            if (m.nrows > 2)
+                stage_rows_16<VEC>(base + L.vals + row_slot(2) * F::RB, values, ld, nchan, c_lo,
+                                   m.row2, m.row3, m.nrows - 2, lane, dma_rows);
             // a group's weights are 32 bytes (two lanes), its slots 16 bytes (one lane)
             const char* w = (const char*)ent_w + m.eb * 32;
             for (int i = wave * 32; i < m.ne; i += CH_WAVES * 32)
@@ -746,6 +759,12 @@ hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t ncha
                    : launch_typed<FORM_F32, HG_BF16, false>(d, P.ntiles, s);
     return vec ? launch_typed<FORM_F32, HG_F16, true>(d, P.ntiles, s)
                : launch_typed<FORM_F32, HG_F16, false>(d, P.ntiles, s);
+}
+
+bool channel_lds_fits(bool m16, int chunk, int blk_max) {
+    int32_t ucap, nbuf;
+    lds_plan(m16, chunk, blk_max, ucap, nbuf);
+    return (size_t)2 * lds_stride(m16, chunk, ucap) + META_LDS <= (size_t)LDS_BYTES;
 }
 
 size_t field_lds_bytes(const FieldDesc& d, bool m16) {

@@ -27,7 +27,7 @@ constexpr int TILE_PGS = TILE_PGX * TILE_PGY;
 constexpr uint32_t SLOT_MASK = 0x0FFFFFFFu;  // low 28 bits: tile-local slot
 constexpr int SLOT_SHIFT = 28;               // high 4 bits: in-support mask
 constexpr int PGOFF_STRIDE = 68;             // uint16 per block: 65 offsets, padded to 136 B
-constexpr int MAX_CHUNK = 32;                // tile slots per staged chunk, upper bound
+constexpr int MAX_CHUNK = 64;                // tile slots per staged chunk, upper bound
 
 // ---------------------------------------------------------------------------
 // HEALPix RING scheme (Gorski et al. 2005; the partition used by the paper's
@@ -257,6 +257,7 @@ FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t ncha
 bool values_vec(const Plan& P, const void* values, int64_t ld, int32_t dtype);
 BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm);
 size_t field_lds_bytes(const FieldDesc& d, bool m16);
+bool channel_lds_fits(bool m16, int chunk, int blk_max);
 hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
                           int64_t* pix, hipStream_t s);
 

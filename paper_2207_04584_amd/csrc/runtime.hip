@@ -219,7 +219,7 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
         if (o->nside < 0 || o->nside > 16384 || (o->nside & (o->nside - 1)))
             return fail(HG_ERR_ARG, "nside must be 0 or a power of two <= 16384");
         if (o->chunk != 0 && (o->chunk < 8 || o->chunk > MAX_CHUNK || o->chunk % 8))
-            return fail(HG_ERR_ARG, "chunk must be 0 or a multiple of 8 in [8, 32]");
+            return fail(HG_ERR_ARG, "chunk must be 0 or a multiple of 8 in [8, 64]");
         if (o->device_mem_cap < 0) return fail(HG_ERR_ARG, "device_mem_cap must be >= 0");
         if (o->reserved || o->reserved2) return fail(HG_ERR_ARG, "reserved fields must be 0");
     }
@@ -241,7 +241,6 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     P.r_rad = k->support_deg * kDeg;
     double sh = sin(0.5 * P.r_rad);
     P.h_r = sh * sh;
-    P.chunk = (o && o->chunk) ? o->chunk : MAX_CHUNK;
     P.npix = (int64_t)m->nx * m->ny;
     P.npgx = (m->nx + PG - 1) / PG;
     P.npgy = (m->ny + PG - 1) / PG;
@@ -255,18 +254,41 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
         delete h;
         return fail(HG_ERR_UNSUPPORTED, "nside too fine for this field (over 2^28 cells)");
     }
-    std::string err;
-    int status = HG_OK;
-    hipError_t e = launch_setup(P, ra_deg, dec_deg, s, err, status);
-    if (e != hipSuccess) {
+    // Chunk length: the caller's, or the longest of a list that still fits two
+    // staged chunks of the plan's densest entry block in LDS (longer chunks
+    // mean fewer synchronisations per tile; the fit is known only once the
+    // blocks are built, so a plan that does not fit is rebuilt shorter).
+    const bool m16 = P.opts.precision != HG_PREC_FP32;
+    std::vector<int32_t> chunks;
+    if (o && o->chunk)
+        chunks = {o->chunk};
+    else if (m16)
+        chunks = {64, 48, 32, 16, 8};
+    else
+        chunks = {48, 32, 16, 8};
+    for (size_t ci = 0; ci < chunks.size(); ci++) {
+        P.chunk = chunks[ci];
+        std::string err;
+        int status = HG_OK;
+        hipError_t e = launch_setup(P, ra_deg, dec_deg, s, err, status);
+        if (e != hipSuccess) {
+            plan_free(P);
+            delete h;
+            return fail_hip(e, "grid_setup");
+        }
+        if (status != HG_OK) {
+            plan_free(P);
+            delete h;
+            return fail(status, err);
+        }
+        if (channel_lds_fits(m16, P.chunk, P.blk_max)) break;
         plan_free(P);
-        delete h;
-        return fail_hip(e, "grid_setup");
-    }
-    if (status != HG_OK) {
-        plan_free(P);
-        delete h;
-        return fail(status, err);
+        if (ci + 1 == chunks.size()) {
+            delete h;
+            return fail(HG_ERR_UNSUPPORTED,
+                        "the densest entry block does not fit two staged chunks in LDS; use a "
+                        "smaller chunk");
+        }
     }
     P.setup_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
