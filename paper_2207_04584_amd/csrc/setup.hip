@@ -427,6 +427,21 @@ __device__ inline double dist2(double h) {
     return d * d;
 }
 
+// sin x for the half-angle differences of the haversine.  Below 2^-7 rad the
+// Maclaurin polynomial x - x^3/3! + x^5/5! - x^7/7! is within an ulp of sin x
+// (the first dropped term, x^9/9!, is below 4e-23 |x|), at a few FMAs instead
+// of a full range-reduced sin; larger arguments (wide supports, the RA wrap,
+// fields near a pole) call sin.
+__device__ inline double sin_half(double x) {
+    if (fabs(x) < 0.0078125) {
+        const double x2 = x * x;
+        double p = fma(x2, -1.0 / 5040.0, 1.0 / 120.0);
+        p = fma(p, x2, -1.0 / 6.0);
+        return fma(x * x2, p, x);
+    }
+    return sin(x);
+}
+
 // One wave per pixel group.  Lanes walk the group's candidates in slot order;
 // each lane tests its candidate against the group's (up to) four pixels with
 // the exact FP64 haversine test, and surviving candidates are compacted in
@@ -491,8 +506,8 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
             int off = v - pref[lo];
             double4 c = srt_coord[ppos[lo] + off];
             slot = (uint32_t)(pslot[lo] + off);
-            double sd0 = sin(0.5 * (c.y - pdec0)), sd1 = sin(0.5 * (c.y - pdec1));
-            double sa0 = sin(0.5 * (c.x - pra0)), sa1 = sin(0.5 * (c.x - pra1));
+            double sd0 = sin_half(0.5 * (c.y - pdec0)), sd1 = sin_half(0.5 * (c.y - pdec1));
+            double sa0 = sin_half(0.5 * (c.x - pra0)), sa1 = sin_half(0.5 * (c.x - pra1));
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 bool ok = ((k & 1) == 0 || vx1) && ((k >> 1) == 0 || vy1);
