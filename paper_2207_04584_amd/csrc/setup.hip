@@ -421,8 +421,12 @@ __device__ inline float round_weight(float w, int32_t prec) {
 // h < 1e-4 (d < 1.15 deg) the Maclaurin series of asin^2(x) in x^2 = h,
 // h (1 + h/3 + 8 h^2/45 + 4 h^3/35 + ...), cut after the h^3 term, is exact to
 // FP64 rounding (the next term is below 1e-17 relative); larger h takes asin.
+// SMALL: the caller knows h < 1e-4 (supports below 1.15 deg), so the asin
+// branch, which costs registers in every inlined copy, is left out.
+template <bool SMALL>
 __device__ inline double dist2(double h) {
-    if (h < 1e-4) return 4.0 * h * (1.0 + h * (1.0 / 3.0 + h * (8.0 / 45.0 + h * (4.0 / 35.0))));
+    if (SMALL || h < 1e-4)
+        return 4.0 * h * (1.0 + h * (1.0 / 3.0 + h * (8.0 / 45.0 + h * (4.0 / 35.0))));
     double d = 2.0 * asin(fmin(1.0, sqrt(h)));
     return d * d;
 }
@@ -432,14 +436,43 @@ __device__ inline double dist2(double h) {
 // (the first dropped term, x^9/9!, is below 4e-23 |x|), at a few FMAs instead
 // of a full range-reduced sin; larger arguments (wide supports, the RA wrap,
 // fields near a pole) call sin.
-__device__ inline double sin_half(double x) {
-    if (fabs(x) < 0.0078125) {
-        const double x2 = x * x;
-        double p = fma(x2, -1.0 / 5040.0, 1.0 / 120.0);
-        p = fma(p, x2, -1.0 / 6.0);
-        return fma(x * x2, p, x);
+__device__ inline double sin_poly(double x) {
+    const double x2 = x * x;
+    double p = fma(x2, -1.0 / 5040.0, 1.0 / 120.0);
+    p = fma(p, x2, -1.0 / 6.0);
+    return fma(x * x2, p, x);
+}
+constexpr double SIN_POLY_MAX = 0.0078125;  // 2^-7
+
+// Out of line: sin's full range reduction would otherwise hold its registers
+// across the whole candidate loop, though arguments past 2^-7 are rare.
+__device__ __attribute__((noinline)) double sin_wide(double x) { return sin(x); }
+
+// The four half-angle sines of a candidate against a pixel group: (dec - dec0,
+// dec - dec1, ra - ra0, ra - ra1) / 2.  Arguments past the polynomial's range
+// go through one shared call of sin, rotated into place, so that the kernel
+// carries a single inlined copy of it.
+__device__ inline void half_sines(double a0, double a1, double a2, double a3, double& s0,
+                                  double& s1, double& s2, double& s3) {
+    s0 = sin_poly(a0);
+    s1 = sin_poly(a1);
+    s2 = sin_poly(a2);
+    s3 = sin_poly(a3);
+    const bool big = fabs(a0) >= SIN_POLY_MAX || fabs(a1) >= SIN_POLY_MAX ||
+                     fabs(a2) >= SIN_POLY_MAX || fabs(a3) >= SIN_POLY_MAX;
+    if (big) {
+#pragma unroll 1
+        for (int k = 0; k < 4; k++) {
+            const double r = fabs(a0) >= SIN_POLY_MAX ? sin_wide(a0) : s0;
+            a0 = a1;
+            a1 = a2;
+            a2 = a3;
+            s0 = s1;
+            s1 = s2;
+            s2 = s3;
+            s3 = r;
+        }
     }
-    return sin(x);
 }
 
 // One wave per pixel group.  Lanes walk the group's candidates in slot order;
@@ -448,10 +481,11 @@ __device__ inline double sin_half(double x) {
 // order into the group's entry list with their four FP32 weights.
 constexpr int GATHER_WAVES = 4;
 
+template <bool SMALL>
 __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     const int4* __restrict__ pg_piece, int32_t pg_rings, const int64_t* __restrict__ pg_base,
     const double4* __restrict__ srt_coord, int32_t npgx, int64_t npg, hg_map m, double h_r,
-    double two_s2, int32_t prec, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
+    double inv_two_s2, int32_t prec, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
     uint32_t* __restrict__ pg_cnt, int32_t* __restrict__ pix_count, double* __restrict__ pix_W,
     float* __restrict__ pix_Wf, unsigned long long* __restrict__ nnz_total) {
     extern __shared__ int sh_gather[];
@@ -488,6 +522,7 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     double wsum[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t base_out = pg_base[pg];
     int written = 0;
+    int lo = 0;  // the piece holding candidate v; v only grows, so lo only advances
     for (int v0 = 0; v0 < total; v0 += 64) {
         int v = v0 + lane;
         bool active = v < total;
@@ -495,33 +530,45 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
         float w[4] = {0.f, 0.f, 0.f, 0.f};
         uint32_t slot = 0;
         if (active) {
-            int lo = 0, hi = npc - 1;  // last piece with pref <= v
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (pref[mid] <= v)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
+            while (pref[lo + 1] <= v) lo++;  // stops by pref[npc] = total > v
             int off = v - pref[lo];
             double4 c = srt_coord[ppos[lo] + off];
             slot = (uint32_t)(pslot[lo] + off);
-            double sd0 = sin_half(0.5 * (c.y - pdec0)), sd1 = sin_half(0.5 * (c.y - pdec1));
-            double sa0 = sin_half(0.5 * (c.x - pra0)), sa1 = sin_half(0.5 * (c.x - pra1));
+            double sd0, sd1, sa0, sa1;
+            half_sines(0.5 * (c.y - pdec0), 0.5 * (c.y - pdec1), 0.5 * (c.x - pra0),
+                       0.5 * (c.x - pra1), sd0, sd1, sa0, sa1);
+            double hk[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 bool ok = ((k & 1) == 0 || vx1) && ((k >> 1) == 0 || vy1);
                 double sd = (k >> 1) ? sd1 : sd0;
                 double sa = (k & 1) ? sa1 : sa0;
                 double pc = (k >> 1) ? pcos1 : pcos0;
-                double h = sd * sd + pc * c.z * sa * sa;
-                if (ok && h <= h_r) {
-                    float wf = round_weight((float)exp(-dist2(h) / two_s2), prec);
-                    w[k] = wf;
-                    mask |= 1u << k;
-                    cnt[k] += 1;
-                    wsum[k] += (double)wf;
-                }
+                hk[k] = sd * sd + pc * c.z * sa * sa;
+                if (ok && hk[k] <= h_r) mask |= 1u << k;
+            }
+            // One exp per pass with the pixels rotated through the first
+            // place, so the kernel holds one inlined copy of exp rather than
+            // four (which cost a third of the occupancy in registers).
+            double h0 = hk[0], h1 = hk[1], h2 = hk[2], h3 = hk[3];
+            uint32_t mk = mask;
+#pragma unroll 1
+            for (int k = 0; k < 4; k++) {
+                float wf = 0.f;
+                if (mk & 1u) wf = round_weight((float)exp(-dist2<SMALL>(h0) * inv_two_s2), prec);
+                h0 = h1;
+                h1 = h2;
+                h2 = h3;
+                w[0] = w[1];
+                w[1] = w[2];
+                w[2] = w[3];
+                w[3] = wf;
+                mk >>= 1;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                cnt[k] += (mask >> k) & 1u;
+                wsum[k] += (double)w[k];
             }
         }
         bool keep = active && mask != 0;
@@ -1195,11 +1242,13 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(hipGetLastError());
     {
         size_t shm = (size_t)GATHER_WAVES * 3 * (npc_p + 1) * sizeof(int);
-        double two_s2 = 2.0 * P.sigma * P.sigma;
-        hipLaunchKernelGGL(k_gather, dim3(blocks_for(P.npg, GATHER_WAVES)), dim3(64 * GATHER_WAVES),
+        const double inv_two_s2 = 1.0 / (2.0 * P.sigma * P.sigma);
+        // every in-support h is at most h_r; below 1e-4 no asin is needed
+        auto kern = P.h_r < 1e-4 ? k_gather<true> : k_gather<false>;
+        hipLaunchKernelGGL(kern, dim3(blocks_for(P.npg, GATHER_WAVES)), dim3(64 * GATHER_WAVES),
                            shm, s, (const int4*)P.pg_piece.p, P.pg_rings,
                            (const int64_t*)P.pg_base.p, (const double4*)P.srt_coord.p, P.npgx,
-                           P.npg, P.map, P.h_r, two_s2, P.opts.precision, (uint32_t*)P.ent_slot.p,
+                           P.npg, P.map, P.h_r, inv_two_s2, P.opts.precision, (uint32_t*)P.ent_slot.p,
                            (float4*)P.ent_w.p, (uint32_t*)P.pg_cnt.p, (int32_t*)P.pix_count.p,
                            (double*)P.pix_W.p, (float*)P.pix_Wf.p, nnz_total);
         HG_STEP(hipGetLastError());
