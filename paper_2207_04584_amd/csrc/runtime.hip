@@ -2,12 +2,14 @@
 // validation, plan construction (geometry and kernel constants), a caching
 // device allocator, channel-kernel timing and the parity exports.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <exception>
 #include <map>
 #include <mutex>
 #include <new>
+#include <thread>
 
 #include "hg_common.h"
 
@@ -296,6 +298,20 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     return HG_OK;
 }
 
+// Runs f, turning exceptions into error codes.
+template <typename F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return fail(HG_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(HG_ERR_INTERNAL, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return fail(HG_ERR_INTERNAL, "internal error");
+    }
+}
+
 void batch_free(hg_batch* b) {
     (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();
@@ -312,10 +328,98 @@ void batch_free(hg_batch* b) {
     dev_free(b->descs);
     dev_free(b->items);
     for (hg_plan* h : b->plans) {
+        if (!h) continue;  // a field whose setup failed
         plan_free(h->P);
         delete h;
     }
     delete b;
+}
+
+// Every field's setup, on SETUP_THREADS host threads with a stream each, so
+// that one field's short kernels and read-backs overlap another's work; the
+// largest fields go first.  The streams start after the work already queued
+// on the caller's stream s (which may be writing the coordinates).  On
+// success b->plans holds the plans in field order and tile_blk[i] each
+// field's first-block table; on failure b is freed and the lowest failing
+// field's error is set.
+constexpr int SETUP_THREADS = 4;
+
+int setup_fields(hg_batch* b, const hg_field* fields, int32_t nfields, const hg_opts& po,
+                 hipStream_t s, std::vector<std::vector<int64_t>>& tile_blk) {
+    std::vector<hg_plan*> plans((size_t)nfields, nullptr);
+    std::vector<int> rcs((size_t)nfields, HG_OK);
+    std::vector<std::string> errs((size_t)nfields);
+    std::vector<int32_t> order((size_t)nfields);
+    for (int32_t i = 0; i < nfields; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t c) { return fields[a].n > fields[c].n; });
+    hipEvent_t ready = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ready, s);
+    if (e != hipSuccess) {
+        if (ready) (void)hipEventDestroy(ready);
+        batch_free(b);
+        return fail_hip(e, "batch_create");
+    }
+    const int dev = b->device;
+    std::atomic<int32_t> next{0};
+    auto work = [&]() {
+        hipStream_t ws = nullptr;
+        const bool ok = hipSetDevice(dev) == hipSuccess &&
+                        hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) == hipSuccess &&
+                        hipStreamWaitEvent(ws, ready, 0) == hipSuccess;
+        for (;;) {
+            const int32_t j = next.fetch_add(1);
+            if (j >= nfields) break;
+            const int32_t i = order[j];
+            if (!ok) {
+                rcs[i] = HG_ERR_DEVICE;
+                errs[i] = "could not create a setup stream";
+                continue;
+            }
+            const hg_field& f = fields[i];
+            const int r = guarded([&]() -> int {
+                hg_plan* h = nullptr;
+                int r2 = make_plan(f.ra_deg, f.dec_deg, f.n, &f.kernel, &f.map, &po, ws, &h);
+                if (r2) return r2;
+                plans[i] = h;
+                h->owned_by_batch = true;
+                std::vector<int64_t> tb((size_t)h->P.ntiles + 1);
+                hipError_t e2 = hipMemcpyAsync(tb.data(), h->P.tile_blk.p, 8 * tb.size(),
+                                               hipMemcpyDeviceToHost, ws);
+                if (e2 == hipSuccess) e2 = hipStreamSynchronize(ws);
+                if (e2 != hipSuccess) return fail_hip(e2, "batch_create");
+                tile_blk[i] = std::move(tb);
+                return HG_OK;
+            });
+            if (r) {
+                rcs[i] = r;
+                errs[i] = g_err;
+            }
+        }
+        if (ws) {
+            (void)hipStreamSynchronize(ws);
+            (void)hipStreamDestroy(ws);
+        }
+    };
+    std::vector<std::thread> pool;
+    try {
+        for (int t = 1; t < std::min<int32_t>(nfields, SETUP_THREADS); t++) pool.emplace_back(work);
+    } catch (...) {
+        // fewer threads than asked for: the ones running (and this one) share the fields
+    }
+    work();
+    for (auto& t : pool) t.join();
+    (void)hipEventDestroy(ready);
+    for (int32_t i = 0; i < nfields; i++) b->plans.push_back(plans[i]);
+    for (int32_t i = 0; i < nfields; i++) {
+        if (rcs[i] != HG_OK) {
+            std::string msg = "field " + std::to_string(i) + ": " + errs[i];
+            batch_free(b);
+            return fail(rcs[i], msg);
+        }
+    }
+    return HG_OK;
 }
 
 hipError_t resolve_batch_timing(hg_batch* b) {
@@ -374,19 +478,6 @@ std::vector<BatchItem> plan_batch_items(const std::vector<std::vector<int64_t>>&
     for (int x = 0; x < NX; x++)
         for (size_t i = 0; i < lists[x].size(); i++) pos[i * NX + x] = lists[x][i];
     return pos;
-}
-
-template <typename F>
-int guarded(F&& f) {
-    try {
-        return f();
-    } catch (const std::bad_alloc&) {
-        return fail(HG_ERR_NOMEM, "host allocation failed");
-    } catch (const std::exception& e) {
-        return fail(HG_ERR_INTERNAL, std::string("internal error: ") + e.what());
-    } catch (...) {
-        return fail(HG_ERR_INTERNAL, "internal error");
-    }
 }
 
 }  // namespace
@@ -649,32 +740,18 @@ int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, cons
         hg_opts po = b->opts;
         po.flags &= ~HG_FLAG_TIME_CHANNELS;
         hipStream_t s = (hipStream_t)hip_stream;
+        std::vector<std::vector<int64_t>> tile_blk(nfields);
+        rc = setup_fields(b, fields, nfields, po, s, tile_blk);
+        if (rc) return rc;  // b freed, error set
         std::vector<FieldDesc> descs;
-        std::vector<std::vector<int64_t>> tile_blk;
         std::vector<int32_t> ncb;
         bool vec = true;
         for (int32_t i = 0; i < nfields; i++) {
             const hg_field& f = fields[i];
-            hg_plan* h = nullptr;
-            rc = make_plan(f.ra_deg, f.dec_deg, f.n, &f.kernel, &f.map, &po, s, &h);
-            if (rc) {
-                std::string msg = "field " + std::to_string(i) + ": " + g_err;
-                batch_free(b);
-                return fail(rc, msg);
-            }
-            h->owned_by_batch = true;
-            b->plans.push_back(h);
-            const Plan& P = h->P;
+            const Plan& P = b->plans[i]->P;
             descs.push_back(field_desc(P, f.values, f.ld, f.nchan, f.out));
             ncb.push_back(descs.back().ncb);
             if (f.nchan > 0 && f.n > 0) vec = vec && values_vec(P, f.values, f.ld, dtype);
-            std::vector<int64_t> tb((size_t)P.ntiles + 1);
-            hipError_t e = hipMemcpy(tb.data(), P.tile_blk.p, 8 * tb.size(), hipMemcpyDeviceToHost);
-            if (e != hipSuccess) {
-                batch_free(b);
-                return fail_hip(e, "batch_create");
-            }
-            tile_blk.push_back(std::move(tb));
         }
         std::vector<BatchItem> pos = plan_batch_items(tile_blk, ncb, b->n_items);
         b->n_positions = (int64_t)pos.size();

@@ -982,9 +982,17 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
             w[k][3] = real ? wv.w : 0.f;
         }
         e3_s[base + i] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
-        uint16_t* wd = e3_w + (base + i) * 16;
-        for (int q = 0; q < 4; q++)
-            for (int k = 0; k < 4; k++) wd[q * 4 + k] = weight_bits(w[k][q], prec);
+        // [pixel q][entry k] halves, packed in pairs: two 16-byte stores per lane
+        uint32_t wb[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int q = j >> 1, k = 2 * (j & 1);
+            wb[j] = (uint32_t)weight_bits(w[k][q], prec) |
+                    ((uint32_t)weight_bits(w[k + 1][q], prec) << 16);
+        }
+        uint4* wd = (uint4*)(e3_w + (base + i) * 16);
+        wd[0] = make_uint4(wb[0], wb[1], wb[2], wb[3]);
+        wd[1] = make_uint4(wb[4], wb[5], wb[6], wb[7]);
     }
 }
 
@@ -1034,7 +1042,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
 
     DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, wl;
     DevBuf used, newpos, ctmp, tbase2, slot2;
+    // Buffers go back to the allocation cache, where a setup on another
+    // stream may take them at once: the stream's work is drained first.
     auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
         dev_free(used);
         dev_free(newpos);
         dev_free(ctmp);
