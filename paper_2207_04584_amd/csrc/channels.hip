@@ -285,14 +285,18 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     const int64_t nch = tile_blk[tile + 1] - blk0;
     const uint32_t* sidx = slot_idx + s_base;
 
-    // Wave w owns the groups whose (x mod 4, y mod 4) is (w mod 4, w / 4): a
-    // chunk's samples are spatially compact, so this spreads each chunk's
-    // entries evenly over the 16 waves.
+    // Wave w owns the four groups of one (x mod 4, y mod 4) class: a chunk's
+    // samples are spatially compact, so this spreads each chunk's entries
+    // over the 16 waves.  The class of wave w is y mod 4 = w / 4, x mod 4 =
+    // (w - w / 4) mod 4, so the four waves that share a SIMD (w mod 4 equal)
+    // own a diagonal of classes, one in every row and column: the chunk's
+    // matrix work then splits more evenly over the SIMDs than with the
+    // classes of one column per SIMD.
     bool pv[PGW];
     int lxs[PGW], lys[PGW];
 #pragma unroll
     for (int k = 0; k < PGW; k++) {
-        lxs[k] = (wave & 3) + 4 * (k & 1);
+        lxs[k] = ((wave - (wave >> 2)) & 3) + 4 * (k & 1);
         lys[k] = (wave >> 2) + 4 * (k >> 1);
         pv[k] = tx * TILE_PGX + lxs[k] < npgx && ty * TILE_PGY + lys[k] < npgy;
     }
