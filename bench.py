@@ -284,7 +284,7 @@ def run_batch(args):
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline_batch(fs, vals_dev, nnz_f, args.cpu_pixels // 10)
+        res["cpu_baseline"] = cpu_baseline_batch(fs, vals_dev, nnz_f, 2 * args.cpu_pixels)
         log(f"cpu baseline: {res['cpu_baseline']['sample']}")
     return res
 
@@ -299,7 +299,7 @@ def main():
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=3000)
+    ap.add_argument("--cpu-pixels", type=int, default=4500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain elementwise pass over 1 GiB (read 1 GiB, write "
                          "1 GiB) so that hardware byte counters can be scaled against it")
