@@ -205,7 +205,27 @@ def config(name):
         ra, dec = ra[:1_000_000], dec[:1_000_000]
         return _field((5,), ra, dec, make_map(180.0, 30.0, 600, 600), make_kernel(3.0),
                       "spectral", 200, 1.0, (180.0, 30.0, 10.0, 10.0), 65536, "bf16")
+    if name == "paper":
+        return paper_field()
     raise KeyError(name)
+
+
+def paper_field(n=19_000_000, width=60.0, height=20.0, ra0=30.0, dec0=41.0, nchan=50):
+    """Stand-in for the paper's simulated set (Table 2 of Sec. 5.1.2): a
+    60 x 20 deg map centred on (30, 41) deg, a 180 arcsec beam, 1.5e7 to
+    1.9e7 samples and 50 channels, here from repeated drifts of a 19-beam
+    receiver (as cfg5) at 1 arcmin pixels (a third of the beam).  Smaller
+    ``width``/``height``/``n`` give the same recipe on a sub-field: the
+    samples per track and the track spacing follow from n and height."""
+    rng = _rng(6, 0)
+    decs = hex19_track_decs(rng, dec0, height)
+    per = int(math.ceil(n / decs.shape[0]))
+    ra, dec = drift_scan_coords(rng, decs.shape[0], per, ra0, dec0, width, height,
+                                line_decs=decs)
+    ra, dec = np.mod(ra[:n], 360.0), dec[:n]
+    nx, ny = int(round(width * 60.0)), int(round(height * 60.0))
+    return _field((6,), ra, dec, make_map(ra0, dec0, nx, ny), make_kernel(3.0), "spectral", 20,
+                  1.0, (ra0, dec0, width, height), nchan, "f32")
 
 
 def batch_fields(n_fields=64, scale=1.0):
