@@ -20,7 +20,11 @@ FP32 channels), end to end from page-locked host memory: one step =
 coordinates to the GPU + setup + channels streamed in and the cube streamed
 back + finish.
 
-    python bench.py [--workload drift|batch|paper] [--steps K] [--warmup W] [--gpus 1]
+--workload literal: the drift workload through Algorithm 1 as the paper
+states it (one launch per channel, gamma cells per thread, FP64), the
+comparison path.
+
+    python bench.py [--workload drift|batch|paper|literal] [--steps K] [--warmup W] [--gpus 1]
                     [--precision mfma|fp32] [--no-cpu-baseline]
 
 Prints one JSON line.  value = sum(N * C) / (seconds per step) in G
@@ -295,6 +299,74 @@ def run_batch(args):
     return res
 
 
+def run_literal(args):
+    """Survey row f2: the drift workload through Algorithm 1 as the paper
+    states it (hg_grid_channels_literal: one launch per channel, gamma cells
+    per thread), to set the tiled matrix-core path against.  A sweep over
+    gamma and workgroup size on 16 channels picks the configuration the
+    timed steps (setup + all 1024 channels + finish) use."""
+    import numpy as np
+    import torch
+
+    from paper_2207_04584_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    f = synth.config("cfg2")
+    C = f["nchan"]
+    n = f["ra"].shape[0]
+    m, k = f["map"], f["kernel"]
+    ra = torch.from_numpy(f["ra"]).to(dev)
+    dec = torch.from_numpy(f["dec"]).to(dev)
+    vals = synth.sky_values(f, C, device=dev)
+    out = torch.empty((C, m["ny"], m["nx"]), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    sweep = {}
+    with api.Plan(ra, dec, m, k) as p:
+        sub = vals[:, :16]
+        for gamma in (1, 2, 4):
+            for block in (64, 128, 256, 512):
+                p.grid_literal(sub, out=out[:16], gamma=gamma, block=block)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                p.grid_literal(sub, out=out[:16], gamma=gamma, block=block)
+                torch.cuda.synchronize()
+                sweep[f"gamma{gamma}_block{block}"] = (time.perf_counter() - t0) * 1e3 / 16
+                log(f"literal sweep: gamma {gamma}, block {block}: "
+                    f"{sweep[f'gamma{gamma}_block{block}']:.3f} ms per channel")
+    best = min(sweep, key=sweep.get)
+    gamma, block = (int(x) for x in best.replace("gamma", "").split("_block"))
+    setup_ms = []
+
+    def step():
+        plan = api.Plan(ra, dec, m, k)
+        plan.grid_literal(vals, out=out, gamma=gamma, block=block)
+        torch.cuda.synchronize()
+        setup_ms.append(plan.stats()["setup_ms"])
+        plan.close()
+
+    for _ in range(args.warmup):
+        step()
+    setup_ms.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.1f} ms/step with gamma {gamma}, block {block}")
+    return {
+        "metric": "G sample*channel updates/s (Algorithm 1 as stated, FP64)",
+        "value": n * C / (ms_step * 1e-3) / 1e9, "unit": "G sample*channel updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "drift-scan field as the default workload (1e6 samples, 300x300, "
+                               "1024 FP32 channels); step = setup + Algorithm 1 per channel",
+                   "gamma": gamma, "block": block},
+        "setup_ms": float(np.mean(setup_ms)), "sweep_ms_per_channel": sweep,
+    }
+
+
 def run_paper(args):
     """End to end from host memory on the paper-scale stand-in (its simulated
     set, Table 2 of Sec. 5.1.2): coordinates and values start in page-locked
@@ -385,7 +457,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["drift", "batch", "paper"], default="drift")
+    ap.add_argument("--workload", choices=["drift", "batch", "paper", "literal"],
+                    default="drift")
     ap.add_argument("--paper-samples", type=int, default=19_000_000)
     ap.add_argument("--precision", choices=["mfma", "fp32"], default="mfma")
     ap.add_argument("--fields", type=int, default=64)
@@ -407,7 +480,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
         del src, dst
-    run = {"drift": run_drift, "batch": run_batch, "paper": run_paper}[args.workload]
+    run = {"drift": run_drift, "batch": run_batch, "paper": run_paper,
+           "literal": run_literal}[args.workload]
     res = run(args)
     print(json.dumps(res), flush=True)
 

@@ -170,6 +170,23 @@ int hg_grid_channels_host(hg_plan* p, const void* host_values, int64_t ld, int32
                           int32_t dtype, float* host_out, int32_t block, void* hip_stream,
                           hg_stream_info* info);
 
+/*
+ * Algorithm 1 as the paper states it (Sec. 4.1.2, Fig. 7, with the cells per
+ * thread of Sec. 4.3.3), a comparison path beside hg_grid_channels on the same
+ * plan: one launch per channel; one thread per gamma output cells of one 2x2
+ * pixel group (gamma 1, 2 or 4), walking the HEALPix cell runs of the rings
+ * that can hold a neighbour; for every channel it recomputes each FP64
+ * distance and Gaussian weight and reads the channel's values with stride ld,
+ * and sums w v and w in FP64 (Eq. 1).  NaN where a cell has no neighbour.
+ *   values: DEVICE float32 [n][ld] (FP32 only); out: DEVICE float32
+ *   [nchan][ny][nx].  block_threads: threads per workgroup, a multiple of 64
+ *   in [64, 1024].  Asynchronous on hip_stream.
+ *   Errors: HG_ERR_ARG (NULL pointers, gamma not 1/2/4, block_threads, ld <
+ *   nchan), HG_ERR_STATE (finished plan), HG_ERR_DEVICE.
+ */
+int hg_grid_channels_literal(hg_plan* p, const float* values, int64_t ld, int32_t nchan,
+                             float* out, int32_t gamma, int32_t block_threads, void* hip_stream);
+
 /* Synchronise the device, free everything the plan holds.  NULL is a no-op.
    A plan borrowed from a batch is refused with HG_ERR_STATE. */
 int hg_grid_finish(hg_plan* p);

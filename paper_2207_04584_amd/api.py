@@ -21,8 +21,9 @@ HG_FLAG_TIME_CHANNELS = 1
 
 ABI_FUNCTIONS = ("hg_grid_setup", "hg_grid_channels", "hg_grid_finish", "hg_plan_stats",
                  "hg_plan_counts", "hg_plan_weight_sums", "hg_plan_neighbours",
-                 "hg_ang2pix_ring", "hg_grid_channels_host", "hg_batch_create", "hg_batch_run", "hg_batch_destroy",
-                 "hg_batch_stats", "hg_batch_plan", "hg_last_error")
+                 "hg_ang2pix_ring", "hg_grid_channels_host", "hg_grid_channels_literal",
+                 "hg_batch_create", "hg_batch_run", "hg_batch_destroy", "hg_batch_stats",
+                 "hg_batch_plan", "hg_last_error")
 
 
 class HegridError(RuntimeError):
@@ -97,6 +98,7 @@ def lib():
     L.hg_grid_setup.argtypes = [P, P, i64, ctypes.POINTER(hg_kernel), ctypes.POINTER(hg_map),
                                 ctypes.POINTER(hg_opts), P, ctypes.POINTER(ctypes.c_void_p)]
     L.hg_grid_channels.argtypes = [P, P, i64, i32, i32, P, P]
+    L.hg_grid_channels_literal.argtypes = [P, P, i64, i32, P, i32, i32, P]
     L.hg_grid_finish.argtypes = [P]
     L.hg_plan_stats.argtypes = [P, ctypes.POINTER(hg_stats)]
     L.hg_plan_counts.argtypes = [P, P]
@@ -246,6 +248,30 @@ class Plan:
                                          _stream_ptr(stream), ctypes.byref(info))
         _check(rc, "hg_grid_channels_host")
         return out, {f: getattr(info, f) for f, _ in hg_stream_info._fields_}
+
+    def grid_literal(self, values, out=None, gamma=4, block=256, stream=None):
+        """Algorithm 1 as the paper states it (one launch per channel, one
+        thread per `gamma` cells, FP64 distances, weights and sums), the
+        comparison path: values a float32 device tensor [n][C] with unit
+        channel stride; returns out float32 [C][ny][nx] on the device."""
+        torch = _torch()
+        if values.dim() == 1:
+            values = values.reshape(-1, 1)
+        if (values.dtype != torch.float32 or values.device.type != "cuda"
+                or values.shape[0] != self.n or (self.n > 0 and values.stride(1) != 1)):
+            raise HegridError(HG_ERR_ARG, "values must be a float32 device tensor [n][C] with "
+                              "unit channel stride")
+        nchan = values.shape[1]
+        ld = values.stride(0) if values.shape[0] > 1 else nchan
+        ny, nx = self.shape
+        if out is None:
+            out = torch.empty((nchan, ny, nx), dtype=torch.float32, device=values.device)
+        rc = lib().hg_grid_channels_literal(self._handle(),
+                                            ctypes.c_void_p(values.data_ptr() if self.n else 0),
+                                            ld, nchan, ctypes.c_void_p(out.data_ptr()), int(gamma),
+                                            int(block), _stream_ptr(stream))
+        _check(rc, "hg_grid_channels_literal")
+        return out
 
     def stats(self):
         st = hg_stats()

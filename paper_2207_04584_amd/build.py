@@ -27,6 +27,7 @@ SOURCES = {
     "channels.hip": [],
     "runtime.hip": [],
     "stream.hip": [],
+    "literal.hip": ["-ffp-contract=off"],
 }
 
 

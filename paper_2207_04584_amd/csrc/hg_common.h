@@ -248,11 +248,21 @@ struct BatchKernelInfo {
     int channels_per_block;
 };
 
-// kernel launchers (setup.hip, channels.hip)
+// pixel centres in radians: (i, j) at ra0 + (i - (nx-1)/2) dra, dec0 + (j - (ny-1)/2) ddec
+__device__ inline double pix_ra(const hg_map& m, int64_t i) {
+    return (m.ra0_deg + ((double)i - (m.nx - 1) / 2.0) * m.dra_deg) * kDeg;
+}
+__device__ inline double pix_dec(const hg_map& m, int64_t j) {
+    return (m.dec0_deg + ((double)j - (m.ny - 1) / 2.0) * m.ddec_deg) * kDeg;
+}
+
+// kernel launchers (setup.hip, channels.hip, literal.hip)
 hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hipStream_t s,
                         std::string& err, int& status);
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
                            float* out, hipStream_t s);
+hipError_t launch_literal(const Plan& P, const float* values, int64_t ld, int32_t nchan,
+                          float* out, int32_t gamma, int32_t block, hipStream_t s);
 FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out);
 bool values_vec(const Plan& P, const void* values, int64_t ld, int32_t dtype);
 BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm);

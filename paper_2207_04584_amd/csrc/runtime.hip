@@ -549,6 +549,30 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
     });
 }
 
+int hg_grid_channels_literal(hg_plan* h, const float* values, int64_t ld, int32_t nchan,
+                             float* out, int32_t gamma, int32_t block_threads, void* hip_stream) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!h) return fail(HG_ERR_ARG, "plan must not be NULL");
+        Plan& P = h->P;
+        if (P.finished) return fail(HG_ERR_STATE, "plan already finished");
+        if (nchan < 0) return fail(HG_ERR_ARG, "nchan must be >= 0");
+        if (gamma != 1 && gamma != 2 && gamma != 4)
+            return fail(HG_ERR_ARG, "gamma must be 1, 2 or 4");
+        if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
+            return fail(HG_ERR_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+        if (nchan == 0) return HG_OK;
+        if (!out || (!values && P.n > 0)) return fail(HG_ERR_ARG, "values and out must not be NULL");
+        if (ld < nchan) return fail(HG_ERR_ARG, "ld must be >= nchan");
+        hipError_t e = hipSetDevice(P.device);
+        if (e == hipSuccess)
+            e = launch_literal(P, values, ld, nchan, out, gamma, block_threads,
+                               (hipStream_t)hip_stream);
+        if (e != hipSuccess) return fail_hip(e, "grid_channels_literal");
+        return HG_OK;
+    });
+}
+
 int hg_grid_channels_host(hg_plan* h, const void* host_values, int64_t ld, int32_t nchan,
                           int32_t dtype, float* host_out, int32_t block, void* hip_stream,
                           hg_stream_info* info) {

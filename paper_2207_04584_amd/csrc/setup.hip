@@ -121,12 +121,6 @@ hipError_t scan_exclusive(const Tin* in, int64_t n, Tout* out, Tout* scratch, hi
 }
 
 // ---------------------------------------------------------------------------
-__device__ inline double pix_ra(const hg_map& m, int64_t i) {
-    return (m.ra0_deg + ((double)i - (m.nx - 1) / 2.0) * m.dra_deg) * kDeg;
-}
-__device__ inline double pix_dec(const hg_map& m, int64_t j) {
-    return (m.dec0_deg + ((double)j - (m.ny - 1) / 2.0) * m.ddec_deg) * kDeg;
-}
 
 struct RowInfo {
     int32_t ring_lo, nrings;

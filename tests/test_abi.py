@@ -141,6 +141,7 @@ def test_channels_and_finish_state_rules():
     assert L.hg_plan_counts(None, None) == api.HG_ERR_ARG
     assert L.hg_ang2pix_ring(0, None, None, 1, None, None) == api.HG_ERR_ARG
     assert L.hg_grid_channels_host(None, None, 1, 1, 0, None, 0, None, None) == api.HG_ERR_ARG
+    assert L.hg_grid_channels_literal(None, None, 1, 1, None, 4, 256, None) == api.HG_ERR_ARG
     assert L.hg_ang2pix_ring(8, None, None, 0, None, None) == api.HG_OK  # nothing to do
 
 
