@@ -24,7 +24,12 @@ back + finish.
 states it (one launch per channel, gamma cells per thread, FP64), the
 comparison path.
 
-    python bench.py [--workload drift|batch|paper|literal] [--steps K] [--warmup W] [--gpus 1]
+--workload fifo: the 64 fields of the batch workload through a FIFO of host
+threads with a stream each (setup, then channel kernel, per field), the
+paper's style of pipeline, to set the batched form against.
+
+    python bench.py [--workload drift|batch|paper|literal|fifo] [--steps K] [--warmup W]
+                    [--gpus 1] [--streams S]
                     [--precision mfma|fp32] [--no-cpu-baseline]
 
 Prints one JSON line.  value = sum(N * C) / (seconds per step) in G
@@ -219,18 +224,18 @@ def run_drift(args):
     return res
 
 
-def run_batch(args):
-    import numpy as np
+def batch_inputs(args):
+    """The 64-field workload's fields with their coordinates and FP16 values
+    resident on the GPU."""
     import torch
 
-    from paper_2207_04584_amd import api, synth
+    from paper_2207_04584_amd import synth
 
     dev = torch.device("cuda:0")
     fs = synth.batch_fields(args.fields, scale=args.scale)
-    mfma = args.precision == "mfma"
     log(f"generating {len(fs)} fields on {torch.cuda.get_device_name(0)}")
     fields, vals_dev = [], []
-    for i, f in enumerate(fs):
+    for f in fs:
         v = synth.sky_values(f, f["nchan"], device=dev, dtype="f16")
         vals_dev.append(v)
         fields.append({"ra": torch.from_numpy(f["ra"]).to(dev),
@@ -240,6 +245,57 @@ def run_batch(args):
     nc = sum(f["ra"].shape[0] * f["nchan"] for f in fs)
     pc = sum(f["map"]["nx"] * f["map"]["ny"] * f["nchan"] for f in fs)
     log(f"sum N*C = {nc:.3e}, values {2 * nc / 1e9:.1f} GB, out {4 * pc / 1e9:.1f} GB")
+    return fs, fields, vals_dev, nc, pc
+
+
+def run_fifo(args):
+    """Survey row f3: the 64 fields through the paper's style of pipeline
+    (pipeline.grid_fields_fifo: a FIFO of fields served by host threads with
+    a stream each, setup then channel kernel per field), to set the batched
+    form against on the same fields and form."""
+    import torch
+
+    from paper_2207_04584_amd import api, pipeline
+
+    fs, fields, _, nc, _ = batch_inputs(args)
+    mfma = args.precision == "mfma"
+    prec = api.HG_PREC_MFMA_F16 if mfma else api.HG_PREC_FP32
+
+    def step():
+        pipeline.grid_fields_fifo(fields, n_streams=args.streams, precision=prec)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.1f} ms/step, {args.streams} streams")
+    return {
+        "metric": "G sample*channel updates/s (FIFO multi-stream pipeline, " +
+                  ("FP16-MFMA form)" if mfma else "plain FP32 form)"),
+        "value": nc / (ms_step * 1e-3) / 1e9, "unit": "G sample*channel updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16" if mfma else "f32", "data": "synthetic",
+        "config": {"workload": f"the {len(fs)}-field batching workload; step = every field's "
+                               "setup and channel kernel, fields taken in turn by host threads "
+                               "with a stream each",
+                   "fields": len(fs), "streams": args.streams, "sum_NC": nc,
+                   "form": args.precision},
+    }
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_2207_04584_amd import api
+
+    fs, fields, vals_dev, nc, pc = batch_inputs(args)
+    mfma = args.precision == "mfma"
 
     run_ms, setup_ms, info, nnz_f = [], [], {}, []
     prec = api.HG_PREC_MFMA_F16 if mfma else api.HG_PREC_FP32
@@ -457,8 +513,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["drift", "batch", "paper", "literal"],
+    ap.add_argument("--workload", choices=["drift", "batch", "paper", "literal", "fifo"],
                     default="drift")
+    ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--paper-samples", type=int, default=19_000_000)
     ap.add_argument("--precision", choices=["mfma", "fp32"], default="mfma")
     ap.add_argument("--fields", type=int, default=64)
@@ -481,7 +538,7 @@ def main():
         log(f"copy calibration: {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
         del src, dst
     run = {"drift": run_drift, "batch": run_batch, "paper": run_paper,
-           "literal": run_literal}[args.workload]
+           "literal": run_literal, "fifo": run_fifo}[args.workload]
     res = run(args)
     print(json.dumps(res), flush=True)
 
