@@ -10,7 +10,8 @@
  * with the inclusive support test d <= R of the cell-update workflow
  * (Algorithm 1, Sec. 4.1.2).  Readings where the paper is open:
  *   - kernel: Gaussian of the great-circle distance d, w = exp(-d^2 / 2 sigma^2),
- *     sigma = FWHM / sqrt(8 ln 2);
+ *     sigma = FWHM / sqrt(8 ln 2), by default; a Gauss-tapered sinc and an
+ *     elliptical Gaussian on request (hg_kernel.type);
  *   - support: d <= R, R = hg_kernel.support_deg, tested in FP64 as
  *     sin^2(dDec/2) + cos(Dec_g) cos(Dec_n) sin^2(dRA/2) <= sin^2(R/2);
  *   - map: plate carree in coordinate degrees; pixel (i, j) is centred at
@@ -68,9 +69,26 @@ typedef struct {
     int32_t nx, ny;           /* pixels along RA and Dec, > 0                  */
 } hg_map;
 
+/* Kernel shapes w(g; s) of Eq. 1 (the paper leaves w open).  d is the
+   great-circle distance, theta the bearing of the sample seen from the cell
+   (from north through east). */
+enum {
+    HG_KERNEL_GAUSS = 0,      /* exp(-d^2 / 2 sigma^2), sigma = FWHM / sqrt(8 ln 2)        */
+    HG_KERNEL_GAUSS_SINC = 1, /* sinc(d / b) exp(-(d / a)^2), sinc(x) = sin(pi x)/(pi x);
+                                 a = p1, b = p2 (degrees, > 0); weights may be negative   */
+    HG_KERNEL_ELLIPTICAL = 2  /* exp(-u^2 / 2 s_maj^2 - v^2 / 2 s_min^2): (u, v) = d times
+                                 (cos, sin) of theta - pa, the offset along the major and
+                                 minor axes; s_maj from fwhm_deg, s_min from FWHM p1
+                                 (degrees, > 0), pa = p2 (degrees, north through east)     */
+};
+
 typedef struct {
-    double fwhm_deg;    /* Gaussian FWHM (degrees), > 0                          */
+    double fwhm_deg;    /* Gaussian FWHM (degrees), > 0; the major axis for
+                           HG_KERNEL_ELLIPTICAL (unused by HG_KERNEL_GAUSS_SINC)  */
     double support_deg; /* support radius R (degrees), 0 <= R <= 10, inclusive */
+    int32_t type;       /* HG_KERNEL_*; 0 = Gaussian                            */
+    int32_t reserved;   /* must be 0                                            */
+    double p1, p2;      /* shape parameters of the non-Gaussian kernels         */
 } hg_kernel;
 
 typedef struct {
@@ -182,7 +200,8 @@ int hg_grid_channels_host(hg_plan* p, const void* host_values, int64_t ld, int32
  *   [nchan][ny][nx].  block_threads: threads per workgroup, a multiple of 64
  *   in [64, 1024].  Asynchronous on hip_stream.
  *   Errors: HG_ERR_ARG (NULL pointers, gamma not 1/2/4, block_threads, ld <
- *   nchan), HG_ERR_STATE (finished plan), HG_ERR_DEVICE.
+ *   nchan), HG_ERR_STATE (finished plan), HG_ERR_UNSUPPORTED (a plan whose
+ *   kernel is not the Gaussian), HG_ERR_DEVICE.
  */
 int hg_grid_channels_literal(hg_plan* p, const float* values, int64_t ld, int32_t nchan,
                              float* out, int32_t gamma, int32_t block_threads, void* hip_stream);

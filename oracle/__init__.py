@@ -64,6 +64,12 @@ def _load():
         lib.oracle_neighbours.argtypes = [i64, P, P, ctypes.POINTER(_Map), f64, f64, i32, P, i64,
                                           P, P, P, i64, P]
         lib.oracle_neighbours.restype = ctypes.c_int
+        lib.oracle_grid_k.argtypes = [i64, P, P, P, i32, i64, P, i64, ctypes.POINTER(_Map), f64,
+                                      f64, i32, f64, f64, i32, P, i64, P, P, P, P]
+        lib.oracle_grid_k.restype = ctypes.c_int
+        lib.oracle_neighbours_k.argtypes = [i64, P, P, ctypes.POINTER(_Map), f64, f64, i32, f64,
+                                            f64, i32, P, i64, P, P, P, i64, P]
+        lib.oracle_neighbours_k.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -84,9 +90,20 @@ def _coords(ra_deg, dec_deg):
     return ra, dec
 
 
+def _shape(kernel):
+    """(type, p1, p2) of a kernel dict; the Gaussian when None or untyped."""
+    if kernel is None:
+        return 0, 0.0, 0.0
+    return int(kernel.get("type", 0)), float(kernel.get("p1", 0.0)), float(kernel.get("p2", 0.0))
+
+
 def grid(ra_deg, dec_deg, values, dtype, m, fwhm_deg, support_deg, chans=None, pix=None,
-         brute=False):
+         brute=False, kernel=None):
     """Reference maps for the selected channels and cells.
+
+    kernel: optional dict with "type" (0 Gaussian, 1 Gauss-tapered sinc, 2
+    elliptical Gaussian) and its "p1", "p2" (see oracle.c); fwhm_deg and
+    support_deg are passed separately as for the Gaussian.
 
     values: array [n][ld]; float64 / float32, or uint16 bit patterns for
     ``dtype`` 'bf16' / 'f16' (decoded exactly to FP64 inside the oracle).
@@ -118,16 +135,17 @@ def grid(ra_deg, dec_deg, values, dtype, m, fwhm_deg, support_deg, chans=None, p
     W = np.empty(npix, dtype=np.float64)
     margin = ctypes.c_double(0.0)
     mp = _mk_map(m)
-    rc = lib.oracle_grid(ra.shape[0], _ptr(ra), _ptr(dec), _ptr(vals), code, ld, _ptr(chans),
-                         chans.shape[0], ctypes.byref(mp), float(fwhm_deg), float(support_deg),
-                         int(bool(brute)), _ptr(pix), npix, _ptr(out), _ptr(count), _ptr(W),
-                         ctypes.byref(margin))
+    kt, p1, p2 = _shape(kernel)
+    rc = lib.oracle_grid_k(ra.shape[0], _ptr(ra), _ptr(dec), _ptr(vals), code, ld, _ptr(chans),
+                           chans.shape[0], ctypes.byref(mp), float(fwhm_deg), float(support_deg),
+                           kt, p1, p2, int(bool(brute)), _ptr(pix), npix, _ptr(out),
+                           _ptr(count), _ptr(W), ctypes.byref(margin))
     if rc != 0:
         raise ValueError(f"oracle_grid failed with status {rc}")
     return out, count, W, margin.value
 
 
-def neighbours(ra_deg, dec_deg, m, fwhm_deg, support_deg, pix=None, brute=False):
+def neighbours(ra_deg, dec_deg, m, fwhm_deg, support_deg, pix=None, brute=False, kernel=None):
     """CSR neighbour lists (ascending original index) and FP64 weights."""
     lib = _load()
     ra, dec = _coords(ra_deg, dec_deg)
@@ -137,14 +155,15 @@ def neighbours(ra_deg, dec_deg, m, fwhm_deg, support_deg, pix=None, brute=False)
     row_ptr = np.zeros(npix + 1, dtype=np.int64)
     nnz = ctypes.c_int64(0)
     mp = _mk_map(m)
+    kt, p1, p2 = _shape(kernel)
     args = (ra.shape[0], _ptr(ra), _ptr(dec), ctypes.byref(mp), float(fwhm_deg),
-            float(support_deg), int(bool(brute)), _ptr(pix), npix, _ptr(row_ptr))
-    rc = lib.oracle_neighbours(*args, None, None, 0, ctypes.byref(nnz))
+            float(support_deg), kt, p1, p2, int(bool(brute)), _ptr(pix), npix, _ptr(row_ptr))
+    rc = lib.oracle_neighbours_k(*args, None, None, 0, ctypes.byref(nnz))
     if rc != 0:
         raise ValueError(f"oracle_neighbours failed with status {rc}")
     idx = np.empty(max(nnz.value, 1), dtype=np.int64)
     w = np.empty(max(nnz.value, 1), dtype=np.float64)
-    rc = lib.oracle_neighbours(*args, _ptr(idx), _ptr(w), nnz.value, ctypes.byref(nnz))
+    rc = lib.oracle_neighbours_k(*args, _ptr(idx), _ptr(w), nnz.value, ctypes.byref(nnz))
     if rc != 0:
         raise ValueError(f"oracle_neighbours failed with status {rc}")
     return row_ptr, idx[:nnz.value], w[:nnz.value]

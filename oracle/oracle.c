@@ -16,7 +16,15 @@
  * open; the readings taken here are:
  *
  *   - w(d) = exp(-d^2 / (2 sigma^2)), sigma = FWHM / sqrt(8 ln 2) (not
- *     normalised: W cancels any constant factor);
+ *     normalised: W cancels any constant factor); Eq. 1 leaves w open, and two
+ *     other shapes are offered through the *_k entry points:
+ *       1: Gauss-tapered sinc, w = sinc(d/b) exp(-(d/a)^2), sinc(x) =
+ *          sin(pi x)/(pi x), sinc(0) = 1 (a, b in degrees);
+ *       2: elliptical Gaussian, w = exp(-u^2/(2 s_maj^2) - v^2/(2 s_min^2)),
+ *          u = d cos(theta - pa), v = d sin(theta - pa), theta the bearing of
+ *          the sample from the cell (atan2 of its east and north components,
+ *          from north through east), s = FWHM / sqrt(8 ln 2) for the major
+ *          (fwhm) and minor (p1) axes, pa = p2 degrees;
  *   - d is the great-circle distance, evaluated through the haversine
  *     h = sin^2(dDec/2) + cos(Dec_p) cos(Dec_n) sin^2(dRA/2); the support test
  *     is h <= h_R with h_R = sin^2(R/2), which is d <= R because h grows with d
@@ -132,6 +140,9 @@ typedef struct {
     double* dec;
     or_key* by_dec; /* NULL in brute-force mode */
     double sigma, h_r, r_rad;
+    int ktype;                    /* 0 Gaussian, 1 Gauss-sinc, 2 elliptical */
+    double ka, kb;                /* Gauss-sinc a and b, radians */
+    double smaj, smin, pa;        /* elliptical sigmas and position angle, radians */
     double margin; /* min |h - h_R| / h_R over all pairs tested */
     or_nb* buf;    /* scratch for one cell's neighbours */
     int64_t buf_cap;
@@ -145,10 +156,21 @@ static void or_ctx_free(or_ctx* c) {
 }
 
 static int or_ctx_init(or_ctx* c, int64_t n, const double* ra_deg, const double* dec_deg,
-                       double fwhm_deg, double support_deg, int brute) {
+                       double fwhm_deg, double support_deg, int brute, int32_t ktype, double p1,
+                       double p2) {
     memset(c, 0, sizeof *c);
-    if (n < 0 || (n > 0 && (!ra_deg || !dec_deg)) || !(fwhm_deg > 0) || !(support_deg >= 0))
+    if (n < 0 || (n > 0 && (!ra_deg || !dec_deg)) || !(support_deg >= 0) || ktype < 0 ||
+        ktype > 2)
         return OR_ERR_ARG;
+    if (ktype != 1 && !(fwhm_deg > 0)) return OR_ERR_ARG;
+    if (ktype == 1 && !(p1 > 0 && p2 > 0)) return OR_ERR_ARG;
+    if (ktype == 2 && !(p1 > 0)) return OR_ERR_ARG;
+    c->ktype = ktype;
+    c->ka = p1 * DEG;
+    c->kb = p2 * DEG;
+    c->smaj = fwhm_deg * DEG / sqrt(8.0 * log(2.0));
+    c->smin = p1 * DEG / sqrt(8.0 * log(2.0));
+    c->pa = p2 * DEG;
     c->n = n;
     c->ra = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
     c->dec = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
@@ -176,6 +198,24 @@ static int or_ctx_init(or_ctx* c, int64_t n, const double* ra_deg, const double*
     return OR_OK;
 }
 
+/* the kernel's weight of a pair at distance d, cell (ra_p, dec_p), sample (ra_n, dec_n) */
+static double or_weight(const or_ctx* c, double d, double ra_p, double dec_p, double ra_n,
+                        double dec_n) {
+    if (c->ktype == 1) {
+        double x = 3.14159265358979323846 * d / c->kb;
+        double sinc = x == 0.0 ? 1.0 : sin(x) / x;
+        return sinc * exp(-(d / c->ka) * (d / c->ka));
+    }
+    if (c->ktype == 2) {
+        double east = cos(dec_n) * sin(ra_n - ra_p);
+        double north = cos(dec_p) * sin(dec_n) - sin(dec_p) * cos(dec_n) * cos(ra_n - ra_p);
+        double theta = atan2(east, north);
+        double u = d * cos(theta - c->pa), v = d * sin(theta - c->pa);
+        return exp(-(u * u) / (2.0 * c->smaj * c->smaj) - (v * v) / (2.0 * c->smin * c->smin));
+    }
+    return exp(-(d * d) / (2.0 * c->sigma * c->sigma));
+}
+
 /* one candidate pair: exact inclusive test; appends to the cell's list */
 static int or_try(or_ctx* c, double ra_p, double dec_p, int64_t k, int64_t* cnt) {
     double h = or_haversine(ra_p, dec_p, c->ra[k], c->dec[k]);
@@ -193,7 +233,7 @@ static int or_try(or_ctx* c, double ra_p, double dec_p, int64_t k, int64_t* cnt)
         c->buf_cap = cap;
     }
     c->buf[*cnt].idx = k;
-    c->buf[*cnt].w = exp(-(d * d) / (2.0 * c->sigma * c->sigma));
+    c->buf[*cnt].w = or_weight(c, d, ra_p, dec_p, c->ra[k], c->dec[k]);
     (*cnt)++;
     return OR_OK;
 }
@@ -238,10 +278,11 @@ static int or_check_map(const or_map* m) {
  *   out:      [nchan][npix] FP64, NaN where the cell has no neighbour
  *   count, W: [npix]; margin: closest call min |h - h_R| / h_R (may be NULL)
  */
-int oracle_grid(int64_t n, const double* ra_deg, const double* dec_deg, const void* values,
-                int32_t dtype, int64_t ld, const int64_t* chans, int64_t nchan, const or_map* m,
-                double fwhm_deg, double support_deg, int32_t brute, const int64_t* pix,
-                int64_t npix, double* out, int32_t* count, double* W, double* margin) {
+int oracle_grid_k(int64_t n, const double* ra_deg, const double* dec_deg, const void* values,
+                  int32_t dtype, int64_t ld, const int64_t* chans, int64_t nchan, const or_map* m,
+                  double fwhm_deg, double support_deg, int32_t ktype, double p1, double p2,
+                  int32_t brute, const int64_t* pix, int64_t npix, double* out, int32_t* count,
+                  double* W, double* margin) {
     if (!or_check_map(m) || nchan < 0 || (nchan > 0 && (!values || !chans || !out)) ||
         dtype < OR_F64 || dtype > OR_F16)
         return OR_ERR_ARG;
@@ -250,7 +291,7 @@ int oracle_grid(int64_t n, const double* ra_deg, const double* dec_deg, const vo
     for (int64_t k = 0; k < nchan; k++)
         if (chans[k] < 0 || chans[k] >= ld) return OR_ERR_ARG;
     or_ctx c;
-    int rc = or_ctx_init(&c, n, ra_deg, dec_deg, fwhm_deg, support_deg, brute);
+    int rc = or_ctx_init(&c, n, ra_deg, dec_deg, fwhm_deg, support_deg, brute, ktype, p1, p2);
     if (rc) {
         or_ctx_free(&c);
         return rc;
@@ -285,21 +326,30 @@ int oracle_grid(int64_t n, const double* ra_deg, const double* dec_deg, const vo
     return OR_OK;
 }
 
+/* oracle_grid_k with the Gaussian kernel */
+int oracle_grid(int64_t n, const double* ra_deg, const double* dec_deg, const void* values,
+                int32_t dtype, int64_t ld, const int64_t* chans, int64_t nchan, const or_map* m,
+                double fwhm_deg, double support_deg, int32_t brute, const int64_t* pix,
+                int64_t npix, double* out, int32_t* count, double* W, double* margin) {
+    return oracle_grid_k(n, ra_deg, dec_deg, values, dtype, ld, chans, nchan, m, fwhm_deg,
+                         support_deg, 0, 0.0, 0.0, brute, pix, npix, out, count, W, margin);
+}
+
 /*
  * Neighbour lists (CSR) of the selected cells: row_ptr[npix+1], and for the
  * t-th neighbour of row q its original index idx[t] and weight w[t].  Rows are
  * in ascending original index.  Returns the total count through *nnz; idx and
  * w are written only while they fit in cap (pass cap = 0 to size them).
  */
-int oracle_neighbours(int64_t n, const double* ra_deg, const double* dec_deg, const or_map* m,
-                      double fwhm_deg, double support_deg, int32_t brute, const int64_t* pix,
-                      int64_t npix, int64_t* row_ptr, int64_t* idx, double* w, int64_t cap,
-                      int64_t* nnz) {
+int oracle_neighbours_k(int64_t n, const double* ra_deg, const double* dec_deg,
+                        const or_map* m, double fwhm_deg, double support_deg, int32_t ktype,
+                        double p1, double p2, int32_t brute, const int64_t* pix, int64_t npix,
+                        int64_t* row_ptr, int64_t* idx, double* w, int64_t cap, int64_t* nnz) {
     if (!or_check_map(m) || !row_ptr || !nnz) return OR_ERR_ARG;
     int64_t ncell = (int64_t)m->nx * m->ny;
     if (!pix) npix = ncell;
     or_ctx c;
-    int rc = or_ctx_init(&c, n, ra_deg, dec_deg, fwhm_deg, support_deg, brute);
+    int rc = or_ctx_init(&c, n, ra_deg, dec_deg, fwhm_deg, support_deg, brute, ktype, p1, p2);
     if (rc) {
         or_ctx_free(&c);
         return rc;
@@ -331,4 +381,13 @@ int oracle_neighbours(int64_t n, const double* ra_deg, const double* dec_deg, co
     *nnz = total;
     or_ctx_free(&c);
     return OR_OK;
+}
+
+/* oracle_neighbours_k with the Gaussian kernel */
+int oracle_neighbours(int64_t n, const double* ra_deg, const double* dec_deg, const or_map* m,
+                      double fwhm_deg, double support_deg, int32_t brute, const int64_t* pix,
+                      int64_t npix, int64_t* row_ptr, int64_t* idx, double* w, int64_t cap,
+                      int64_t* nnz) {
+    return oracle_neighbours_k(n, ra_deg, dec_deg, m, fwhm_deg, support_deg, 0, 0.0, 0.0, brute,
+                               pix, npix, row_ptr, idx, w, cap, nnz);
 }

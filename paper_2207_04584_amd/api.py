@@ -39,7 +39,12 @@ class hg_map(ctypes.Structure):
 
 
 class hg_kernel(ctypes.Structure):
-    _fields_ = [("fwhm_deg", ctypes.c_double), ("support_deg", ctypes.c_double)]
+    _fields_ = [("fwhm_deg", ctypes.c_double), ("support_deg", ctypes.c_double),
+                ("type", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("p1", ctypes.c_double), ("p2", ctypes.c_double)]
+
+
+HG_KERNEL_GAUSS, HG_KERNEL_GAUSS_SINC, HG_KERNEL_ELLIPTICAL = 0, 1, 2
 
 
 class hg_opts(ctypes.Structure):
@@ -155,7 +160,8 @@ def make_map(m):
 
 
 def make_kernel(k):
-    return hg_kernel(float(k["fwhm_deg"]), float(k["support_deg"]))
+    return hg_kernel(float(k["fwhm_deg"]), float(k["support_deg"]), int(k.get("type", 0)), 0,
+                     float(k.get("p1", 0.0)), float(k.get("p2", 0.0)))
 
 
 _DTYPES = None

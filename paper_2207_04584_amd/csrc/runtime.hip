@@ -202,7 +202,18 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
     if (!k || !m || (n > 0 && (!ra || !dec)))
         return fail(HG_ERR_ARG, "NULL argument (kernel, map or coordinates)");
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(HG_ERR_ARG, "n must be in [0, 2^31)");
-    if (!finite(k->fwhm_deg) || !(k->fwhm_deg > 0)) return fail(HG_ERR_ARG, "fwhm_deg must be > 0");
+    if (k->type != HG_KERNEL_GAUSS && k->type != HG_KERNEL_GAUSS_SINC &&
+        k->type != HG_KERNEL_ELLIPTICAL)
+        return fail(HG_ERR_UNSUPPORTED, "unknown kernel type");
+    if (k->reserved) return fail(HG_ERR_ARG, "kernel reserved field must be 0");
+    if (k->type != HG_KERNEL_GAUSS_SINC && (!finite(k->fwhm_deg) || !(k->fwhm_deg > 0)))
+        return fail(HG_ERR_ARG, "fwhm_deg must be > 0");
+    if (k->type == HG_KERNEL_GAUSS_SINC &&
+        (!finite(k->p1) || !(k->p1 > 0) || !finite(k->p2) || !(k->p2 > 0)))
+        return fail(HG_ERR_ARG, "the Gauss-sinc kernel needs a = p1 > 0 and b = p2 > 0");
+    if (k->type == HG_KERNEL_ELLIPTICAL && (!finite(k->p1) || !(k->p1 > 0) || !finite(k->p2)))
+        return fail(HG_ERR_ARG, "the elliptical kernel needs a minor FWHM p1 > 0 and a finite "
+                                "position angle p2");
     if (!finite(k->support_deg) || !(k->support_deg >= 0) || k->support_deg > 10.0)
         return fail(HG_ERR_ARG, "support_deg must be in [0, 10]");
     if (m->nx <= 0 || m->ny <= 0) return fail(HG_ERR_ARG, "map nx and ny must be > 0");
@@ -239,7 +250,7 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     P.kern = *k;
     if (o) P.opts = *o;
     P.n = n;
-    P.sigma = k->fwhm_deg * kDeg / sqrt(8.0 * log(2.0));
+    P.sigma = k->type == HG_KERNEL_GAUSS_SINC ? 0.0 : k->fwhm_deg * kDeg / sqrt(8.0 * log(2.0));
     P.r_rad = k->support_deg * kDeg;
     double sh = sin(0.5 * P.r_rad);
     P.h_r = sh * sh;
@@ -559,6 +570,8 @@ int hg_grid_channels_literal(hg_plan* h, const float* values, int64_t ld, int32_
         if (nchan < 0) return fail(HG_ERR_ARG, "nchan must be >= 0");
         if (gamma != 1 && gamma != 2 && gamma != 4)
             return fail(HG_ERR_ARG, "gamma must be 1, 2 or 4");
+        if (P.kern.type != HG_KERNEL_GAUSS)
+            return fail(HG_ERR_UNSUPPORTED, "the Algorithm 1 path has the Gaussian kernel only");
         if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
             return fail(HG_ERR_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
         if (nchan == 0) return HG_OK;

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void k_slot_fill(const int4* __restrict__ tile
 __device__ inline float round_weight(float w, int32_t prec) {
     if (prec == HG_PREC_MFMA_BF16) {
         uint32_t u = __float_as_uint(w);
-        u += 0x7FFFu + ((u >> 16) & 1u);  // finite positive weights only
+        u += 0x7FFFu + ((u >> 16) & 1u);  // finite weights (either sign)
         return __uint_as_float(u & 0xFFFF0000u);
     }
     if (prec == HG_PREC_MFMA_F16) return (float)(_Float16)w;
@@ -469,17 +469,70 @@ __device__ inline void half_sines(double a0, double a1, double a2, double a3, do
     }
 }
 
+// Kernel constants for the weight of Eq. 1 (w for the plan's hg_kernel type).
+struct KernelArgs {
+    double inv_two_s2;      // Gaussian: 1 / 2 sigma^2
+    double inv_a2, pi_b;    // Gauss-sinc: 1 / a^2, pi / b
+    double inv_two_smaj2, inv_two_smin2, cos_pa, sin_pa;  // elliptical
+};
+
+KernelArgs kernel_args(const Plan& P) {
+    KernelArgs ka{};
+    const double f2s = 1.0 / sqrt(8.0 * log(2.0));
+    if (P.kern.type == HG_KERNEL_GAUSS) {
+        ka.inv_two_s2 = 1.0 / (2.0 * P.sigma * P.sigma);
+    } else if (P.kern.type == HG_KERNEL_GAUSS_SINC) {
+        const double a = P.kern.p1 * kDeg, b = P.kern.p2 * kDeg;
+        ka.inv_a2 = 1.0 / (a * a);
+        ka.pi_b = 3.14159265358979323846 / b;
+    } else {
+        const double smaj = P.kern.fwhm_deg * kDeg * f2s, smin = P.kern.p1 * kDeg * f2s;
+        ka.inv_two_smaj2 = 1.0 / (2.0 * smaj * smaj);
+        ka.inv_two_smin2 = 1.0 / (2.0 * smin * smin);
+        ka.cos_pa = cos(P.kern.p2 * kDeg);
+        ka.sin_pa = sin(P.kern.p2 * kDeg);
+    }
+    return ka;
+}
+
+// The weight of a pair in support, from its squared distance d2 and (for the
+// elliptical kernel) the two positions: the bearing theta of the sample seen
+// from the cell has sin theta : cos theta = E : N with E = cos dec_n sin dRA,
+// N = cos dec_p sin dec_n - sin dec_p cos dec_n cos dRA (both sin d times the
+// unit components), so the offsets along the axes at position angle pa are
+// u = d cos(theta - pa), v = d sin(theta - pa).
+template <int KT>
+__device__ inline double kernel_weight(const KernelArgs& ka, double d2, double ra_n,
+                                       double dec_n, double cos_n, double ra_p, double dec_p,
+                                       double cos_p) {
+    if (KT == HG_KERNEL_GAUSS) return exp(-d2 * ka.inv_two_s2);
+    if (KT == HG_KERNEL_GAUSS_SINC) {
+        const double x = sqrt(d2) * ka.pi_b;
+        const double sinc = x > 0.0 ? sin(x) / x : 1.0;
+        return sinc * exp(-d2 * ka.inv_a2);
+    }
+    const double dra = ra_n - ra_p;
+    const double e = cos_n * sin(dra);
+    const double nn = cos_p * sin(dec_n) - sin(dec_p) * cos_n * cos(dra);
+    const double r2 = e * e + nn * nn;
+    if (!(r2 > 0.0)) return 1.0;  // d = 0
+    const double ct = nn / sqrt(r2), st = e / sqrt(r2);
+    const double cu = ct * ka.cos_pa + st * ka.sin_pa;  // cos(theta - pa)
+    const double sv = st * ka.cos_pa - ct * ka.sin_pa;  // sin(theta - pa)
+    return exp(-d2 * (cu * cu * ka.inv_two_smaj2 + sv * sv * ka.inv_two_smin2));
+}
+
 // One wave per pixel group.  Lanes walk the group's candidates in slot order;
 // each lane tests its candidate against the group's (up to) four pixels with
 // the exact FP64 haversine test, and surviving candidates are compacted in
 // order into the group's entry list with their four FP32 weights.
 constexpr int GATHER_WAVES = 4;
 
-template <bool SMALL>
+template <bool SMALL, int KT>
 __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     const int4* __restrict__ pg_piece, int32_t pg_rings, const int64_t* __restrict__ pg_base,
     const double4* __restrict__ srt_coord, int32_t npgx, int64_t npg, hg_map m, double h_r,
-    double inv_two_s2, int32_t prec, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
+    KernelArgs ka, int32_t prec, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
     uint32_t* __restrict__ pg_cnt, int32_t* __restrict__ pix_count, double* __restrict__ pix_W,
     float* __restrict__ pix_Wf, unsigned long long* __restrict__ nnz_total) {
     extern __shared__ int sh_gather[];
@@ -549,7 +602,13 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
 #pragma unroll 1
             for (int k = 0; k < 4; k++) {
                 float wf = 0.f;
-                if (mk & 1u) wf = round_weight((float)exp(-dist2<SMALL>(h0) * inv_two_s2), prec);
+                if (mk & 1u) {
+                    const double w =
+                        kernel_weight<KT>(ka, dist2<SMALL>(h0), c.x, c.y, c.z,
+                                          (k & 1) ? pra1 : pra0, (k >> 1) ? pdec1 : pdec0,
+                                          (k >> 1) ? pcos1 : pcos0);
+                    wf = round_weight((float)w, prec);
+                }
                 h0 = h1;
                 h1 = h2;
                 h2 = h3;
@@ -1247,13 +1306,20 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(hipGetLastError());
     {
         size_t shm = (size_t)GATHER_WAVES * 3 * (npc_p + 1) * sizeof(int);
-        const double inv_two_s2 = 1.0 / (2.0 * P.sigma * P.sigma);
+        const KernelArgs ka = kernel_args(P);
         // every in-support h is at most h_r; below 1e-4 no asin is needed
-        auto kern = P.h_r < 1e-4 ? k_gather<true> : k_gather<false>;
+        const bool small = P.h_r < 1e-4;
+        auto kern = P.kern.type == HG_KERNEL_GAUSS
+                        ? (small ? k_gather<true, HG_KERNEL_GAUSS> : k_gather<false, HG_KERNEL_GAUSS>)
+                    : P.kern.type == HG_KERNEL_GAUSS_SINC
+                        ? (small ? k_gather<true, HG_KERNEL_GAUSS_SINC>
+                                 : k_gather<false, HG_KERNEL_GAUSS_SINC>)
+                        : (small ? k_gather<true, HG_KERNEL_ELLIPTICAL>
+                                 : k_gather<false, HG_KERNEL_ELLIPTICAL>);
         hipLaunchKernelGGL(kern, dim3(blocks_for(P.npg, GATHER_WAVES)), dim3(64 * GATHER_WAVES),
                            shm, s, (const int4*)P.pg_piece.p, P.pg_rings,
                            (const int64_t*)P.pg_base.p, (const double4*)P.srt_coord.p, P.npgx,
-                           P.npg, P.map, P.h_r, inv_two_s2, P.opts.precision, (uint32_t*)P.ent_slot.p,
+                           P.npg, P.map, P.h_r, ka, P.opts.precision, (uint32_t*)P.ent_slot.p,
                            (float4*)P.ent_w.p, (uint32_t*)P.pg_cnt.p, (int32_t*)P.pix_count.p,
                            (double*)P.pix_W.p, (float*)P.pix_Wf.p, nnz_total);
         HG_STEP(hipGetLastError());

@@ -293,3 +293,81 @@ def test_bad_arguments_are_rejected():
     bad = dict(m, nx=0)
     with pytest.raises(ValueError):
         oracle.grid([0.0], [0.0], np.zeros((1, 1)), "f64", bad, 0.05, 0.1)
+
+
+# --- other kernel shapes of Eq. 1 (survey row f4): closed forms and invariants
+
+def one_pair_weight(ra_s, dec_s, ra_p, dec_p, fwhm, support, kernel):
+    """W of a one-cell map at (ra_p, dec_p) holding one sample: the pair's weight."""
+    m = {"ra0_deg": ra_p, "dec0_deg": dec_p, "dra_deg": 1 / 60, "ddec_deg": 1 / 60,
+         "nx": 1, "ny": 1}
+    _, cnt, W, _ = oracle.grid(np.array([ra_s]), np.array([dec_s]), np.ones((1, 1)), "f64", m,
+                               fwhm, support, kernel=kernel)
+    assert cnt[0] == 1
+    return W[0]
+
+
+def test_elliptical_axes_on_the_equator():
+    """On the equator a sample due east (bearing 90 deg) or due north (0 deg)
+    of the cell is offset purely along one axis, so the weight is the 1-D
+    Gaussian of that axis; a quarter turn of the position angle swaps them."""
+    fwhm_maj, fwhm_min, R = 4.0 / 60, 2.0 / 60, 0.2
+    s_maj, s_min = (f * math.pi / 180 / math.sqrt(8 * math.log(2)) for f in (fwhm_maj, fwhm_min))
+    d_deg = 1.7 / 60
+    d = d_deg * math.pi / 180
+    for pa, s_east, s_north in [(0.0, s_min, s_maj), (90.0, s_maj, s_min)]:
+        k = {"type": 2, "p1": fwhm_min, "p2": pa}
+        w_e = one_pair_weight(10.0 + d_deg, 0.0, 10.0, 0.0, fwhm_maj, R, k)
+        w_n = one_pair_weight(10.0, d_deg, 10.0, 0.0, fwhm_maj, R, k)
+        assert w_e == pytest.approx(math.exp(-d * d / (2 * s_east ** 2)), rel=1e-12)
+        assert w_n == pytest.approx(math.exp(-d * d / (2 * s_north ** 2)), rel=1e-12)
+
+
+def test_elliptical_round_beam_is_the_gaussian_and_half_turn_symmetric():
+    ra, dec, vals, m, k = _field(31, n=800, dec0=47.0)
+    g = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"])
+    for pa in (0.0, 37.0, 123.0):
+        e = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"],
+                              kernel={"type": 2, "p1": k["fwhm_deg"], "p2": pa})
+        np.testing.assert_array_equal(e[0], g[0])
+        np.testing.assert_array_equal(e[1], g[1])
+        np.testing.assert_allclose(e[2], g[2], rtol=1e-13)
+    el = {"type": 2, "p1": 0.4 * k["fwhm_deg"], "p2": 25.0}
+    a = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"], kernel=el)
+    b = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"],
+                          kernel=dict(el, p2=25.0 + 180.0))
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_allclose(a[2], b[2], rtol=1e-12)
+    assert not np.allclose(a[2], g[2])  # the shape does change the weights
+
+
+def test_gauss_sinc_closed_forms():
+    """sinc(d/b) exp(-(d/a)^2) along a meridian (distance = Dec offset):
+    1 at d = 0, 2/pi exp(-(b/2a)^2) at d = b/2, zero at d = b, negative
+    between b and 2b."""
+    a, b, R = 2.0 / 60, 3.0 / 60, 0.2
+    k = {"type": 1, "p1": a, "p2": b}
+    assert one_pair_weight(20.0, 5.0, 20.0, 5.0, 1.0, R, k) == 1.0
+    w_half = one_pair_weight(20.0, 5.0 + b / 2, 20.0, 5.0, 1.0, R, k)
+    assert w_half == pytest.approx(2 / math.pi * math.exp(-(b / (2 * a)) ** 2), rel=1e-12)
+    assert abs(one_pair_weight(20.0, 5.0 + b, 20.0, 5.0, 1.0, R, k)) < 1e-15
+    assert one_pair_weight(20.0, 5.0 + 1.5 * b, 20.0, 5.0, 1.0, R, k) < 0
+
+
+def test_kernel_shape_leaves_the_support_unchanged():
+    ra, dec, vals, m, k = _field(32, n=700)
+    base = oracle.grid(ra, dec, vals, "f64", m, k["fwhm_deg"], k["support_deg"])
+    for shape in ({"type": 1, "p1": 2.0 / 60, "p2": 3.0 / 60},
+                  {"type": 2, "p1": 1.5 / 60, "p2": 60.0}):
+        other = oracle.grid(ra, dec, vals, "f64", m, k["fwhm_deg"], k["support_deg"],
+                            kernel=shape)
+        np.testing.assert_array_equal(other[1], base[1])
+        np.testing.assert_array_equal(np.isnan(other[0]), np.isnan(base[0]))
+
+
+def test_kernel_shape_arguments_are_checked():
+    m = synth.make_map(0.0, 0.0, 2, 2)
+    for shape in ({"type": 1, "p1": 0.0, "p2": 0.05}, {"type": 2, "p1": -1.0},
+                  {"type": 3}):
+        with pytest.raises(ValueError):
+            oracle.grid([0.0], [0.0], np.zeros((1, 1)), "f64", m, 0.05, 0.1, kernel=shape)
