@@ -498,6 +498,24 @@ __device__ __attribute__((always_inline)) inline void grid_item(
             const int n = (FORM == FORM_F32 ? 1 : 4) * (e1K[k] - eK[k]);
             slK[k] = es[(FORM == FORM_F32 ? 1 : 4) * eK[k] + (lane < n ? lane : 0)];
         }
+        // A wave holding more than its share of this chunk's entries gets a
+        // higher issue priority: the chunk ends with its longest wave, which
+        // otherwise shares its SIMD evenly with lighter waves until they are
+        // done and then runs alone.
+        {
+            int mine = 0;
+#pragma unroll
+            for (int k = 0; k < PGW; k++) mine += pv[k] ? e1K[k] - eK[k] : 0;
+            const int share = mine * CH_WAVES;  // against po_end, the chunk's total
+            if (share >= 2 * po_end)
+                __builtin_amdgcn_s_setprio(3);
+            else if (2 * share >= 3 * po_end)
+                __builtin_amdgcn_s_setprio(2);
+            else if (share >= po_end)
+                __builtin_amdgcn_s_setprio(1);
+            else
+                __builtin_amdgcn_s_setprio(0);
+        }
 #pragma unroll
         for (int k = 0; k < PGW; k++) {
             if (!pv[k]) continue;
