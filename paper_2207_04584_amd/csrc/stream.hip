@@ -146,10 +146,16 @@ int grid_channels_host(Plan& P, const void* host_values, int64_t ld, int32_t nch
     const size_t es = dtype == HG_F32 ? 4 : 2;
     const int64_t n = P.n, npix = P.npix;
     const int32_t blk = std::min(block, nchan);
-    const int64_t ldd = (blk + 7) / 8 * 8;  // device row stride: 16-byte aligned rows
     const int nb = (nchan + blk - 1) / blk;
     const bool direct = is_pinned(host_values) && is_pinned(host_out);
     const bool staged = !direct;
+    // Device row stride: 16-byte aligned rows for the kernel's vector
+    // loads, except when one block takes whole page-locked rows: then the
+    // rows keep the host's stride and go over in one linear copy (a 2-D copy
+    // of short rows runs far below the link's rate; unaligned rows take the
+    // kernel's scalar staging instead).
+    const bool linear = direct && nb == 1 && blk == ld;
+    const int64_t ldd = linear ? ld : (blk + 7) / 8 * 8;
     const size_t val_bytes = (size_t)std::max<int64_t>(n, 1) * ldd * es;
     const size_t out_bytes = (size_t)blk * npix * 4;
     if (P.opts.device_mem_cap > 0) {
@@ -225,6 +231,9 @@ int grid_channels_host(Plan& P, const void* host_values, int64_t ld, int32_t nch
             if (e == hipSuccess) {
                 if (staged)
                     e = hipMemcpyAsync(R.vals[s].p, R.pin_in[s], (size_t)n * ldd * es,
+                                       hipMemcpyHostToDevice, R.h2d);
+                else if (linear)
+                    e = hipMemcpyAsync(R.vals[s].p, vin, (size_t)n * ld * es,
                                        hipMemcpyHostToDevice, R.h2d);
                 else
                     e = hipMemcpy2DAsync(R.vals[s].p, (size_t)ldd * es, vin + (size_t)c0 * es,
