@@ -211,7 +211,7 @@ def run_drift(args):
                                "300x300 map at 1 arcmin, FWHM 3 arcmin, support 3 sigma, "
                                "1024 FP32 channels; step = setup + channels",
                    "n_samples": n, "channels": C, "map": [m["ny"], m["nx"]], "nnz": nnz,
-                   "entries": entries, "form": "fp32"},
+                   "entry_units": entries, "form": "fp32"},
         "channels_ms": ch_avg, "setup_ms": float(np.mean(setup_ms)),
         "channels_only_value": n * C / (ch_avg * 1e-3) / 1e9,
         "roofline": roof,

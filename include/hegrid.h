@@ -113,7 +113,9 @@ typedef struct {
     int64_t n_samples;   /* samples passed to setup                              */
     int64_t n_used;      /* samples inside the band of rings that can reach the map */
     int64_t nnz;         /* (pixel, sample) pairs in support                      */
-    int64_t n_entries;   /* (pixel group, sample) entries the channel kernel reads */
+    int64_t n_entries;   /* entry-block units the channel kernel reads: groups of
+                            four (pixel group, sample) entries, each (group, chunk)
+                            run padded to a whole unit                             */
     int64_t n_cells;     /* HEALPix cells in the band                             */
     int64_t total_slots; /* staged sample slots summed over tiles                 */
     int64_t device_bytes;/* device memory held by the plan                        */

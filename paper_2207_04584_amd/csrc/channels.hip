@@ -55,9 +55,10 @@ template <int FORM>
 struct Form {
     static constexpr int VB = FORM == FORM_F32 ? 4 : 2;   // bytes per staged value
     static constexpr int RB = CW * VB;                     // bytes per staged row
-    static constexpr int WB = FORM == FORM_F32 ? 16 : 32;  // weight bytes per unit
-    static constexpr int SB = FORM == FORM_F32 ? 4 : 16;   // slot bytes per unit
-    static constexpr int UPS = FORM == FORM_F32 ? 1 : 4;   // entries per unit
+    // a unit is a group of four entries of one pixel group: weights [pixel][entry]
+    static constexpr int WB = FORM == FORM_F32 ? 64 : 32;  // weight bytes per unit
+    static constexpr int SB = 16;                          // slot bytes per unit
+    static constexpr int UPS = 4;                          // entries per unit
 };
 
 // One staged chunk in LDS: `chunk` value rows, then the entry block (weights,
@@ -380,14 +381,14 @@ __device__ __attribute__((always_inline)) inline void grid_item(
             if (m.nrows > 3)
                 stage_row_f32<DT, VEC>(base + L.vals + row_slot(3) * F::RB, values, ld, nchan,
                                        c_lo, m.row3, lane, dma_rows);
-            const float4* w = (const float4*)ent_w + m.eb;
-            const uint32_t* sl = (const uint32_t*)ent_s + m.eb;
-            for (int i = wave * 64; i < m.ne; i += CH_THREADS) {
-                if (i + lane < m.ne) {
-                    dma16s(w + i, 16u * lane, base + L.ew + i * 16);
-                    dma4s(sl + i, 4u * lane, base + L.es + i * 4);
-                }
-            }
+            // a unit's weights are 64 bytes (four lanes), its slots 16 bytes (one lane)
+            const char* w = (const char*)ent_w + m.eb * 64;
+            for (int i = wave * 16; i < m.ne; i += CH_WAVES * 16)
+                if (i + (lane >> 2) < m.ne)
+                    dma16s(w + (int64_t)i * 64, 16u * lane, base + L.ew + i * 64);
+            const uint4* sl = (const uint4*)ent_s + m.eb;
+            for (int i = wave * 64; i < m.ne; i += CH_THREADS)
+                if (i + lane < m.ne) dma16s(sl + i, 16u * lane, base + L.es + i * 16);
         } else {
             if (m.nrows > 0)
                 stage_rows_16<VEC>(base + L.vals + row_slot(0) * F::RB, values, ld, nchan, c_lo,
@@ -414,7 +415,8 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         int k = 0;
         if (FORM == FORM_F32) {
             if (dma_rows) k += m.nrows;
-            if (m.ne > wave * 64) k += 2 * ((m.ne - wave * 64 + CH_THREADS - 1) / CH_THREADS);
+            if (m.ne > wave * 16) k += (m.ne - wave * 16 + CH_WAVES * 16 - 1) / (CH_WAVES * 16);
+            if (m.ne > wave * 64) k += (m.ne - wave * 64 + CH_THREADS - 1) / CH_THREADS;
         } else {
             if (dma_rows && m.nrows > 0) k += m.nrows;
             if (m.ne > wave * 32) k += (m.ne - wave * 32 + CH_WAVES * 32 - 1) / (CH_WAVES * 32);
@@ -486,17 +488,26 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         // `chunk` slots each, lane i holding the run's i-th), all read before
         // any is used so that the LDS latency is paid once per chunk.  Ranges
         // and slots are wave-uniform and go to scalar registers by v_readlane.
+        // FP32 form: offsets count entries, 4 x (first unit) + (entries of
+        // padding in the run's last unit); 16-bit forms: offsets count units,
+        // and whole units are multiplied.  eK: first unit, nK: entries to do.
         const uint32_t po_lane = po[lane];
         const int po_end = __builtin_amdgcn_readfirstlane((int)po[TILE_PGS]);
-        int eK[PGW], e1K[PGW];
+        int eK[PGW], nK[PGW];
         uint32_t slK[PGW];
 #pragma unroll
         for (int k = 0; k < PGW; k++) {
             const int lp = lys[k] * TILE_PGX + lxs[k];
-            eK[k] = (int)__builtin_amdgcn_readlane(po_lane, lp);
-            e1K[k] = lp + 1 < TILE_PGS ? (int)__builtin_amdgcn_readlane(po_lane, lp + 1) : po_end;
-            const int n = (FORM == FORM_F32 ? 1 : 4) * (e1K[k] - eK[k]);
-            slK[k] = es[(FORM == FORM_F32 ? 1 : 4) * eK[k] + (lane < n ? lane : 0)];
+            const int a = (int)__builtin_amdgcn_readlane(po_lane, lp);
+            const int b = lp + 1 < TILE_PGS ? (int)__builtin_amdgcn_readlane(po_lane, lp + 1) : po_end;
+            if (FORM == FORM_F32) {
+                eK[k] = a >> 2;
+                nK[k] = (b & ~3) - (a & ~3) - (a & 3);
+            } else {
+                eK[k] = a;
+                nK[k] = 4 * (b - a);
+            }
+            slK[k] = es[4 * eK[k] + (lane < nK[k] ? lane : 0)];
         }
         // A wave holding more than its share of this chunk's entries gets a
         // higher issue priority: the chunk ends with its longest wave, which
@@ -505,8 +516,9 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         {
             int mine = 0;
 #pragma unroll
-            for (int k = 0; k < PGW; k++) mine += pv[k] ? e1K[k] - eK[k] : 0;
-            const int share = mine * CH_WAVES;  // against po_end, the chunk's total
+            for (int k = 0; k < PGW; k++) mine += pv[k] ? nK[k] : 0;
+            // against the chunk's total entries (padding included)
+            const int share = mine * CH_WAVES / (FORM == FORM_F32 ? 1 : 4);
             if (share >= 2 * po_end)
                 __builtin_amdgcn_s_setprio(3);
             else if (2 * share >= 3 * po_end)
@@ -519,8 +531,8 @@ __device__ __attribute__((always_inline)) inline void grid_item(
 #pragma unroll
         for (int k = 0; k < PGW; k++) {
             if (!pv[k]) continue;
-            const int e = eK[k], e1 = e1K[k];
-            if (e == e1) continue;
+            const int e = eK[k], n = nK[k];
+            if (n == 0) continue;
             v4f part[G];
 #pragma unroll
             for (int g = 0; g < G; g++) part[g] = (v4f){0.f, 0.f, 0.f, 0.f};
@@ -528,11 +540,12 @@ __device__ __attribute__((always_inline)) inline void grid_item(
             if (FORM == FORM_F32) {
                 // Each entry's slot comes from v_readlane into a scalar
                 // register, so the value read needs no second LDS round trip.
-                // Entries go four at a time so that the eight LDS reads of a
-                // step are in flight together ahead of its sixteen MFMAs.
-                const int n = e1 - e;
+                // Entries go a unit (four) at a time: one 16-byte read brings
+                // this lane's pixel's four weights, and the step's five LDS
+                // reads are in flight together ahead of its sixteen MFMAs.  A
+                // run's last unit multiplies only its real entries.
                 const uint32_t slot_lane = slK[k];
-                const float* ewq = (const float*)ew + e * 4 + q;
+                const char* wq = ew + e * F::WB + q * 16;
                 const char* vl = vals + lane * 16;
                 int j = 0;
                 for (; j + 4 <= n; j += 4) {
@@ -540,30 +553,35 @@ __device__ __attribute__((always_inline)) inline void grid_item(
                     uint32_t s1 = __builtin_amdgcn_readlane(slot_lane, j + 1);
                     uint32_t s2 = __builtin_amdgcn_readlane(slot_lane, j + 2);
                     uint32_t s3 = __builtin_amdgcn_readlane(slot_lane, j + 3);
-                    float a0 = ewq[j * 4], a1 = ewq[j * 4 + 4], a2 = ewq[j * 4 + 8],
-                          a3 = ewq[j * 4 + 12];
+                    const float4 a = *(const float4*)(wq + j * 16);
                     float4 v0 = *(const float4*)(vl + s0 * F::RB);
                     float4 v1 = *(const float4*)(vl + s1 * F::RB);
                     float4 v2 = *(const float4*)(vl + s2 * F::RB);
                     float4 v3 = *(const float4*)(vl + s3 * F::RB);
-                    mfma4_f32(part, a0, v0);
-                    mfma4_f32(part, a1, v1);
-                    mfma4_f32(part, a2, v2);
-                    mfma4_f32(part, a3, v3);
+                    mfma4_f32(part, a.x, v0);
+                    mfma4_f32(part, a.y, v1);
+                    mfma4_f32(part, a.z, v2);
+                    mfma4_f32(part, a.w, v3);
                     // schedule: all LDS reads of the step, then its MFMAs
-                    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
                     __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
                 }
-                for (; j < n; j++) {
-                    uint32_t sj = __builtin_amdgcn_readlane(slot_lane, j);
-                    float a0 = ewq[j * 4];
-                    float4 v0 = *(const float4*)(vl + sj * F::RB);
-                    mfma4_f32(part, a0, v0);
+                if (j < n) {
+                    const int r = n - j;  // 1..3 entries left
+                    const float4 a = *(const float4*)(wq + j * 16);
+                    mfma4_f32(part, a.x,
+                              *(const float4*)(vl + __builtin_amdgcn_readlane(slot_lane, j) * F::RB));
+                    if (r > 1)
+                        mfma4_f32(part, a.y, *(const float4*)(vl + __builtin_amdgcn_readlane(
+                                                                       slot_lane, j + 1) * F::RB));
+                    if (r > 2)
+                        mfma4_f32(part, a.z, *(const float4*)(vl + __builtin_amdgcn_readlane(
+                                                                       slot_lane, j + 2) * F::RB));
                 }
             } else {
                 // groups of four entries, slots picked by v_readlane
                 const uint32_t slot_lane = slK[k];
-                for (int t = 0; t < e1 - e; t++) {
+                for (int t = 0; t < n / 4; t++) {
                     uint32_t s0 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 0);
                     uint32_t s1 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 1);
                     uint32_t s2 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 2);

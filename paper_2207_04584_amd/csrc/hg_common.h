@@ -196,8 +196,8 @@ struct Plan {
     DevBuf tile_blk;     // int64 [ntiles+1] first block of each tile
     DevBuf blk_base;     // int64 [n_blocks+1] first entry of each block
     DevBuf blk_pgoff;    // uint16 [n_blocks][PGOFF_STRIDE] per-group offsets in the block
-    DevBuf e2_w;         // float4 [entries] weights, block order
-    DevBuf e2_s;         // uint32 [entries] slot within the chunk, block order
+    DevBuf e2_w;         // float [units][4 pixels][4 entries] weights, block order
+    DevBuf e2_s;         // uint4 [units] chunk-local slots of a unit's four entries
     // precision forms: entries in groups of four per pixel group (the MFMA K)
     DevBuf e3_w;         // uint16 [groups][4 pixels][4 entries] BF16 / FP16 weights
     DevBuf e3_s;         // uint4  [groups] chunk-local slots of the four entries

@@ -884,15 +884,18 @@ __global__ __launch_bounds__(256) void k_block_meta(
     if (b >= n_blocks) return;  // uniform per wave
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
-    int x = r.n;  // inclusive scan over the 64 groups
+    // units are groups of four entries; a group's run starts on a unit and
+    // its last unit is padded: po[l] = 4 x (first unit) + (padding entries)
+    const int ng = (r.n + 3) >> 2;
+    int x = ng;  // inclusive scan over the 64 groups
     for (int o = 1; o < 64; o <<= 1) {
         int y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
     uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
-    po[lane] = (uint16_t)(x - r.n);
+    po[lane] = (uint16_t)(4 * (x - ng) + (4 * ng - r.n));
     if (lane == 63) {
-        po[64] = (uint16_t)x;
+        po[64] = (uint16_t)(4 * x);
         po[65] = po[66] = po[67] = 0;
         blk_cnt[b] = x;
     }
@@ -912,15 +915,29 @@ __device__ inline int group_of_unit(const uint16_t* po, int i) {
     return lo;
 }
 
+// group_of_unit for offsets in entries with the run's padding in the low two
+// bits (the FP32 form's blocks): the last l with po[l] / 4 <= i.
+__device__ inline int group_of_unit_x4(const uint16_t* po, int i) {
+    int lo = 0, hi = TILE_PGS - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (((int)po[mid] >> 2) <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // One wave per block: lane l knows group l's run (first entry, count); the
-// block's units are then copied flat, lane i taking unit i (coalesced writes).
+// block's units are then written flat, lane i taking unit i (coalesced writes).
 __global__ __launch_bounds__(256) void k_block_fill(
     int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks, int32_t chunk,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
     const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
     const uint32_t* __restrict__ ent_slot, const float4* __restrict__ ent_w,
     const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
-    float4* __restrict__ e2_w, uint32_t* __restrict__ e2_s) {
+    float4* __restrict__ e2_w, uint4* __restrict__ e2_s) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
@@ -928,19 +945,35 @@ __global__ __launch_bounds__(256) void k_block_fill(
                              pg_base);
     const uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
     const int64_t base = blk_base[b];
-    const int ne = (int)(blk_base[b + 1] - base);
+    const int nu = (int)(blk_base[b + 1] - base);  // units (groups of four entries)
     const uint32_t s0 = (uint32_t)(r.c * chunk);
     const uint32_t src_lo = (uint32_t)r.src, src_hi = (uint32_t)((uint64_t)r.src >> 32);
-    for (int i0 = 0; i0 < ne; i0 += 64) {  // same trip count on every lane
+    for (int i0 = 0; i0 < nu; i0 += 64) {  // same trip count on every lane; lane i: unit i
         const int i = i0 + lane;
-        const int lp = i < ne ? group_of_unit(po, i) : 0;
+        const int lp = i < nu ? group_of_unit_x4(po, i) : 0;
         const int64_t src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)src_hi, lp, 64) << 32) |
-                                      (uint32_t)__shfl((int)src_lo, lp, 64)) +
-                            (i - (int)po[lp]);
-        if (i < ne) {
-            e2_w[base + i] = ent_w[src];
-            e2_s[base + i] = (ent_slot[src] & SLOT_MASK) - s0;
+                                      (uint32_t)__shfl((int)src_lo, lp, 64));
+        const int n = __shfl(r.n, lp, 64);
+        if (i >= nu) continue;
+        const int t = i - ((int)po[lp] >> 2);  // unit index within the run
+        uint32_t sl[4];
+        float w[4][4];  // [entry][pixel]
+        for (int k = 0; k < 4; k++) {
+            const int e = 4 * t + k;
+            const bool real = e < n;
+            const int ee = real ? e : n - 1;
+            sl[k] = (ent_slot[src + ee] & SLOT_MASK) - s0;
+            const float4 wv = ent_w[src + ee];
+            w[k][0] = real ? wv.x : 0.f;
+            w[k][1] = real ? wv.y : 0.f;
+            w[k][2] = real ? wv.z : 0.f;
+            w[k][3] = real ? wv.w : 0.f;
         }
+        e2_s[base + i] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
+        // [pixel q][entry k]: pixel q's weights for the unit's four entries
+        float4* wd = e2_w + (base + i) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; q++) wd[q] = make_float4(w[0][q], w[1][q], w[2][q], w[3][q]);
     }
 }
 
@@ -1276,9 +1309,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     }
     if (P.opts.device_mem_cap > 0) {
         // slot list, entries, chunk pointers, and the slot compaction's
-        // transient arrays (flag, new position, compacted list: 16 B a slot)
+        // transient arrays (flag, new position, compacted list: 16 B a slot);
+        // the entry blocks pad each (group, chunk) run to four entries
         size_t need = (size_t)P.total_slots * (4 + 16) + (size_t)P.ent_cap * 20 +
-                      (size_t)P.chunk_ptrs * 4;
+                      (size_t)P.chunk_ptrs * (4 + 60);
         size_t have = 0;
         for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                           &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.cp_base, &P.pix_count, &P.pix_W,
@@ -1426,8 +1460,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
             HG_STEP(hipGetLastError());
         }
     } else {
-        HG_STEP(dev_alloc(P.e2_w, (size_t)(n_ent ? n_ent : 1) * 16));
-        HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 4));
+        HG_STEP(dev_alloc(P.e2_w, (size_t)(n_ent ? n_ent : 1) * 64));
+        HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 16));
         if (P.n_blocks > 0) {
             hipLaunchKernelGGL(k_block_fill, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s,
                                P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks, P.chunk,
@@ -1435,7 +1469,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                (const uint32_t*)P.chunk_ptr.p, (const int64_t*)P.pg_base.p,
                                (const uint32_t*)P.ent_slot.p, (const float4*)P.ent_w.p,
                                (const int64_t*)P.blk_base.p, (const uint16_t*)P.blk_pgoff.p,
-                               (float4*)P.e2_w.p, (uint32_t*)P.e2_s.p);
+                               (float4*)P.e2_w.p, (uint4*)P.e2_s.p);
             HG_STEP(hipGetLastError());
         }
     }
