@@ -58,5 +58,20 @@ def build():
     return LIB
 
 
+def build_c_example():
+    """The host program that uses the boundary from C-style code
+    (tests/c_abi/hg_c_example.cpp), linked against the library with an rpath
+    to it; run by the GPU tests."""
+    src = os.path.join(ROOT, "tests", "c_abi", "hg_c_example.cpp")
+    exe = os.path.join(ROOT, "tests", "c_abi", "hg_c_example")
+    rpath = os.path.relpath(PKG, os.path.dirname(exe))
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-O2", "-I", os.path.join(ROOT, "include"), src,
+           "-o", exe, "-L", PKG, "-lhegrid", f"-Wl,-rpath,$ORIGIN/{rpath}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C example failed to build:\n{r.stdout}\n{r.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     print(build())
