@@ -128,24 +128,50 @@ struct RowInfo {
 };
 
 // 1. binning ------------------------------------------------------------------
+// counter[k] += 1 for every active lane with valid set, one atomic per
+// distinct key in the wave (consecutive samples of a scan share cells, and
+// per-lane atomics on one address serialise).  Returns each such lane the
+// counter's old value plus its rank among the wave's lanes with the same key:
+// distinct values, as separate atomics would give, in another order.
+__device__ inline uint32_t wave_atomic_inc(uint32_t* counter, uint32_t k, bool valid) {
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(valid);
+    uint32_t result = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t kl = (uint32_t)__shfl((int)k, leader, 64);
+        const uint64_t same = __ballot(valid && k == kl) & todo;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counter[kl], (uint32_t)__popcll(same));
+        base = (uint32_t)__shfl((int)base, leader, 64);
+        if ((same >> lane) & 1ull) result = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
+    return result;
+}
+
 __global__ void k_bin(const double* __restrict__ ra_deg, const double* __restrict__ dec_deg,
                       int64_t n, int64_t nside, int64_t cell_base, int64_t n_cells,
                       uint32_t* __restrict__ key, uint32_t* __restrict__ cnt, int* flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double a = ra_deg[i], d = dec_deg[i];
-    if (!isfinite(a) || !isfinite(d) || fabs(d) > 90.0) {
-        atomicOr(flag, 1);
-        key[i] = BAD_KEY;
-        return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = false;
+    uint32_t c32 = 0;
+    if (i < n) {
+        const double a = ra_deg[i], d = dec_deg[i];
+        if (!isfinite(a) || !isfinite(d) || fabs(d) > 90.0) {
+            atomicOr(flag, 1);
+            key[i] = BAD_KEY;
+        } else {
+            const int64_t c = hp_ang2pix(nside, sin(d * kDeg), a * kDeg) - cell_base;
+            if (c < 0 || c >= n_cells) {
+                key[i] = BAD_KEY;
+            } else {
+                key[i] = c32 = (uint32_t)c;
+                valid = true;
+            }
+        }
     }
-    int64_t c = hp_ang2pix(nside, sin(d * kDeg), a * kDeg) - cell_base;
-    if (c < 0 || c >= n_cells) {
-        key[i] = BAD_KEY;
-        return;
-    }
-    key[i] = (uint32_t)c;
-    atomicAdd(&cnt[c], 1u);
+    (void)wave_atomic_inc(cnt, c32, valid);
 }
 
 __global__ void k_ang2pix(const double* __restrict__ ra_deg, const double* __restrict__ dec_deg,
@@ -159,12 +185,11 @@ __global__ void k_ang2pix(const double* __restrict__ ra_deg, const double* __res
 // 2. sort ------------------------------------------------------------------------
 __global__ void k_scatter(const uint32_t* __restrict__ key, int64_t n, uint32_t* __restrict__ cursor,
                           uint32_t* __restrict__ srt_idx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t c = key[i];
-    if (c == BAD_KEY) return;
-    uint32_t pos = atomicAdd(&cursor[c], 1u);
-    srt_idx[pos] = (uint32_t)i;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t c = i < n ? key[i] : BAD_KEY;
+    const bool valid = c != BAD_KEY;
+    const uint32_t pos = wave_atomic_inc(cursor, valid ? c : 0u, valid);
+    if (valid) srt_idx[pos] = (uint32_t)i;
 }
 
 __device__ inline void sift_down(uint32_t* v, uint32_t root, uint32_t end) {
