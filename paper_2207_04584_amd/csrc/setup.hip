@@ -107,9 +107,48 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_final(const Tin* in, int64_t n,
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = run;
 }
 
+// Short arrays in one workgroup: tiles of SCAN_B scanned in turn with a
+// running carry (three launches of a few microseconds each otherwise).
+constexpr int64_t SCAN_ONE_MAX = 8 * SCAN_B;
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(SCAN_T) void k_scan_one(const Tin* in, int64_t n, Tout* out) {
+    __shared__ Tout vals[SCAN_B];
+    __shared__ Tout sh[SCAN_T / 64 + 1];
+    Tout carry = 0;
+    for (int64_t base = 0; base < n || base == 0; base += SCAN_B) {
+        for (int k = 0; k < SCAN_I; k++) {
+            int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+            vals[k * SCAN_T + threadIdx.x] = i < n ? (Tout)in[i] : (Tout)0;
+        }
+        __syncthreads();
+        Tout sum = 0;
+        for (int k = 0; k < SCAN_I; k++) sum += vals[threadIdx.x * SCAN_I + k];
+        Tout tot;
+        Tout run = block_exclusive_scan<Tout>(sum, sh, tot) + carry;
+        for (int k = 0; k < SCAN_I; k++) {
+            Tout v = vals[threadIdx.x * SCAN_I + k];
+            vals[threadIdx.x * SCAN_I + k] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (int k = 0; k < SCAN_I; k++) {
+            int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
+            if (i < n) out[i] = vals[k * SCAN_T + threadIdx.x];
+        }
+        carry += tot;
+        __syncthreads();  // vals is refilled by the next tile
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 // scratch must hold ceil(n / SCAN_B) Tout
 template <typename Tin, typename Tout>
 hipError_t scan_exclusive(const Tin* in, int64_t n, Tout* out, Tout* scratch, hipStream_t s) {
+    if (n <= SCAN_ONE_MAX) {
+        hipLaunchKernelGGL((k_scan_one<Tin, Tout>), dim3(1), dim3(SCAN_T), 0, s, in, n, out);
+        return hipGetLastError();
+    }
     int64_t nb = (n + SCAN_B - 1) / SCAN_B;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n,
