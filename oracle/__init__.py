@@ -32,6 +32,10 @@ class _Map(ctypes.Structure):
         ("ddec_deg", ctypes.c_double),
         ("nx", ctypes.c_int32),
         ("ny", ctypes.c_int32),
+        ("proj", ctypes.c_int32),
+        ("nside", ctypes.c_int32),
+        ("ring0", ctypes.c_int32),
+        ("pix0", ctypes.c_int32),
     ]
 
 
@@ -70,6 +74,8 @@ def _load():
         lib.oracle_neighbours_k.argtypes = [i64, P, P, ctypes.POINTER(_Map), f64, f64, i32, f64,
                                             f64, i32, P, i64, P, P, P, i64, P]
         lib.oracle_neighbours_k.restype = ctypes.c_int
+        lib.oracle_cell_centres.argtypes = [ctypes.POINTER(_Map), P, P, P]
+        lib.oracle_cell_centres.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -79,8 +85,27 @@ def _ptr(a):
 
 
 def _mk_map(m):
+    """A map dict: plate carree (ra0_deg, dec0_deg, dra_deg, ddec_deg, nx, ny)
+    or, with proj = 1, a HEALPix patch (nside, ring0, pix0, nx, ny)."""
+    if int(m.get("proj", 0)) == 1:
+        return _Map(0.0, 0.0, 0.0, 0.0, int(m["nx"]), int(m["ny"]), 1, int(m["nside"]),
+                    int(m["ring0"]), int(m["pix0"]))
     return _Map(float(m["ra0_deg"]), float(m["dec0_deg"]), float(m["dra_deg"]),
-                float(m["ddec_deg"]), int(m["nx"]), int(m["ny"]))
+                float(m["ddec_deg"]), int(m["nx"]), int(m["ny"]), 0, 0, 0, 0)
+
+
+def cell_centres(m):
+    """(ra, dec) radians [ny*nx] of the map's cell centres and, for a HEALPix
+    patch, the cells' RING numbers (else -1)."""
+    lib = _load()
+    mm = _mk_map(m)
+    n = mm.nx * mm.ny
+    ra, dec = np.empty(n), np.empty(n)
+    ids = np.empty(n, dtype=np.int64)
+    rc = lib.oracle_cell_centres(ctypes.byref(mm), _ptr(ra), _ptr(dec), _ptr(ids))
+    if rc:
+        raise ValueError(f"oracle_cell_centres failed ({rc})")
+    return ra, dec, ids
 
 
 def _coords(ra_deg, dec_deg):

@@ -31,7 +31,11 @@
  *     on [0, pi]; then d = 2 asin(min(1, sqrt(h)));
  *   - grid: plate carree in coordinate degrees; pixel (i, j) has centre
  *     RA = ra0 + (i - (nx-1)/2) dra, Dec = dec0 + (j - (ny-1)/2) ddec,
- *     flat index p = j*nx + i, output layout [channel][j][i];
+ *     flat index p = j*nx + i, output layout [channel][j][i]; or (proj 1) a
+ *     patch of a HEALPix RING grid in its equatorial belt (Eq. 1 leaves the
+ *     cell set open): cell (i, j) is RING pixel number
+ *     2 ns (ns - 1) + 4 ns (r - ns) + (pix0 + i) mod 4 ns of ring r = ring0 - j,
+ *     centred where the HEALPix layout puts that pixel (or_healpix_centre);
  *   - a cell with no sample in its support gets V = NaN, count 0, W = 0;
  *   - sums run over the neighbours in ascending original sample index.
  *
@@ -60,9 +64,34 @@ typedef struct {
     double ra0_deg, dec0_deg; /* map centre */
     double dra_deg, ddec_deg; /* pixel spacing in coordinate degrees */
     int32_t nx, ny;
+    int32_t proj;              /* 0 plate carree, 1 HEALPix patch */
+    int32_t nside, ring0, pix0; /* HEALPix patch: resolution, ring of row 0, pixel of column 0 */
 } or_map;
 
+static const double PI = 3.14159265358979323846;
 static const double DEG = 3.14159265358979323846 / 180.0;
+
+/* The RING number of cell (i, j) of a HEALPix patch: the ring-0-based
+   numbering runs ring by ring from the north pole; the north cap's rings
+   1 .. ns-1 hold 4, 8, ..., 4 (ns-1) pixels, 2 ns (ns - 1) in all, and each
+   belt ring holds 4 ns. */
+static int64_t or_healpix_cell(const or_map* m, int64_t i, int64_t j) {
+    int64_t ns = m->nside, r = m->ring0 - j;
+    return 2 * ns * (ns - 1) + 4 * ns * (r - ns) + (m->pix0 + i) % (4 * ns);
+}
+
+/* Centre of belt pixel pix at resolution ns (Gorski et al. 2005): its ring r
+   and place k in the ring follow from the count above; the belt rings are
+   equally spaced in z = sin Dec from 2/3 (ring ns) to -2/3 (ring 3 ns), and
+   a ring's 4 ns pixels are equally spaced in RA from 0, or from half a pixel
+   on the rings where r - ns is even. */
+static void or_healpix_centre(int64_t ns, int64_t pix, double* ra, double* dec) {
+    int64_t q = pix - 2 * ns * (ns - 1);
+    int64_t r = ns + q / (4 * ns), k = q % (4 * ns);
+    double half = ((r - ns) % 2 == 0) ? 0.5 : 0.0;
+    *dec = asin((double)(4 * ns - 2 * r) / (double)(3 * ns));
+    *ra = ((double)k + half) * (PI / (double)(2 * ns));
+}
 
 /* Exact widening of one stored value to FP64. */
 static double or_decode(const void* base, int64_t off, int dtype) {
@@ -97,6 +126,10 @@ static double or_decode(const void* base, int64_t off, int dtype) {
 
 static void or_pixel_centre(const or_map* m, int64_t p, double* ra, double* dec) {
     int64_t i = p % m->nx, j = p / m->nx;
+    if (m->proj == 1) {
+        or_healpix_centre(m->nside, or_healpix_cell(m, i, j), ra, dec);
+        return;
+    }
     *ra = (m->ra0_deg + ((double)i - (m->nx - 1) / 2.0) * m->dra_deg) * DEG;
     *dec = (m->dec0_deg + ((double)j - (m->ny - 1) / 2.0) * m->ddec_deg) * DEG;
 }
@@ -202,7 +235,7 @@ static int or_ctx_init(or_ctx* c, int64_t n, const double* ra_deg, const double*
 static double or_weight(const or_ctx* c, double d, double ra_p, double dec_p, double ra_n,
                         double dec_n) {
     if (c->ktype == 1) {
-        double x = 3.14159265358979323846 * d / c->kb;
+        double x = PI * d / c->kb;
         double sinc = x == 0.0 ? 1.0 : sin(x) / x;
         return sinc * exp(-(d / c->ka) * (d / c->ka));
     }
@@ -266,8 +299,25 @@ static int or_cell(or_ctx* c, double ra_p, double dec_p, int64_t* cnt) {
 }
 
 static int or_check_map(const or_map* m) {
-    if (!m || m->nx <= 0 || m->ny <= 0 || !(m->dra_deg > 0) || !(m->ddec_deg > 0)) return 0;
-    return 1;
+    if (!m || m->nx <= 0 || m->ny <= 0) return 0;
+    if (m->proj == 1) {
+        int64_t ns = m->nside;
+        return ns >= 1 && m->nx <= 4 * ns && m->pix0 >= 0 && m->pix0 < 4 * ns &&
+               m->ring0 - (m->ny - 1) >= ns && m->ring0 <= 3 * ns;
+    }
+    return m->proj == 0 && m->dra_deg > 0 && m->ddec_deg > 0;
+}
+
+/* Centres (radians) of all nx*ny cells, flat index j*nx + i, and for a
+   HEALPix patch their RING numbers (ids may be NULL). */
+int oracle_cell_centres(const or_map* m, double* ra, double* dec, int64_t* ids) {
+    if (!or_check_map(m) || !ra || !dec) return OR_ERR_ARG;
+    int64_t ncell = (int64_t)m->nx * m->ny;
+    for (int64_t p = 0; p < ncell; p++) {
+        or_pixel_centre(m, p, &ra[p], &dec[p]);
+        if (ids) ids[p] = m->proj == 1 ? or_healpix_cell(m, p % m->nx, p / m->nx) : -1;
+    }
+    return OR_OK;
 }
 
 /*

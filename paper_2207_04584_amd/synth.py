@@ -36,6 +36,22 @@ def make_map(ra0, dec0, nx, ny, pix_arcmin=1.0):
             "ddec_deg": pix_arcmin * ARCMIN, "nx": int(nx), "ny": int(ny)}
 
 
+def healpix_patch(ra0, dec0, width_deg, height_deg, nside):
+    """A HEALPix target map over a width x height box around (ra0, dec0), in
+    the equatorial belt: the rings whose centres' z = 4/3 - 2r/(3 nside) fall
+    in the box's Dec range (rows run south to north, so ring0 is the southern
+    one) and, in each ring, the pixels over its RA range (spacing 360/(4 nside)
+    deg).  The map dict the library and the reference gridder take."""
+    z_lo = math.sin(math.radians(dec0 - 0.5 * height_deg))
+    z_hi = math.sin(math.radians(dec0 + 0.5 * height_deg))
+    r_north = math.ceil((4.0 / 3.0 - z_hi) * 1.5 * nside)
+    r_south = math.floor((4.0 / 3.0 - z_lo) * 1.5 * nside)
+    dphi = 360.0 / (4 * nside)
+    return {"proj": 1, "nside": int(nside), "ring0": int(r_south),
+            "pix0": int(math.floor((ra0 - 0.5 * width_deg) / dphi)) % (4 * nside),
+            "nx": int(round(width_deg / dphi)), "ny": int(r_south - r_north + 1)}
+
+
 def make_kernel(fwhm_arcmin, support_sigmas=3.0):
     fwhm = fwhm_arcmin * ARCMIN
     return {"fwhm_deg": fwhm, "support_deg": support_sigmas * fwhm * FWHM_TO_SIGMA}

@@ -371,3 +371,87 @@ def test_kernel_shape_arguments_are_checked():
                   {"type": 3}):
         with pytest.raises(ValueError):
             oracle.grid([0.0], [0.0], np.zeros((1, 1)), "f64", m, 0.05, 0.1, kernel=shape)
+
+
+# HEALPix target maps: cells are the pixels of a patch of a HEALPix RING grid
+# (row j = ring ring0 - j, column i = pixel (pix0 + i) mod 4 nside of the ring)
+
+HPX_PATCHES = [(1, 3, 0, 4, 3), (8, 24, 0, 32, 17), (64, 150, 250, 20, 7), (2048, 3000, 17, 9, 4)]
+
+
+def hpx(nside, ring0, pix0, nx, ny):
+    return dict(proj=1, nside=nside, ring0=ring0, pix0=pix0, nx=nx, ny=ny)
+
+
+@pytest.mark.parametrize("nside,ring0,pix0,nx,ny", HPX_PATCHES)
+def test_healpix_patch_centres_match_the_healpix_reference(nside, ring0, pix0, nx, ny):
+    """Centres and RING numbers of the oracle's patch cells against the
+    separately written (and separately pinned) numpy HEALPix reference: each
+    centre is that pixel's centre, and lies in the pixel it names."""
+    from oracle import healpix_ref
+    ra, dec, ids = oracle.cell_centres(hpx(nside, ring0, pix0, nx, ny))
+    z, phi = healpix_ref.pix2ang(nside, ids)
+    np.testing.assert_allclose(np.sin(dec), z, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ra, phi, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(healpix_ref.ang2pix(nside, np.sin(dec), ra), ids)
+    # rows are rings ring0, ring0 - 1, ... (northward); columns run eastward
+    first = np.array([healpix_ref.ring_info(nside, ring0 - j)[0] for j in range(ny)])
+    want = first[:, None] + (pix0 + np.arange(nx))[None, :] % (4 * nside)
+    np.testing.assert_array_equal(ids.reshape(ny, nx), want)
+
+
+def test_healpix_base_pixels_closed_form():
+    """nside = 1: the twelve base pixels, all in the belt (rings 1..3), at
+    z = 2/3, 0, -2/3; rings 1 and 3 start half a pixel (pi/4) east of RA 0."""
+    ra, dec, ids = oracle.cell_centres(hpx(1, 3, 0, 4, 3))
+    np.testing.assert_array_equal(ids, [8, 9, 10, 11, 4, 5, 6, 7, 0, 1, 2, 3])
+    z = np.sin(dec).reshape(3, 4)
+    np.testing.assert_allclose(z, np.repeat([[-2 / 3], [0.0], [2 / 3]], 4, axis=1), atol=1e-15)
+    k = np.arange(4)
+    np.testing.assert_allclose(ra.reshape(3, 4),
+                               [np.pi / 4 + k * np.pi / 2, k * np.pi / 2, np.pi / 4 + k * np.pi / 2],
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("ktype", [0, 2])
+def test_healpix_map_gridding_is_cellwise_plate_carree(ktype):
+    """Gridding onto a HEALPix patch equals gridding each of its cells alone
+    as a 1 x 1 plate-carree map centred there (the map only fixes the cell
+    centres); for the Gaussian and the elliptical kernel."""
+    rng = np.random.default_rng(41 + ktype)
+    m = hpx(512, 700, 100, 8, 6)  # 6.9' pixels near (17.6 deg, 25 deg)
+    ra_c, dec_c, _ = oracle.cell_centres(m)
+    n = 3000
+    ra = np.degrees(ra_c.mean()) + (rng.random(n) - 0.5) * 1.6
+    dec = np.degrees(dec_c.mean()) + (rng.random(n) - 0.5) * 1.0
+    vals = rng.normal(size=(n, 3))
+    kern = None if ktype == 0 else dict(type=2, p1=6.0 * ARC, p2=35.0)
+    fwhm, R = 10.0 * ARC, 13.0 * ARC
+    V, c, W, margin = oracle.grid(ra, dec, vals, "f64", m, fwhm, R, kernel=kern)
+    assert margin > 1e-9 and (c > 0).all() and c.min() > 20
+    for p in range(ra_c.size):
+        one = dict(ra0_deg=np.degrees(ra_c[p]), dec0_deg=np.degrees(dec_c[p]), dra_deg=ARC,
+                   ddec_deg=ARC, nx=1, ny=1)
+        V1, c1, W1, _ = oracle.grid(ra, dec, vals, "f64", one, fwhm, R, kernel=kern)
+        assert c1[0] == c[p]
+        np.testing.assert_allclose(W1[0], W[p], rtol=1e-12)
+        np.testing.assert_allclose(V1[:, 0], V[:, p], rtol=1e-10, atol=1e-12)
+
+
+def test_healpix_patch_arguments_are_checked():
+    with pytest.raises(ValueError):
+        oracle.cell_centres(hpx(8, 24, 0, 33, 2))  # nx > 4 nside
+    with pytest.raises(ValueError):
+        oracle.cell_centres(hpx(8, 10, 0, 4, 4))  # ring 7 is in the polar cap
+
+
+def test_healpix_patch_recipe_covers_its_box():
+    """The input recipe's HEALPix patch for a 5 x 5 deg box: its rings and
+    columns lie in the box and reach its edges to within one spacing."""
+    m = synth.healpix_patch(180.0, 30.0, 5.0, 5.0, 4096)
+    ra, dec, ids = oracle.cell_centres(m)
+    ra, dec = np.degrees(ra), np.degrees(dec)
+    dphi = 360.0 / (4 * 4096)
+    assert 27.5 <= dec.min() < 27.5 + 0.02 and 32.5 - 0.02 < dec.max() <= 32.5
+    assert 177.5 - dphi <= ra.min() < 177.5 + dphi and 182.5 - dphi < ra.max() <= 182.5 + dphi
+    assert len(np.unique(ids)) == m["nx"] * m["ny"]
