@@ -8,6 +8,11 @@ path on that batch: grid_setup (FP64 binning, sort, look-up table, planner,
 neighbour gather) + grid_channels (all 1024 channels) + finish, with
 coordinates and values already resident in HBM.
 
+--map healpix / --kernel sinc|elliptical (drift workload): the same samples
+gridded onto a HEALPix target patch over the same 5 x 5 degrees (nside 4096,
+0.86 arcmin pixels, 228 x 465 cells) and/or with a Gauss-tapered sinc or an
+elliptical Gaussian kernel.
+
 --workload batch: 64 independent fields (sample counts log-uniform in
 1e4..2e6, square maps of side 32..512 at 1 arcmin, 256 / 1024 / 4096 FP16
 channels, FWHM U(2, 5) arcmin).  One step = hg_batch_create (every field's
@@ -29,7 +34,8 @@ threads with a stream each (setup, then channel kernel, per field), the
 paper's style of pipeline, to set the batched form against.
 
     python bench.py [--workload drift|batch|paper|literal|fifo] [--steps K] [--warmup W]
-                    [--gpus 1] [--streams S]
+                    [--gpus 1] [--streams S] [--map car|healpix]
+                    [--kernel gauss|sinc|elliptical]
                     [--precision mfma|fp32] [--no-cpu-baseline]
 
 Prints one JSON line.  value = sum(N * C) / (seconds per step) in G
@@ -68,7 +74,7 @@ def cpu_baseline(f, vals_host, n_pix, seed=7):
     pix = np.sort(np.random.default_rng(seed).choice(P, n_pix, replace=False))
     t0 = time.perf_counter()
     oracle.grid(f["ra"], f["dec"], vals_host, "f32", m, f["kernel"]["fwhm_deg"],
-                f["kernel"]["support_deg"], pix=pix)
+                f["kernel"]["support_deg"], pix=pix, kernel=f["kernel"])
     dt = time.perf_counter() - t0
     full_s = dt * P / n_pix
     n, C = vals_host.shape
@@ -158,6 +164,19 @@ def run_drift(args):
 
     dev = torch.device("cuda:0")
     f = synth.config("cfg2")
+    variant = []
+    if args.map == "healpix":
+        # the same 5 x 5 deg of sky as a HEALPix patch at nside 4096 (0.86' pixels)
+        f["map"] = synth.healpix_patch(180.0, 30.0, 5.0, 5.0, 4096)
+        variant.append("HEALPix nside-4096 target patch")
+    if args.kernel == "sinc":
+        f["kernel"] = dict(f["kernel"], type=api.HG_KERNEL_GAUSS_SINC, p1=2.5 * synth.ARCMIN,
+                           p2=3.0 * synth.ARCMIN)
+        variant.append("Gauss-tapered sinc a=2.5' b=3'")
+    elif args.kernel == "elliptical":
+        f["kernel"] = dict(f["kernel"], type=api.HG_KERNEL_ELLIPTICAL, p1=2.0 * synth.ARCMIN,
+                           p2=30.0)
+        variant.append("elliptical Gaussian 3'x2' at PA 30 deg")
     C = f["nchan"]
     n = f["ra"].shape[0]
     m, k = f["map"], f["kernel"]
@@ -200,17 +219,19 @@ def run_drift(args):
 
     roof = roofline(2.0 * nnz * C, 4.0 * n * C + 4.0 * P * C, ch_avg, PEAK_FP32_MFMA_TFLOPS,
                     "k_channels (FP32 form, FP32 values)")
-    roof["traffic"] = measured_traffic("drift")
+    roof["traffic"] = None if variant else measured_traffic("drift")
+    workload = ("drift-scan field: 1e6 samples on 40 tracks, 5x5 deg, "
+                "300x300 map at 1 arcmin, FWHM 3 arcmin, support 3 sigma, "
+                "1024 FP32 channels; step = setup + channels")
+    if variant:
+        workload += "; variant: " + ", ".join(variant) + f" ({m['nx']}x{m['ny']} cells)"
     res = {
         "metric": "G sample*channel updates/s (plain FP32 form)",
         "value": value, "unit": "G sample*channel updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "drift-scan field: 1e6 samples on 40 tracks, 5x5 deg, "
-                               "300x300 map at 1 arcmin, FWHM 3 arcmin, support 3 sigma, "
-                               "1024 FP32 channels; step = setup + channels",
-                   "n_samples": n, "channels": C, "map": [m["ny"], m["nx"]], "nnz": nnz,
+        "config": {"workload": workload, "n_samples": n, "channels": C, "map": [m["ny"], m["nx"]], "nnz": nnz,
                    "entry_units": entries, "form": "fp32"},
         "channels_ms": ch_avg, "setup_ms": float(np.mean(setup_ms)),
         "channels_only_value": n * C / (ch_avg * 1e-3) / 1e9,
@@ -516,6 +537,10 @@ def main():
     ap.add_argument("--workload", choices=["drift", "batch", "paper", "literal", "fifo"],
                     default="drift")
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--map", choices=["car", "healpix"], default="car",
+                    help="drift workload: plate-carree map or a HEALPix target patch")
+    ap.add_argument("--kernel", choices=["gauss", "sinc", "elliptical"], default="gauss",
+                    help="drift workload: kernel shape")
     ap.add_argument("--paper-samples", type=int, default=19_000_000)
     ap.add_argument("--precision", choices=["mfma", "fp32"], default="mfma")
     ap.add_argument("--fields", type=int, default=64)

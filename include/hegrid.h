@@ -15,7 +15,8 @@
  *   - support: d <= R, R = hg_kernel.support_deg, tested in FP64 as
  *     sin^2(dDec/2) + cos(Dec_g) cos(Dec_n) sin^2(dRA/2) <= sin^2(R/2);
  *   - map: plate carree in coordinate degrees; pixel (i, j) is centred at
- *     RA = ra0 + (i - (nx-1)/2) dra, Dec = dec0 + (j - (ny-1)/2) ddec;
+ *     RA = ra0 + (i - (nx-1)/2) dra, Dec = dec0 + (j - (ny-1)/2) ddec; or a
+ *     patch of a HEALPix grid (hg_map.proj; Eq. 1 leaves the cell set G open);
  *   - a cell with no sample in its support gets NaN (count 0, W 0).
  *
  * The work is split the way the paper's shared-component design splits it
@@ -63,10 +64,31 @@ extern "C" {
 
 typedef struct hg_plan hg_plan; /* opaque; owns all device memory it allocates */
 
+/* target cell sets (hg_map.proj) */
+#define HG_PROJ_CAR 0     /* plate carree in coordinate degrees                  */
+#define HG_PROJ_HEALPIX 1 /* a patch of a HEALPix RING grid (Gorski et al. 2005) */
+
+/* Output cells are laid out [ny][nx], cell (i, j) at flat index j*nx + i.
+   HG_PROJ_CAR: cell (i, j) is centred at RA = ra0 + (i - (nx-1)/2) dra,
+   Dec = dec0 + (j - (ny-1)/2) ddec; nside, ring0 and pix0 must be 0.
+   HG_PROJ_HEALPIX: row j is HEALPix ring r = ring0 - j (rings counted from 1 at
+   the north pole, so rows run south to north) and column i is pixel
+   k = (pix0 + i) mod 4 nside of that ring (0-based, eastward from RA 0): the
+   RING-scheme pixel 2 nside (nside - 1) + 4 nside (r - nside) + k, centred at
+   z = sin Dec = 4/3 - 2 r / (3 nside), RA = (k + s/2) pi / (2 nside) with
+   s = (r - nside + 1) mod 2.  Every ring must lie in the equatorial belt
+   (nside <= r <= 3 nside), where each ring holds 4 nside equally spaced
+   pixels; polar-cap rings give HG_ERR_UNSUPPORTED.  nx <= 4 nside;
+   ra0/dec0/dra/ddec are unused and must be 0.  hg_map_pixel_ids gives the
+   pixel numbers of the patch. */
 typedef struct {
-    double ra0_deg, dec0_deg; /* map centre (degrees)                          */
-    double dra_deg, ddec_deg; /* pixel spacing in coordinate degrees, > 0      */
-    int32_t nx, ny;           /* pixels along RA and Dec, > 0                  */
+    double ra0_deg, dec0_deg; /* CAR: map centre (degrees)                     */
+    double dra_deg, ddec_deg; /* CAR: pixel spacing in coordinate degrees, > 0 */
+    int32_t nx, ny;           /* cells along RA and Dec, > 0                   */
+    int32_t proj;             /* HG_PROJ_*; 0 = plate carree                   */
+    int32_t nside;            /* HEALPIX: grid resolution, a power of two <= 2^20 */
+    int32_t ring0;            /* HEALPIX: ring of row 0                        */
+    int32_t pix0;             /* HEALPIX: pixel of column 0 within each ring, < 4 nside */
 } hg_map;
 
 /* Kernel shapes w(g; s) of Eq. 1 (the paper leaves w open).  d is the
@@ -239,6 +261,15 @@ int hg_plan_neighbours(const hg_plan* p, int64_t* row_ptr, int64_t* idx, float* 
  */
 int hg_ang2pix_ring(int32_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
                     int64_t* pix, void* hip_stream);
+
+/*
+ * HEALPix RING pixel numbers of a HG_PROJ_HEALPIX map's cells, HOST int64
+ * [ny*nx] (flat index j*nx + i), by the formula given with hg_map: where to
+ * put the gridded cells in a full-sky RING array.  Host arithmetic only (no
+ * device call).  The map is checked as hg_grid_setup checks it; a plate-carree
+ * map gives HG_ERR_ARG.
+ */
+int hg_map_pixel_ids(const hg_map* m, int64_t* host_ids);
 
 /*
  * Batched form: many independent fields (each its own Eq. 1 problem with its

@@ -23,7 +23,7 @@ ABI_FUNCTIONS = ("hg_grid_setup", "hg_grid_channels", "hg_grid_finish", "hg_plan
                  "hg_plan_counts", "hg_plan_weight_sums", "hg_plan_neighbours",
                  "hg_ang2pix_ring", "hg_grid_channels_host", "hg_grid_channels_literal",
                  "hg_batch_create", "hg_batch_run", "hg_batch_destroy", "hg_batch_stats",
-                 "hg_batch_plan", "hg_last_error")
+                 "hg_batch_plan", "hg_map_pixel_ids", "hg_last_error")
 
 
 class HegridError(RuntimeError):
@@ -35,7 +35,12 @@ class HegridError(RuntimeError):
 class hg_map(ctypes.Structure):
     _fields_ = [("ra0_deg", ctypes.c_double), ("dec0_deg", ctypes.c_double),
                 ("dra_deg", ctypes.c_double), ("ddec_deg", ctypes.c_double),
-                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("proj", ctypes.c_int32), ("nside", ctypes.c_int32),
+                ("ring0", ctypes.c_int32), ("pix0", ctypes.c_int32)]
+
+
+HG_PROJ_CAR, HG_PROJ_HEALPIX = 0, 1
 
 
 class hg_kernel(ctypes.Structure):
@@ -110,6 +115,7 @@ def lib():
     L.hg_plan_weight_sums.argtypes = [P, P]
     L.hg_plan_neighbours.argtypes = [P, P, P, P, i64, ctypes.POINTER(ctypes.c_int64)]
     L.hg_ang2pix_ring.argtypes = [i32, P, P, i64, P, P]
+    L.hg_map_pixel_ids.argtypes = [ctypes.POINTER(hg_map), P]
     L.hg_grid_channels_host.argtypes = [P, P, i64, i32, i32, P, i32, P,
                                         ctypes.POINTER(hg_stream_info)]
     L.hg_batch_create.argtypes = [ctypes.POINTER(hg_field), i32, i32, ctypes.POINTER(hg_opts), P,
@@ -155,8 +161,27 @@ def _dev_f64(x):
 
 
 def make_map(m):
+    """A map dict as the C struct: plate carree {"ra0_deg", "dec0_deg",
+    "dra_deg", "ddec_deg", "nx", "ny"}, or a HEALPix patch {"proj":
+    HG_PROJ_HEALPIX, "nside", "ring0", "pix0", "nx", "ny"} (row j = ring
+    ring0 - j, column i = pixel (pix0 + i) mod 4 nside of the ring)."""
+    proj = int(m.get("proj", HG_PROJ_CAR))
+    if proj == HG_PROJ_HEALPIX:
+        return hg_map(0.0, 0.0, 0.0, 0.0, int(m["nx"]), int(m["ny"]), proj, int(m["nside"]),
+                      int(m["ring0"]), int(m["pix0"]))
     return hg_map(float(m["ra0_deg"]), float(m["dec0_deg"]), float(m["dra_deg"]),
-                  float(m["ddec_deg"]), int(m["nx"]), int(m["ny"]))
+                  float(m["ddec_deg"]), int(m["nx"]), int(m["ny"]), proj,
+                  int(m.get("nside", 0)), int(m.get("ring0", 0)), int(m.get("pix0", 0)))
+
+
+def map_pixel_ids(m):
+    """HEALPix RING pixel numbers of a HEALPix map's cells, int64 [ny][nx]
+    (host arithmetic in the library; no device needed)."""
+    hm = make_map(m)
+    ids = np.empty((hm.ny, hm.nx), dtype=np.int64)
+    _check(lib().hg_map_pixel_ids(ctypes.byref(hm), ids.ctypes.data_as(ctypes.c_void_p)),
+           "hg_map_pixel_ids")
+    return ids
 
 
 def make_kernel(k):

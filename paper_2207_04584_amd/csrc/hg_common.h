@@ -248,12 +248,34 @@ struct BatchKernelInfo {
     int channels_per_block;
 };
 
-// pixel centres in radians: (i, j) at ra0 + (i - (nx-1)/2) dra, dec0 + (j - (ny-1)/2) ddec
-__device__ inline double pix_ra(const hg_map& m, int64_t i) {
+// Cell centres in radians.  Plate carree: (i, j) at ra0 + (i - (nx-1)/2) dra,
+// dec0 + (j - (ny-1)/2) ddec.  HEALPix patch (equatorial belt): row j is ring
+// r = ring0 - j at z = 4/3 - 2r/(3 nside); column i is pixel pix0 + i of the
+// ring, at RA (pix0 + i + s/2) pi / (2 nside) with s = (r - nside + 1) mod 2,
+// left unwrapped past 2 pi (every use of an RA is periodic or wraps it).
+__host__ __device__ inline double pix_dec(const hg_map& m, int64_t j) {
+    if (m.proj == HG_PROJ_HEALPIX)
+        return asin(4.0 / 3.0 - 2.0 * (double)(m.ring0 - j) / (3.0 * (double)m.nside));
+    return (m.dec0_deg + ((double)j - (m.ny - 1) / 2.0) * m.ddec_deg) * kDeg;
+}
+__host__ __device__ inline double pix_ra(const hg_map& m, int64_t i, int64_t j) {
+    if (m.proj == HG_PROJ_HEALPIX) {
+        const int64_t s = (m.ring0 - j - m.nside + 1) & 1;
+        return ((double)(m.pix0 + i) + 0.5 * (double)s) * (kPi / (2.0 * (double)m.nside));
+    }
     return (m.ra0_deg + ((double)i - (m.nx - 1) / 2.0) * m.dra_deg) * kDeg;
 }
-__device__ inline double pix_dec(const hg_map& m, int64_t j) {
-    return (m.dec0_deg + ((double)j - (m.ny - 1) / 2.0) * m.ddec_deg) * kDeg;
+// least and greatest centre RA of column i over all rows (the planner's bounds;
+// HEALPix rings alternate by half a pixel)
+__host__ __device__ inline double col_ra_lo(const hg_map& m, int64_t i) {
+    if (m.proj == HG_PROJ_HEALPIX)
+        return (double)(m.pix0 + i) * (kPi / (2.0 * (double)m.nside));
+    return pix_ra(m, i, 0);
+}
+__host__ __device__ inline double col_ra_hi(const hg_map& m, int64_t i) {
+    if (m.proj == HG_PROJ_HEALPIX)
+        return ((double)(m.pix0 + i) + 0.5) * (kPi / (2.0 * (double)m.nside));
+    return pix_ra(m, i, 0);
 }
 
 // kernel launchers (setup.hip, channels.hip, literal.hip)

@@ -39,7 +39,7 @@ __global__ void k_literal(const int4* __restrict__ pg_piece, int32_t pg_rings,
         ci[g] = ix + (k & 1);
         cj[g] = iy + (k >> 1);
         valid[g] = ci[g] < m.nx && cj[g] < m.ny;
-        pra[g] = pix_ra(m, ci[g]);
+        pra[g] = pix_ra(m, ci[g], cj[g]);
         pdec[g] = pix_dec(m, cj[g]);
         pcos[g] = cos(pdec[g]);
     }

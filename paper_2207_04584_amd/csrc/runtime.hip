@@ -87,9 +87,16 @@ int ensure_device() {
 int64_t choose_nside(Plan& P) {
     if (P.opts.nside > 0) return P.opts.nside;
     const hg_map& m = P.map;
-    double cosd = cos(m.dec0_deg * kDeg);
-    double w = m.nx * m.dra_deg * kDeg * (cosd > 0.05 ? cosd : 0.05) + 2 * P.r_rad;
-    double h = m.ny * m.ddec_deg * kDeg + 2 * P.r_rad;
+    double w, h;  // extent of the map plus the support on each side (radians)
+    if (m.proj == HG_PROJ_HEALPIX) {
+        double cosd = cos(0.5 * (pix_dec(m, 0) + pix_dec(m, m.ny - 1)));
+        w = m.nx * (kPi / (2.0 * m.nside)) * (cosd > 0.05 ? cosd : 0.05) + 2 * P.r_rad;
+        h = pix_dec(m, m.ny - 1) - pix_dec(m, 0) + 2 * P.r_rad;
+    } else {
+        double cosd = cos(m.dec0_deg * kDeg);
+        w = m.nx * m.dra_deg * kDeg * (cosd > 0.05 ? cosd : 0.05) + 2 * P.r_rad;
+        h = m.ny * m.ddec_deg * kDeg + 2 * P.r_rad;
+    }
     double rho = (double)P.n / (w * h);  // samples per steradian near the map
     double target = 0.5 * P.r_rad;
     if (rho > 0) target = fmin(target, sqrt(64.0 / rho));
@@ -197,6 +204,39 @@ hipError_t resolve_timing(Plan& P) {
 
 bool finite(double x) { return std::isfinite(x); }
 
+int validate_map(const hg_map* m) {
+    if (!m) return fail(HG_ERR_ARG, "NULL map");
+    if (m->nx <= 0 || m->ny <= 0) return fail(HG_ERR_ARG, "map nx and ny must be > 0");
+    if ((int64_t)m->nx * m->ny >= ((int64_t)1 << 31)) return fail(HG_ERR_ARG, "map too large");
+    if (m->proj == HG_PROJ_HEALPIX) {
+        const int64_t ns = m->nside, top = (int64_t)m->ring0 - (m->ny - 1);
+        if (m->ra0_deg != 0.0 || m->dec0_deg != 0.0 || m->dra_deg != 0.0 || m->ddec_deg != 0.0)
+            return fail(HG_ERR_ARG, "a HEALPix map leaves ra0, dec0, dra and ddec at 0");
+        if (ns < 1 || ns > ((int64_t)1 << 20) || (ns & (ns - 1)))
+            return fail(HG_ERR_ARG, "HEALPix map nside must be a power of two <= 2^20");
+        if (m->pix0 < 0 || m->pix0 >= 4 * ns || m->nx > 4 * ns)
+            return fail(HG_ERR_ARG, "HEALPix map needs 0 <= pix0 < 4 nside and nx <= 4 nside");
+        if (top < 1 || m->ring0 > 4 * ns - 1)
+            return fail(HG_ERR_ARG, "HEALPix map rows ring0 - ny + 1 .. ring0 must be rings "
+                                    "1 .. 4 nside - 1");
+        if (top < ns || m->ring0 > 3 * ns)
+            return fail(HG_ERR_UNSUPPORTED, "HEALPix map rows must lie in the equatorial belt "
+                                            "(nside <= ring <= 3 nside)");
+        return HG_OK;
+    }
+    if (m->proj != HG_PROJ_CAR) return fail(HG_ERR_UNSUPPORTED, "unknown map projection");
+    if (m->nside || m->ring0 || m->pix0)
+        return fail(HG_ERR_ARG, "a plate-carree map leaves nside, ring0 and pix0 at 0");
+    if (!finite(m->ra0_deg) || !finite(m->dec0_deg) || !finite(m->dra_deg) ||
+        !finite(m->ddec_deg) || !(m->dra_deg > 0) || !(m->ddec_deg > 0))
+        return fail(HG_ERR_ARG, "map centre must be finite and spacings > 0");
+    double d0 = m->dec0_deg - (m->ny - 1) / 2.0 * m->ddec_deg;
+    double d1 = m->dec0_deg + (m->ny - 1) / 2.0 * m->ddec_deg;
+    if (!(d0 > -90.0) || !(d1 < 90.0))
+        return fail(HG_ERR_ARG, "pixel centres must lie strictly between the poles");
+    return HG_OK;
+}
+
 int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kernel* k,
                    const hg_map* m, const hg_opts* o) {
     if (!k || !m || (n > 0 && (!ra || !dec)))
@@ -216,15 +256,8 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
                                 "position angle p2");
     if (!finite(k->support_deg) || !(k->support_deg >= 0) || k->support_deg > 10.0)
         return fail(HG_ERR_ARG, "support_deg must be in [0, 10]");
-    if (m->nx <= 0 || m->ny <= 0) return fail(HG_ERR_ARG, "map nx and ny must be > 0");
-    if ((int64_t)m->nx * m->ny >= ((int64_t)1 << 31)) return fail(HG_ERR_ARG, "map too large");
-    if (!finite(m->ra0_deg) || !finite(m->dec0_deg) || !finite(m->dra_deg) ||
-        !finite(m->ddec_deg) || !(m->dra_deg > 0) || !(m->ddec_deg > 0))
-        return fail(HG_ERR_ARG, "map centre must be finite and spacings > 0");
-    double d0 = m->dec0_deg - (m->ny - 1) / 2.0 * m->ddec_deg;
-    double d1 = m->dec0_deg + (m->ny - 1) / 2.0 * m->ddec_deg;
-    if (!(d0 > -90.0) || !(d1 < 90.0))
-        return fail(HG_ERR_ARG, "pixel centres must lie strictly between the poles");
+    int rc = validate_map(m);
+    if (rc != HG_OK) return rc;
     if (o) {
         if (o->precision != HG_PREC_FP32 && o->precision != HG_PREC_MFMA_BF16 &&
             o->precision != HG_PREC_MFMA_F16)
@@ -677,6 +710,23 @@ int hg_plan_weight_sums(const hg_plan* h, double* host_W) {
         const Plan& P = h->P;
         hipError_t e = hipMemcpy(host_W, P.pix_W.p, 8 * (size_t)P.npix, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return fail_hip(e, "plan_weight_sums");
+        return HG_OK;
+    });
+}
+
+int hg_map_pixel_ids(const hg_map* m, int64_t* host_ids) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!m || !host_ids) return fail(HG_ERR_ARG, "NULL argument");
+        int rc = validate_map(m);
+        if (rc != HG_OK) return rc;
+        if (m->proj != HG_PROJ_HEALPIX) return fail(HG_ERR_ARG, "not a HEALPix map");
+        const int64_t ns = m->nside, per_ring = 4 * ns, cap = 2 * ns * (ns - 1);
+        for (int64_t j = 0; j < m->ny; j++) {
+            const int64_t first = cap + per_ring * (m->ring0 - j - ns);  // first pixel of the ring
+            for (int64_t i = 0; i < m->nx; i++)
+                host_ids[j * m->nx + i] = first + (m->pix0 + i) % per_ring;
+        }
         return HG_OK;
     });
 }

@@ -349,7 +349,7 @@ __global__ void k_tile_plan(const RowInfo* __restrict__ rows, int32_t ntx, int64
     int64_t i0 = (int64_t)tx * TILE_PGX * PG;
     int64_t i1 = i0 + TILE_PGX * PG - 1;
     if (i1 > m.nx - 1) i1 = m.nx - 1;
-    double a0 = pix_ra(m, i0) - ri.dalpha - eps, a1 = pix_ra(m, i1) + ri.dalpha + eps;
+    double a0 = col_ra_lo(m, i0) - ri.dalpha - eps, a1 = col_ra_hi(m, i1) + ri.dalpha + eps;
     int64_t pa[2], pb[2];
     int np = hp_ring_pieces(r, a0, a1, &pa[0], &pb[0], &pa[1], &pb[1]);
     for (int q = 0; q < np; q++) {
@@ -407,7 +407,7 @@ __global__ void k_pg_plan(const RowInfo* __restrict__ pg_rows, const RowInfo* __
     Ring r = hp_ring(nside, ring);
     int64_t i0 = (int64_t)gx * PG, i1 = i0 + PG - 1;
     if (i1 > m.nx - 1) i1 = m.nx - 1;
-    double a0 = pix_ra(m, i0) - pr.dalpha - eps, a1 = pix_ra(m, i1) + pr.dalpha + eps;
+    double a0 = col_ra_lo(m, i0) - pr.dalpha - eps, a1 = col_ra_hi(m, i1) + pr.dalpha + eps;
     int64_t pa[2], pb[2];
     int np = hp_ring_pieces(r, a0, a1, &pa[0], &pb[0], &pa[1], &pb[1]);
     RowInfo tr = tile_rows[ty];
@@ -589,10 +589,11 @@ __device__ inline double kernel_weight(const KernelArgs& ka, double d2, double r
 // One wave per pixel group.  Lanes walk the group's candidates in slot order;
 // each lane tests its candidate against the group's (up to) four pixels with
 // the exact FP64 haversine test, and surviving candidates are compacted in
-// order into the group's entry list with their four FP32 weights.
+// order into the group's entry list with their four FP32 weights.  HPX: the
+// map is a HEALPix patch, whose two rows have their own pixel RAs.
 constexpr int GATHER_WAVES = 4;
 
-template <bool SMALL, int KT>
+template <bool SMALL, int KT, bool HPX>
 __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     const int4* __restrict__ pg_piece, int32_t pg_rings, const int64_t* __restrict__ pg_base,
     const double4* __restrict__ srt_coord, int32_t npgx, int64_t npg, hg_map m, double h_r,
@@ -626,7 +627,12 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
     int64_t ix = (int64_t)gx * PG, iy = (int64_t)gy * PG;
     bool vx1 = ix + 1 < m.nx, vy1 = iy + 1 < m.ny;
-    double pra0 = pix_ra(m, ix), pra1 = pix_ra(m, ix + 1);
+    // pra[k]: pixel k = (column k & 1, row k >> 1); the rows share RAs unless HPX
+    double pra[4];
+    pra[0] = pix_ra(m, ix, iy);
+    pra[1] = pix_ra(m, ix + 1, iy);
+    pra[2] = HPX ? pix_ra(m, ix, iy + 1) : pra[0];
+    pra[3] = HPX ? pix_ra(m, ix + 1, iy + 1) : pra[1];
     double pdec0 = pix_dec(m, iy), pdec1 = pix_dec(m, iy + 1);
     double pcos0 = cos(pdec0), pcos1 = cos(pdec1);
     int cnt[4] = {0, 0, 0, 0};
@@ -645,17 +651,25 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
             int off = v - pref[lo];
             double4 c = srt_coord[ppos[lo] + off];
             slot = (uint32_t)(pslot[lo] + off);
-            double sd0, sd1, sa0, sa1;
-            half_sines(0.5 * (c.y - pdec0), 0.5 * (c.y - pdec1), 0.5 * (c.x - pra0),
-                       0.5 * (c.x - pra1), sd0, sd1, sa0, sa1);
+            double sd0, sd1, sa[4];
+            half_sines(0.5 * (c.y - pdec0), 0.5 * (c.y - pdec1), 0.5 * (c.x - pra[0]),
+                       0.5 * (c.x - pra[1]), sd0, sd1, sa[0], sa[1]);
+            if (HPX) {
+                double u0, u1;
+                half_sines(0.5 * (c.x - pra[2]), 0.5 * (c.x - pra[3]), 0.0, 0.0, sa[2], sa[3],
+                           u0, u1);
+            } else {
+                sa[2] = sa[0];
+                sa[3] = sa[1];
+            }
             double hk[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 bool ok = ((k & 1) == 0 || vx1) && ((k >> 1) == 0 || vy1);
                 double sd = (k >> 1) ? sd1 : sd0;
-                double sa = (k & 1) ? sa1 : sa0;
+                double sa_k = sa[k];
                 double pc = (k >> 1) ? pcos1 : pcos0;
-                hk[k] = sd * sd + pc * c.z * sa * sa;
+                hk[k] = sd * sd + pc * c.z * sa_k * sa_k;
                 if (ok && hk[k] <= h_r) mask |= 1u << k;
             }
             // One exp per pass with the pixels rotated through the first
@@ -668,9 +682,8 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 float wf = 0.f;
                 if (mk & 1u) {
                     const double w =
-                        kernel_weight<KT>(ka, dist2<SMALL>(h0), c.x, c.y, c.z,
-                                          (k & 1) ? pra1 : pra0, (k >> 1) ? pdec1 : pdec0,
-                                          (k >> 1) ? pcos1 : pcos0);
+                        kernel_weight<KT>(ka, dist2<SMALL>(h0), c.x, c.y, c.z, pra[k],
+                                          (k >> 1) ? pdec1 : pdec0, (k >> 1) ? pcos1 : pcos0);
                     wf = round_weight((float)w, prec);
                 }
                 h0 = h1;
@@ -724,6 +737,18 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
         }
         atomicAdd(nnz_total, (unsigned long long)tot);
     }
+}
+
+// the gather instance for a kernel shape, support size and map kind
+template <bool HPX>
+auto gather_kernel(int32_t type, bool small) {
+    if (type == HG_KERNEL_GAUSS)
+        return small ? k_gather<true, HG_KERNEL_GAUSS, HPX> : k_gather<false, HG_KERNEL_GAUSS, HPX>;
+    if (type == HG_KERNEL_GAUSS_SINC)
+        return small ? k_gather<true, HG_KERNEL_GAUSS_SINC, HPX>
+                     : k_gather<false, HG_KERNEL_GAUSS_SINC, HPX>;
+    return small ? k_gather<true, HG_KERNEL_ELLIPTICAL, HPX>
+                 : k_gather<false, HG_KERNEL_ELLIPTICAL, HPX>;
 }
 
 // Per (pixel group, chunk): first entry whose slot is in the chunk, relative to
@@ -842,10 +867,6 @@ double ra_halfwidth(double d0, double d1, double r, double eps) {
     return asin(x);
 }
 
-double host_pix_dec(const hg_map& m, int64_t j) {
-    return (m.dec0_deg + ((double)j - (m.ny - 1) / 2.0) * m.ddec_deg) * kDeg;
-}
-
 }  // namespace
 
 hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
@@ -867,7 +888,7 @@ static void plan_rows(Plan& P, std::vector<RowInfo>& trows, std::vector<RowInfo>
     for (int ty = 0; ty < P.nty; ty++) {
         int64_t j0 = (int64_t)ty * TILE_PGY * PG, j1 = j0 + TILE_PGY * PG - 1;
         if (j1 > m.ny - 1) j1 = m.ny - 1;
-        double d0 = host_pix_dec(m, j0), d1 = host_pix_dec(m, j1);
+        double d0 = pix_dec(m, j0), d1 = pix_dec(m, j1);
         RowInfo ri;
         ring_range(P.nside, d0, d1, P.r_rad, eps, &ri.ring_lo, &ri.nrings);
         ri.dalpha = ra_halfwidth(d0, d1, P.r_rad, eps);
@@ -877,7 +898,7 @@ static void plan_rows(Plan& P, std::vector<RowInfo>& trows, std::vector<RowInfo>
     for (int gy = 0; gy < P.npgy; gy++) {
         int64_t j0 = (int64_t)gy * PG, j1 = j0 + PG - 1;
         if (j1 > m.ny - 1) j1 = m.ny - 1;
-        double d0 = host_pix_dec(m, j0), d1 = host_pix_dec(m, j1);
+        double d0 = pix_dec(m, j0), d1 = pix_dec(m, j1);
         RowInfo ri;
         ring_range(P.nside, d0, d1, P.r_rad, eps, &ri.ring_lo, &ri.nrings);
         ri.dalpha = ra_halfwidth(d0, d1, P.r_rad, eps);
@@ -890,7 +911,7 @@ static void plan_rows(Plan& P, std::vector<RowInfo>& trows, std::vector<RowInfo>
 
 void plan_band(Plan& P, double eps) {
     const hg_map& m = P.map;
-    double d0 = host_pix_dec(m, 0), d1 = host_pix_dec(m, m.ny - 1);
+    double d0 = pix_dec(m, 0), d1 = pix_dec(m, m.ny - 1);
     int32_t lo, cnt;
     ring_range(P.nside, d0, d1, P.r_rad, eps, &lo, &cnt);
     P.ring_lo = lo;
@@ -1407,13 +1428,9 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         const KernelArgs ka = kernel_args(P);
         // every in-support h is at most h_r; below 1e-4 no asin is needed
         const bool small = P.h_r < 1e-4;
-        auto kern = P.kern.type == HG_KERNEL_GAUSS
-                        ? (small ? k_gather<true, HG_KERNEL_GAUSS> : k_gather<false, HG_KERNEL_GAUSS>)
-                    : P.kern.type == HG_KERNEL_GAUSS_SINC
-                        ? (small ? k_gather<true, HG_KERNEL_GAUSS_SINC>
-                                 : k_gather<false, HG_KERNEL_GAUSS_SINC>)
-                        : (small ? k_gather<true, HG_KERNEL_ELLIPTICAL>
-                                 : k_gather<false, HG_KERNEL_ELLIPTICAL>);
+        const bool hpx = P.map.proj == HG_PROJ_HEALPIX;
+        auto kern = hpx ? gather_kernel<true>(P.kern.type, small)
+                        : gather_kernel<false>(P.kern.type, small);
         hipLaunchKernelGGL(kern, dim3(blocks_for(P.npg, GATHER_WAVES)), dim3(64 * GATHER_WAVES),
                            shm, s, (const int4*)P.pg_piece.p, P.pg_rings,
                            (const int64_t*)P.pg_base.p, (const double4*)P.srt_coord.p, P.npgx,

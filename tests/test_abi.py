@@ -6,8 +6,10 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
+import oracle
 from paper_2207_04584_amd import api
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -123,6 +125,68 @@ def test_setup_rejects_bad_arguments_without_a_device(case):
     assert api.last_error()
     if case != "null_out":
         assert not h.value  # *out is cleared on failure
+
+
+def hpx_map(nside=64, ring0=100, pix0=10, nx=12, ny=9):
+    return api.make_map(dict(proj=api.HG_PROJ_HEALPIX, nside=nside, ring0=ring0, pix0=pix0,
+                             nx=nx, ny=ny))
+
+
+@pytest.mark.parametrize("case", ["hpx_radec", "hpx_nside", "hpx_nx", "hpx_pix0", "hpx_ring",
+                                  "car_nside"])
+def test_setup_rejects_bad_maps_without_a_device(case):
+    k, m = good()
+    if case == "car_nside":
+        m.nside = 4
+    else:
+        m = hpx_map()
+        if case == "hpx_radec":
+            m.ra0_deg = 10.0
+        elif case == "hpx_nside":
+            m.nside = 48
+        elif case == "hpx_nx":
+            m.nx = 4 * 64 + 1
+        elif case == "hpx_pix0":
+            m.pix0 = 4 * 64
+        elif case == "hpx_ring":
+            m.ring0 = 4 * 64  # past the last ring, 4 nside - 1
+    rc, h = _setup(k=k, m=m, o=api.hg_opts())
+    assert rc == api.HG_ERR_ARG, api.last_error()
+    assert not h.value
+
+
+@pytest.mark.parametrize("case", ["polar_north", "polar_south", "unknown_proj"])
+def test_polar_cap_rows_and_unknown_projections_are_unsupported(case):
+    k, _ = good()
+    if case == "polar_north":
+        m = hpx_map(ring0=70, ny=8)  # rows reach ring 63 < nside
+    elif case == "polar_south":
+        m = hpx_map(ring0=3 * 64 + 1, ny=4)  # row 0 is ring 193 > 3 nside
+    else:
+        m = hpx_map()
+        m.proj = 7
+    rc, h = _setup(k=k, m=m, o=api.hg_opts())
+    assert rc == api.HG_ERR_UNSUPPORTED, api.last_error()
+
+
+@pytest.mark.parametrize("nside,ring0,pix0,nx,ny", [(1, 3, 0, 4, 3), (64, 100, 10, 12, 9),
+                                                    (64, 192, 250, 9, 129), (2048, 5000, 8190, 7, 5)])
+def test_map_pixel_ids_match_the_reference(nside, ring0, pix0, nx, ny):
+    """hg_map_pixel_ids (host arithmetic, no device) against the reference's
+    own RING numbering of the same patch; the last two patches wrap past the
+    end of their rings, and (64, 192, ...) spans the whole belt."""
+    m = dict(proj=api.HG_PROJ_HEALPIX, nside=nside, ring0=ring0, pix0=pix0, nx=nx, ny=ny)
+    ids = api.map_pixel_ids(m)
+    _, _, ref = oracle.cell_centres(m)
+    np.testing.assert_array_equal(ids.ravel(), ref)
+    assert len(np.unique(ids)) == nx * ny
+
+
+def test_map_pixel_ids_refuses_plate_carree():
+    _, m = good()
+    ids = np.empty(m.nx * m.ny, dtype=np.int64)
+    assert api.lib().hg_map_pixel_ids(ctypes.byref(m), ids.ctypes.data) == api.HG_ERR_ARG
+    assert api.lib().hg_map_pixel_ids(None, None) == api.HG_ERR_ARG
 
 
 def test_unknown_precision_is_unsupported():

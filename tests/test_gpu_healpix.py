@@ -1,0 +1,152 @@
+"""GPU tests of HEALPix target maps (hg_map.proj = HG_PROJ_HEALPIX): Eq. 1
+gridded onto the pixels of a patch of a HEALPix RING grid in its equatorial
+belt, where rows are rings and alternate rings are offset by half a pixel.
+Against the FP64 reference: counts and neighbour lists bit-exact, weights to
+FP32 rounding, maps within 1e-6 (FP32 form) or 2e-3 (BF16 form); a patch
+across RA = 0, a patch of whole rings (every tile wraps), the elliptical
+kernel (whose bearing uses each cell's own RA), the Algorithm 1 path and a
+batch that mixes a HEALPix field with a plate-carree one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_04584_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2207_04584_amd import api  # noqa: E402
+from parity_util import norm_err, to_host_values  # noqa: E402
+
+DEV = "cuda:0"
+ARC = 1.0 / 60.0
+
+# name: (nside, ring0, pix0, nx, ny, FWHM arcmin, support deg, n samples, kernel shape)
+CASES = {
+    # 1.72' pixels near (43.9, 20.9) deg; ragged tiles in both directions
+    "basic": (2048, 3000, 1000, 45, 37, 3.0, None, 6000, None),
+    # the patch's columns run past the end of their rings, across RA = 0
+    "across_ra0": (2048, 4100, 8192 - 20, 40, 21, 3.0, None, 5000, None),
+    # every ring of the belt, whole: 3.7 deg pixels, a 7 deg support
+    "whole_belt": (16, 48, 0, 64, 33, 300.0, 7.0, 20000, None),
+    "elliptical": (2048, 2300, 3000, 33, 30, 3.5, 4.5 * ARC, 5000,
+                   dict(type=api.HG_KERNEL_ELLIPTICAL, p1=1.6 * ARC, p2=30.0)),
+}
+
+
+def hpx_map(nside, ring0, pix0, nx, ny):
+    return dict(proj=api.HG_PROJ_HEALPIX, nside=nside, ring0=ring0, pix0=pix0, nx=nx, ny=ny)
+
+
+def field(name, dtype=torch.float32, C=5):
+    nside, ring0, pix0, nx, ny, fwhm, R, n, shape = CASES[name]
+    rng = np.random.default_rng(sum(map(ord, name)))
+    m = hpx_map(nside, ring0, pix0, nx, ny)
+    k = synth.make_kernel(fwhm)
+    if R is not None:
+        k["support_deg"] = R
+    if shape is not None:
+        k.update(shape)
+    ra_c, dec_c, _ = oracle.cell_centres(m)
+    if name == "whole_belt":
+        z = rng.uniform(-0.8, 0.8, n)
+        ra, dec = rng.uniform(0.0, 360.0, n), np.degrees(np.arcsin(z))
+    else:
+        # samples over the patch and a margin around it; RA unwrapped from the
+        # first column, then folded into [0, 360)
+        lo = math.degrees(ra_c[0]) - 0.1
+        width = nx * 360.0 / (4 * nside) + 0.2
+        ra = np.mod(lo + rng.random(n) * width, 360.0)
+        d0, d1 = math.degrees(dec_c.min()), math.degrees(dec_c.max())
+        dec = d0 - 0.1 + rng.random(n) * (d1 - d0 + 0.2)
+    vals = torch.from_numpy(rng.normal(2.0, 1.0, size=(n, C)).astype(np.float32))
+    return ra, dec, vals.to(dtype).to(DEV), m, k
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_healpix_map_against_reference(name):
+    ra, dec, vals, m, k = field(name)
+    print(f"\n  {name}: nside {m['nside']} rings {m['ring0'] - m['ny'] + 1}..{m['ring0']} "
+          f"pix0 {m['pix0']} {m['nx']}x{m['ny']}", flush=True)
+    with api.Plan(ra, dec, m, k) as p:
+        out = p.grid(vals).cpu().numpy().reshape(vals.shape[1], -1)
+        cnt = p.counts()
+        W = p.weight_sums()
+        rp, idx, w = p.neighbours()
+    hv, code = to_host_values(vals)
+    Vr, cr, Wr, margin = oracle.grid(ra, dec, hv, code, m, k["fwhm_deg"], k["support_deg"],
+                                     kernel=k)
+    orp, oidx, ow = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"], kernel=k)
+    assert margin > 1e-12
+    assert (cr > 0).mean() > 0.9
+    np.testing.assert_array_equal(cnt, cr)
+    np.testing.assert_array_equal(rp, orp)
+    np.testing.assert_array_equal(idx, oidx)
+    np.testing.assert_allclose(w, ow, rtol=2e-7, atol=1e-12)
+    ok = cr > 0
+    np.testing.assert_allclose(W[ok], Wr[ok], rtol=1e-6)
+    np.testing.assert_array_equal(np.isnan(out), np.isnan(Vr))
+    e_max, e_rms = norm_err(out, Vr, ok)
+    print(f"  nnz {int(cnt.sum())} e_max={e_max:.3g} e_rms={e_rms:.3g}", flush=True)
+    assert e_max <= 1e-6
+
+
+def test_healpix_map_bf16_form():
+    ra, dec, vals, m, k = field("basic", dtype=torch.bfloat16, C=300)
+    with api.Plan(ra, dec, m, k, precision=api.HG_PREC_MFMA_BF16) as p:
+        out = p.grid(vals).cpu().numpy().reshape(vals.shape[1], -1)
+        cnt = p.counts()
+    hv, code = to_host_values(vals)
+    chans = np.array([0, 255, 299])
+    Vr, cr, _, _ = oracle.grid(ra, dec, hv, code, m, k["fwhm_deg"], k["support_deg"],
+                               chans=chans)
+    np.testing.assert_array_equal(cnt, cr)
+    e_max, _ = norm_err(out[chans], Vr, cr > 0)
+    assert e_max <= 2e-3
+
+
+def test_healpix_map_through_algorithm_1():
+    ra, dec, vals, m, k = field("across_ra0", C=3)
+    with api.Plan(ra, dec, m, k) as p:
+        out = p.grid_literal(vals, gamma=2, block=64).cpu().numpy().reshape(3, -1)
+    hv, code = to_host_values(vals)
+    Vr, cr, _, _ = oracle.grid(ra, dec, hv, code, m, k["fwhm_deg"], k["support_deg"])
+    np.testing.assert_array_equal(np.isnan(out), np.isnan(Vr))
+    e_max, _ = norm_err(out, Vr, cr > 0)
+    assert e_max <= 1e-6
+
+
+def test_batch_mixing_healpix_and_plate_carree_fields():
+    """Both fields in one launch equal their single-field maps bit for bit."""
+    ra1, dec1, v1, m1, k1 = field("basic", C=20)
+    rng = np.random.default_rng(5)
+    n2, nx2, ny2 = 3000, 30, 26
+    ra2 = 120.0 + (rng.random(n2) - 0.5) * nx2 * ARC * 1.3
+    dec2 = -10.0 + (rng.random(n2) - 0.5) * ny2 * ARC * 1.3
+    v2 = torch.from_numpy(rng.normal(size=(n2, 7)).astype(np.float32)).to(DEV)
+    fields = [{"ra": ra1, "dec": dec1, "map": m1, "kernel": k1, "values": v1},
+              {"ra": ra2, "dec": dec2, "map": synth.make_map(120.0, -10.0, nx2, ny2),
+               "kernel": synth.make_kernel(3.0), "values": v2}]
+    with api.Batch(fields) as b:
+        outs = [o.clone() for o in b.run()]
+    for f, o in zip(fields, outs):
+        with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"]) as p:
+            single = p.grid(f["values"])
+        assert torch.equal(torch.isnan(o), torch.isnan(single))
+        assert torch.equal(torch.nan_to_num(o), torch.nan_to_num(single))
+
+
+def test_pixel_ids_place_the_patch_in_a_full_sky_array():
+    """The patch's cells, scattered by hg_map_pixel_ids into a full-sky RING
+    array, land on the pixels whose centres the reference puts there."""
+    from oracle import healpix_ref
+    m = hpx_map(*CASES["across_ra0"][:5])
+    ids = api.map_pixel_ids(m).ravel()
+    ra, dec, _ = oracle.cell_centres(m)
+    np.testing.assert_array_equal(healpix_ref.ang2pix(m["nside"], np.sin(dec), ra), ids)
