@@ -942,12 +942,13 @@ struct BlockLane {
     int n;
 };
 
-__device__ inline BlockLane block_lane(int64_t b, int lane, int32_t npgx, int32_t npgy, int32_t ntx,
-                                       int64_t ntiles, const int64_t* tile_blk,
-                                       const int64_t* cp_base, const uint32_t* chunk_ptr,
-                                       const int64_t* pg_base) {
+// lane l of block b (of tile `tile`): group l's run of entries in the block's chunk
+__device__ inline BlockLane block_lane_at(int64_t b, int64_t tile, int lane, int32_t npgx,
+                                          int32_t npgy, int32_t ntx, const int64_t* tile_blk,
+                                          const int64_t* cp_base, const uint32_t* chunk_ptr,
+                                          const int64_t* pg_base) {
     BlockLane r;
-    r.tile = tile_of_block(tile_blk, ntiles, b);
+    r.tile = tile;
     r.c = b - tile_blk[r.tile];
     int64_t nch = tile_blk[r.tile + 1] - tile_blk[r.tile];
     int tx = (int)(r.tile % ntx), ty = (int)(r.tile / ntx);
@@ -959,16 +960,63 @@ __device__ inline BlockLane block_lane(int64_t b, int lane, int32_t npgx, int32_
     return r;
 }
 
+__device__ inline BlockLane block_lane(int64_t b, int lane, int32_t npgx, int32_t npgy, int32_t ntx,
+                                       int64_t ntiles, const int64_t* tile_blk,
+                                       const int64_t* cp_base, const uint32_t* chunk_ptr,
+                                       const int64_t* pg_base) {
+    return block_lane_at(b, tile_of_block(tile_blk, ntiles, b), lane, npgx, npgy, ntx, tile_blk,
+                         cp_base, chunk_ptr, pg_base);
+}
+
+// A block's units are its groups' runs cut in fours, group after group; lane l
+// holds group l's first unit, run start and length.  For unit i: the group
+// holding it (the last l whose first unit is <= i; an empty group shares its
+// first unit with the next group), found by a binary search over the wave's
+// registers, with that group's run and the unit's place in it.
+struct UnitRef {
+    int64_t src;
+    int n, t;
+};
+__device__ inline UnitRef unit_ref(int i, int first, int64_t src, int n) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(first, lo + step, 64) <= i) lo += step;  // lo + step <= 63
+    const uint32_t slo = (uint32_t)src, shi = (uint32_t)((uint64_t)src >> 32);
+    UnitRef u;
+    u.src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)shi, lo, 64) << 32) |
+                      (uint32_t)__shfl((int)slo, lo, 64));
+    u.n = __shfl(n, lo, 64);
+    u.t = i - __shfl(first, lo, 64);
+    return u;
+}
+
+// The four entries of a unit (a run's last unit padded with zero weights and
+// its last real slot), slots relative to the chunk's first slot s0.
+__device__ inline void load_unit(const UnitRef& u, uint32_t s0, const uint32_t* ent_slot,
+                                 const float4* ent_w, uint32_t sl[4], float4 w[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int e = 4 * u.t + k;
+        const bool real = e < u.n;
+        const int64_t at = u.src + (real ? e : u.n - 1);
+        sl[k] = (ent_slot[at] & SLOT_MASK) - s0;
+        const float4 v = ent_w[at];
+        w[k] = real ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_block_meta(
     int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
     const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
-    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff) {
+    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff, int32_t* __restrict__ blk_tile) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
+    if (lane == 0) blk_tile[b] = (int32_t)r.tile;
     // units are groups of four entries; a group's run starts on a unit and
     // its last unit is padded: po[l] = 4 x (first unit) + (padding entries)
     const int ng = (r.n + 3) >> 2;
@@ -986,79 +1034,64 @@ __global__ __launch_bounds__(256) void k_block_meta(
     }
 }
 
-// Index of the group holding unit i of a block: the last l with po[l] <= i
-// (po: the block's 65 non-decreasing group offsets, po[64] > i).
-__device__ inline int group_of_unit(const uint16_t* po, int i) {
-    int lo = 0, hi = TILE_PGS - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if ((int)po[mid] <= i)
-            lo = mid;
-        else
-            hi = mid - 1;
+// The group layout of a block as its meta pass wrote it, rebuilt in the
+// wave's registers: lane l's first unit (exclusive scan of the groups' unit
+// counts) and the block's unit count.
+__device__ inline int block_units(int n, int& first) {
+    const int ng = (n + 3) >> 2;
+    int x = ng;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if ((threadIdx.x & 63) >= o) x += y;
     }
-    return lo;
-}
-
-// group_of_unit for offsets in entries with the run's padding in the low two
-// bits (the FP32 form's blocks): the last l with po[l] / 4 <= i.
-__device__ inline int group_of_unit_x4(const uint16_t* po, int i) {
-    int lo = 0, hi = TILE_PGS - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (((int)po[mid] >> 2) <= i)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
+    first = x - ng;
+    return __shfl(x, 63, 64);
 }
 
 // One wave per block: lane l knows group l's run (first entry, count); the
-// block's units are then written flat, lane i taking unit i (coalesced writes).
+// block's units are then written flat, lane i taking units i and i + 64 of
+// each pass of 128 (coalesced writes; both units' loads in flight together).
 __global__ __launch_bounds__(256) void k_block_fill(
-    int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks, int32_t chunk,
-    const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
-    const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
-    const uint32_t* __restrict__ ent_slot, const float4* __restrict__ ent_w,
-    const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t n_blocks, int32_t chunk,
+    const int32_t* __restrict__ blk_tile, const int64_t* __restrict__ tile_blk,
+    const int64_t* __restrict__ cp_base, const uint32_t* __restrict__ chunk_ptr,
+    const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ ent_slot,
+    const float4* __restrict__ ent_w, const int64_t* __restrict__ blk_base,
     float4* __restrict__ e2_w, uint4* __restrict__ e2_s) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
-    BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
-                             pg_base);
-    const uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
     const int64_t base = blk_base[b];
-    const int nu = (int)(blk_base[b + 1] - base);  // units (groups of four entries)
+    BlockLane r = block_lane_at(b, blk_tile[b], lane, npgx, npgy, ntx, tile_blk, cp_base,
+                                chunk_ptr, pg_base);
+    int first;
+    const int nu = block_units(r.n, first);
     const uint32_t s0 = (uint32_t)(r.c * chunk);
-    const uint32_t src_lo = (uint32_t)r.src, src_hi = (uint32_t)((uint64_t)r.src >> 32);
-    for (int i0 = 0; i0 < nu; i0 += 64) {  // same trip count on every lane; lane i: unit i
-        const int i = i0 + lane;
-        const int lp = i < nu ? group_of_unit_x4(po, i) : 0;
-        const int64_t src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)src_hi, lp, 64) << 32) |
-                                      (uint32_t)__shfl((int)src_lo, lp, 64));
-        const int n = __shfl(r.n, lp, 64);
-        if (i >= nu) continue;
-        const int t = i - ((int)po[lp] >> 2);  // unit index within the run
-        uint32_t sl[4];
-        float w[4][4];  // [entry][pixel]
-        for (int k = 0; k < 4; k++) {
-            const int e = 4 * t + k;
-            const bool real = e < n;
-            const int ee = real ? e : n - 1;
-            sl[k] = (ent_slot[src + ee] & SLOT_MASK) - s0;
-            const float4 wv = ent_w[src + ee];
-            w[k][0] = real ? wv.x : 0.f;
-            w[k][1] = real ? wv.y : 0.f;
-            w[k][2] = real ? wv.z : 0.f;
-            w[k][3] = real ? wv.w : 0.f;
-        }
-        e2_s[base + i] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
+    for (int i0 = 0; i0 < nu; i0 += 128) {  // same trip count on every lane
+        const int ia = i0 + lane, ib = ia + 64;
+        const UnitRef ua = unit_ref(ia, first, r.src, r.n);
+        const UnitRef ub = unit_ref(ib, first, r.src, r.n);
+        uint32_t sa[4], sb[4];
+        float4 wa[4], wb[4];
+        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, sa, wa);
+        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, sb, wb);
         // [pixel q][entry k]: pixel q's weights for the unit's four entries
-        float4* wd = e2_w + (base + i) * 4;
-#pragma unroll
-        for (int q = 0; q < 4; q++) wd[q] = make_float4(w[0][q], w[1][q], w[2][q], w[3][q]);
+        if (ia < nu) {
+            e2_s[base + ia] = make_uint4(sa[0], sa[1], sa[2], sa[3]);
+            float4* wd = e2_w + (base + ia) * 4;
+            wd[0] = make_float4(wa[0].x, wa[1].x, wa[2].x, wa[3].x);
+            wd[1] = make_float4(wa[0].y, wa[1].y, wa[2].y, wa[3].y);
+            wd[2] = make_float4(wa[0].z, wa[1].z, wa[2].z, wa[3].z);
+            wd[3] = make_float4(wa[0].w, wa[1].w, wa[2].w, wa[3].w);
+        }
+        if (ib < nu) {
+            e2_s[base + ib] = make_uint4(sb[0], sb[1], sb[2], sb[3]);
+            float4* wd = e2_w + (base + ib) * 4;
+            wd[0] = make_float4(wb[0].x, wb[1].x, wb[2].x, wb[3].x);
+            wd[1] = make_float4(wb[0].y, wb[1].y, wb[2].y, wb[3].y);
+            wd[2] = make_float4(wb[0].z, wb[1].z, wb[2].z, wb[3].z);
+            wd[3] = make_float4(wb[0].w, wb[1].w, wb[2].w, wb[3].w);
+        }
     }
 }
 
@@ -1085,12 +1118,13 @@ __global__ __launch_bounds__(256) void k_block_meta_g(
     int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
     const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
-    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff) {
+    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff, int32_t* __restrict__ blk_tile) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
+    if (lane == 0) blk_tile[b] = (int32_t)r.tile;
     int ng = (r.n + 3) >> 2;
     int x = ng;
     for (int o = 1; o < 64; o <<= 1) {
@@ -1114,56 +1148,54 @@ __device__ inline uint16_t weight_bits(float w, int32_t prec) {
     return u;
 }
 
+__device__ inline void store_unit_g(uint16_t* e3_w, uint4* e3_s, int64_t at, const uint32_t sl[4],
+                                    const float4 w[4], int32_t prec) {
+    e3_s[at] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
+    // [pixel q][entry k] halves, packed in pairs: two 16-byte stores
+    const float wk[4][4] = {{w[0].x, w[0].y, w[0].z, w[0].w},
+                            {w[1].x, w[1].y, w[1].z, w[1].w},
+                            {w[2].x, w[2].y, w[2].z, w[2].w},
+                            {w[3].x, w[3].y, w[3].z, w[3].w}};  // [entry][pixel]
+    uint32_t wb[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int q = j >> 1, k = 2 * (j & 1);
+        wb[j] = (uint32_t)weight_bits(wk[k][q], prec) |
+                ((uint32_t)weight_bits(wk[k + 1][q], prec) << 16);
+    }
+    uint4* wd = (uint4*)(e3_w + at * 16);
+    wd[0] = make_uint4(wb[0], wb[1], wb[2], wb[3]);
+    wd[1] = make_uint4(wb[4], wb[5], wb[6], wb[7]);
+}
+
+// k_block_fill for the 16-bit forms: the same walk over a block's units (groups
+// of four entries), weights stored in the MFMA input type.
 __global__ __launch_bounds__(256) void k_block_fill_g(
-    int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks, int32_t chunk,
-    int32_t prec, const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
-    const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
-    const uint32_t* __restrict__ ent_slot, const float4* __restrict__ ent_w,
-    const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t n_blocks, int32_t chunk, int32_t prec,
+    const int32_t* __restrict__ blk_tile, const int64_t* __restrict__ tile_blk,
+    const int64_t* __restrict__ cp_base, const uint32_t* __restrict__ chunk_ptr,
+    const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ ent_slot,
+    const float4* __restrict__ ent_w, const int64_t* __restrict__ blk_base,
     uint16_t* __restrict__ e3_w, uint4* __restrict__ e3_s) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
-    BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
-                             pg_base);
-    const uint16_t* po = blk_pgoff + b * PGOFF_STRIDE;
     const int64_t base = blk_base[b];
-    const int ng_blk = (int)(blk_base[b + 1] - base);
+    BlockLane r = block_lane_at(b, blk_tile[b], lane, npgx, npgy, ntx, tile_blk, cp_base,
+                                chunk_ptr, pg_base);
+    int first;
+    const int nu = block_units(r.n, first);
     const uint32_t s0 = (uint32_t)(r.c * chunk);
-    const uint32_t src_lo = (uint32_t)r.src, src_hi = (uint32_t)((uint64_t)r.src >> 32);
-    for (int i0 = 0; i0 < ng_blk; i0 += 64) {  // lane i: group of four entries i
-        const int i = i0 + lane;
-        const int lp = i < ng_blk ? group_of_unit(po, i) : 0;
-        const int64_t src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)src_hi, lp, 64) << 32) |
-                                      (uint32_t)__shfl((int)src_lo, lp, 64));
-        const int n = __shfl(r.n, lp, 64);
-        if (i >= ng_blk) continue;
-        const int t = i - (int)po[lp];  // group index within the run
-        uint32_t sl[4];
-        float w[4][4];  // [entry][pixel]
-        for (int k = 0; k < 4; k++) {
-            int e = 4 * t + k;
-            bool real = e < n;
-            int ee = real ? e : n - 1;
-            sl[k] = (ent_slot[src + ee] & SLOT_MASK) - s0;
-            float4 wv = ent_w[src + ee];
-            w[k][0] = real ? wv.x : 0.f;
-            w[k][1] = real ? wv.y : 0.f;
-            w[k][2] = real ? wv.z : 0.f;
-            w[k][3] = real ? wv.w : 0.f;
-        }
-        e3_s[base + i] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
-        // [pixel q][entry k] halves, packed in pairs: two 16-byte stores per lane
-        uint32_t wb[8];
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int q = j >> 1, k = 2 * (j & 1);
-            wb[j] = (uint32_t)weight_bits(w[k][q], prec) |
-                    ((uint32_t)weight_bits(w[k + 1][q], prec) << 16);
-        }
-        uint4* wd = (uint4*)(e3_w + (base + i) * 16);
-        wd[0] = make_uint4(wb[0], wb[1], wb[2], wb[3]);
-        wd[1] = make_uint4(wb[4], wb[5], wb[6], wb[7]);
+    for (int i0 = 0; i0 < nu; i0 += 128) {  // same trip count on every lane
+        const int ia = i0 + lane, ib = ia + 64;
+        const UnitRef ua = unit_ref(ia, first, r.src, r.n);
+        const UnitRef ub = unit_ref(ib, first, r.src, r.n);
+        uint32_t sa[4], sb[4];
+        float4 wa[4], wb[4];
+        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, sa, wa);
+        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, sb, wb);
+        if (ia < nu) store_unit_g(e3_w, e3_s, base + ia, sa, wa, prec);
+        if (ib < nu) store_unit_g(e3_w, e3_s, base + ib, sb, wb, prec);
     }
 }
 
@@ -1211,7 +1243,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                     std::max<int64_t>(P.npg + 1, P.ntiles + 1));
     int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
 
-    DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, wl;
+    DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, btile, wl;
     DevBuf used, newpos, ctmp, tbase2, slot2;
     // Buffers go back to the allocation cache, where a setup on another
     // stream may take them at once: the stream's work is drained first.
@@ -1225,6 +1257,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         dev_free(wl);
         dev_free(tnch);
         dev_free(bcnt);
+        dev_free(btile);
         dev_free(key);
         dev_free(cnt);
         dev_free(cursor);
@@ -1415,6 +1448,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(P.ent_w, (size_t)(P.ent_cap ? P.ent_cap : 1) * 16));
     HG_STEP(dev_alloc(P.chunk_ptr, (size_t)(P.chunk_ptrs ? P.chunk_ptrs : 1) * 4));
     HG_STEP(dev_alloc(bcnt, sizeof(int64_t) * (size_t)(P.n_blocks + 1)));
+    HG_STEP(dev_alloc(btile, sizeof(int32_t) * (size_t)(P.n_blocks + 1)));
     HG_STEP(dev_alloc(P.blk_base, sizeof(int64_t) * (size_t)(P.n_blocks + 1)));
     HG_STEP(dev_alloc(P.blk_pgoff, sizeof(uint16_t) * PGOFF_STRIDE * (size_t)(P.n_blocks + 1)));
 
@@ -1506,7 +1540,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            dim3(256), 0, s, P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks,
                            (const int64_t*)P.tile_blk.p, (const int64_t*)P.cp_base.p,
                            (const uint32_t*)P.chunk_ptr.p, (const int64_t*)P.pg_base.p,
-                           (int64_t*)bcnt.p, (uint16_t*)P.blk_pgoff.p);
+                           (int64_t*)bcnt.p, (uint16_t*)P.blk_pgoff.p, (int32_t*)btile.p);
         HG_STEP(hipGetLastError());
         // the largest block sizes the channel kernel's LDS entry area
         hipLaunchKernelGGL(k_max_count, dim3(256), dim3(256), 0, s, (const int64_t*)bcnt.p,
@@ -1531,13 +1565,12 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(P.e3_s, (size_t)(n_ent ? n_ent : 1) * 16));
         if (P.n_blocks > 0) {
             hipLaunchKernelGGL(k_block_fill_g, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s,
-                               P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks, P.chunk,
-                               P.opts.precision, (const int64_t*)P.tile_blk.p,
+                               P.npgx, P.npgy, P.ntx, P.n_blocks, P.chunk, P.opts.precision,
+                               (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
                                (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
                                (const int64_t*)P.pg_base.p, (const uint32_t*)P.ent_slot.p,
                                (const float4*)P.ent_w.p, (const int64_t*)P.blk_base.p,
-                               (const uint16_t*)P.blk_pgoff.p, (uint16_t*)P.e3_w.p,
-                               (uint4*)P.e3_s.p);
+                               (uint16_t*)P.e3_w.p, (uint4*)P.e3_s.p);
             HG_STEP(hipGetLastError());
         }
     } else {
@@ -1545,11 +1578,11 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 16));
         if (P.n_blocks > 0) {
             hipLaunchKernelGGL(k_block_fill, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s,
-                               P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks, P.chunk,
-                               (const int64_t*)P.tile_blk.p, (const int64_t*)P.cp_base.p,
-                               (const uint32_t*)P.chunk_ptr.p, (const int64_t*)P.pg_base.p,
-                               (const uint32_t*)P.ent_slot.p, (const float4*)P.ent_w.p,
-                               (const int64_t*)P.blk_base.p, (const uint16_t*)P.blk_pgoff.p,
+                               P.npgx, P.npgy, P.ntx, P.n_blocks, P.chunk,
+                               (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
+                               (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
+                               (const int64_t*)P.pg_base.p, (const uint32_t*)P.ent_slot.p,
+                               (const float4*)P.ent_w.p, (const int64_t*)P.blk_base.p,
                                (float4*)P.e2_w.p, (uint4*)P.e2_s.p);
             HG_STEP(hipGetLastError());
         }
