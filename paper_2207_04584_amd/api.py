@@ -379,6 +379,57 @@ def _values_arg(values, n):
     return values, (values.stride(0) if values.shape[0] > 1 else values.shape[1])
 
 
+def grid_from_host(ra_deg, dec_deg, map, kernel, values, out=None, precision=HG_PREC_FP32,
+                   chunk=0, dev_values=None, dev_out=None):
+    """Eq. 1 end to end from host memory, with the values' copy to the device
+    hidden behind the setup: setup reads only the coordinates, so the values
+    go over on a stream of their own while the plan is built on the current
+    stream; then the channel kernel runs on the device copy and the cube comes
+    back.  ra_deg, dec_deg: host FP64 [n]; values: host tensor [n][C] (pinned,
+    for the copy to be asynchronous); out: pinned float32 [C][ny][nx] or None.
+    dev_values, dev_out: device buffers to reuse (allocated when None).
+    Returns (out, info): info holds the phases' times in ms (h2d of the
+    values, setup, kernel, d2h of the cube)."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if values.dim() == 1:
+        values = values.reshape(-1, 1)
+    n, nchan = values.shape
+    ny, nx = int(map["ny"]), int(map["nx"])
+    if dev_values is None:
+        dev_values = torch.empty((n, nchan), dtype=values.dtype, device=dev)
+    if dev_out is None:
+        dev_out = torch.empty((nchan, ny, nx), dtype=torch.float32, device=dev)
+    if out is None:
+        out = torch.empty((nchan, ny, nx), dtype=torch.float32, pin_memory=True)
+    cur = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ra = torch.as_tensor(ra_deg, dtype=torch.float64).to(dev, non_blocking=True)
+    dec = torch.as_tensor(dec_deg, dtype=torch.float64).to(dev, non_blocking=True)
+    # the values follow the coordinates over the bus (setup waits only for
+    # those), and their buffer is free once the current stream's earlier work is
+    side.wait_stream(cur)
+    with torch.cuda.stream(side):
+        ev[0].record()
+        dev_values.copy_(values, non_blocking=True)
+        ev[1].record()
+    plan = Plan(ra, dec, map, kernel, precision=precision, chunk=chunk, time_channels=True)
+    try:
+        cur.wait_stream(side)
+        plan.grid(dev_values, dev_out)
+        ev[2].record(cur)
+        out.copy_(dev_out, non_blocking=True)
+        ev[3].record(cur)
+        cur.synchronize()
+        st = plan.stats()
+    finally:
+        plan.close()
+    return out, {"h2d_ms": ev[0].elapsed_time(ev[1]), "setup_ms": st["setup_ms"],
+                 "kernel_ms": st["last_channels_ms"], "d2h_ms": ev[2].elapsed_time(ev[3]),
+                 "nnz": st["nnz"]}
+
+
 class Batch:
     """Many fields gridded by one graph-held launch (hg_batch_create /
     hg_batch_run / hg_batch_destroy).

@@ -9,6 +9,9 @@ in from page-locked (or pageable) host memory and the cube streamed back.
     reference on every pixel.
   * The full 1.9e7-sample field: counts and all 50 channels on pixels
     sampled over the map (corners, edges, interior) against the reference.
+  * The overlapped form bench.py times (api.grid_from_host: the values'
+    copy on a second stream behind the setup, then the device kernel) gives
+    the streamed form's cube bit for bit, on the sub-field and at full size.
 """
 import numpy as np
 import pytest
@@ -64,11 +67,27 @@ def test_paper_subfield_against_reference(pinned):
     assert e_max <= FP32_TOL
 
 
+def overlapped_equals(f, vals, out):
+    ra = torch.from_numpy(f["ra"]).pin_memory()
+    dec = torch.from_numpy(f["dec"]).pin_memory()
+    out2, info = api.grid_from_host(ra, dec, f["map"], f["kernel"], vals)
+    print(f"  overlapped: {info}", flush=True)
+    assert torch.equal(torch.isnan(out2), torch.isnan(out))
+    assert torch.equal(torch.nan_to_num(out2), torch.nan_to_num(out))
+
+
+def test_paper_subfield_overlapped_form():
+    f = synth.paper_field(n=200_000, width=6.0, height=2.0)
+    vals, out, _ = run_end_to_end(f, pinned=True)
+    overlapped_equals(f, vals, out)
+
+
 def test_paper_full_size_sampled_pixels():
     f = synth.paper_field()
     assert f["ra"].shape[0] == 19_000_000
     nx, ny = f["map"]["nx"], f["map"]["ny"]
     vals, out, cnt = run_end_to_end(f, pinned=True)
+    overlapped_equals(f, vals, out)
     rng = np.random.default_rng(6)
     xs = np.concatenate([[0, nx - 1, 0, nx - 1, nx // 2, 0, nx - 1], rng.integers(0, nx, 33)])
     ys = np.concatenate([[0, 0, ny - 1, ny - 1, ny // 2, ny // 2, ny // 2], rng.integers(0, ny, 33)])
