@@ -559,25 +559,35 @@ KernelArgs kernel_args(const Plan& P) {
     return ka;
 }
 
+// What the elliptical kernel needs of a pair beyond d^2: sin(dRA/2) as the
+// haversine took it, dRA = RA_n - RA_p itself (for its whole turns), and the
+// cosines and sines of the two declinations.
+struct PairGeom {
+    double sa, dra, cos_n, sin_n, cos_p, sin_p;
+};
+
 // The weight of a pair in support, from its squared distance d2 and (for the
-// elliptical kernel) the two positions: the bearing theta of the sample seen
+// elliptical kernel) the pair's geometry: the bearing theta of the sample seen
 // from the cell has sin theta : cos theta = E : N with E = cos dec_n sin dRA,
 // N = cos dec_p sin dec_n - sin dec_p cos dec_n cos dRA (both sin d times the
 // unit components), so the offsets along the axes at position angle pa are
-// u = d cos(theta - pa), v = d sin(theta - pa).
+// u = d cos(theta - pa), v = d sin(theta - pa).  sin dRA and cos dRA come from
+// the haversine's half-angle sine: with dRA = 2 pi k + r, |r| <= pi,
+// sin(r/2) = (-1)^k sin(dRA/2) and cos(r/2) = sqrt(1 - sin^2(r/2)) >= 0, so
+// sin dRA = 2 sin(r/2) cos(r/2) and cos dRA = 1 - 2 sin^2(r/2).
 template <int KT>
-__device__ inline double kernel_weight(const KernelArgs& ka, double d2, double ra_n,
-                                       double dec_n, double cos_n, double ra_p, double dec_p,
-                                       double cos_p) {
+__device__ inline double kernel_weight(const KernelArgs& ka, double d2, const PairGeom& g) {
     if (KT == HG_KERNEL_GAUSS) return exp(-d2 * ka.inv_two_s2);
     if (KT == HG_KERNEL_GAUSS_SINC) {
         const double x = sqrt(d2) * ka.pi_b;
         const double sinc = x > 0.0 ? sin(x) / x : 1.0;
         return sinc * exp(-d2 * ka.inv_a2);
     }
-    const double dra = ra_n - ra_p;
-    const double e = cos_n * sin(dra);
-    const double nn = cos_p * sin(dec_n) - sin(dec_p) * cos_n * cos(dra);
+    const double turns = rint(g.dra * (0.5 / kPi));
+    const double sh = ((int64_t)turns & 1) ? -g.sa : g.sa;  // sin(r/2)
+    const double ch = sqrt(fmax(0.0, 1.0 - sh * sh));       // cos(r/2)
+    const double e = g.cos_n * (2.0 * sh * ch);
+    const double nn = g.cos_p * g.sin_n - g.sin_p * g.cos_n * (1.0 - 2.0 * sh * sh);
     const double r2 = e * e + nn * nn;
     if (!(r2 > 0.0)) return 1.0;  // d = 0
     const double ct = nn / sqrt(r2), st = e / sqrt(r2);
@@ -635,6 +645,8 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     pra[3] = HPX ? pix_ra(m, ix + 1, iy + 1) : pra[1];
     double pdec0 = pix_dec(m, iy), pdec1 = pix_dec(m, iy + 1);
     double pcos0 = cos(pdec0), pcos1 = cos(pdec1);
+    const double psin0 = KT == HG_KERNEL_ELLIPTICAL ? sin(pdec0) : 0.0;
+    const double psin1 = KT == HG_KERNEL_ELLIPTICAL ? sin(pdec1) : 0.0;
     int cnt[4] = {0, 0, 0, 0};
     double wsum[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t base_out = pg_base[pg];
@@ -674,21 +686,30 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
             }
             // One exp per pass with the pixels rotated through the first
             // place, so the kernel holds one inlined copy of exp rather than
-            // four (which cost a third of the occupancy in registers).
+            // four (which cost a third of the occupancy in registers).  The
+            // elliptical kernel's pair geometry rotates with them (unused by
+            // the other shapes, so it costs them nothing).
             double h0 = hk[0], h1 = hk[1], h2 = hk[2], h3 = hk[3];
+            double s0 = sa[0], s1 = sa[1], s2 = sa[2], s3 = sa[3];
+            double r0 = c.x - pra[0], r1 = c.x - pra[1], r2 = c.x - pra[2], r3 = c.x - pra[3];
             uint32_t mk = mask;
 #pragma unroll 1
             for (int k = 0; k < 4; k++) {
                 float wf = 0.f;
                 if (mk & 1u) {
-                    const double w =
-                        kernel_weight<KT>(ka, dist2<SMALL>(h0), c.x, c.y, c.z, pra[k],
-                                          (k >> 1) ? pdec1 : pdec0, (k >> 1) ? pcos1 : pcos0);
-                    wf = round_weight((float)w, prec);
+                    const PairGeom g{s0, r0, c.z, c.w, (k >> 1) ? pcos1 : pcos0,
+                                     (k >> 1) ? psin1 : psin0};
+                    wf = round_weight((float)kernel_weight<KT>(ka, dist2<SMALL>(h0), g), prec);
                 }
                 h0 = h1;
                 h1 = h2;
                 h2 = h3;
+                s0 = s1;
+                s1 = s2;
+                s2 = s3;
+                r0 = r1;
+                r1 = r2;
+                r2 = r3;
                 w[0] = w[1];
                 w[1] = w[2];
                 w[2] = w[3];
@@ -1216,12 +1237,13 @@ __global__ void k_sorted_coords_dev(const double* __restrict__ ra_deg,
                                     const double* __restrict__ dec_deg,
                                     const uint32_t* __restrict__ srt_idx,
                                     const uint32_t* __restrict__ n_used_dev, int64_t n,
-                                    double4* __restrict__ out) {
+                                    int32_t with_sin, double4* __restrict__ out) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n || q >= (int64_t)*n_used_dev) return;
     uint32_t k = srt_idx[q];
     double ra = ra_deg[k] * kDeg, dec = dec_deg[k] * kDeg;
-    out[q] = make_double4(ra, dec, cos(dec), 0.0);
+    // (RA, Dec, cos Dec, sin Dec or 0): the sine only for the elliptical kernel
+    out[q] = make_double4(ra, dec, cos(dec), with_sin ? sin(dec) : 0.0);
 }
 
 // Runs the whole setup.  Allocation sizes that depend on the data are read
@@ -1359,6 +1381,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         hipLaunchKernelGGL(k_sorted_coords_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, ra_deg,
                            dec_deg, (const uint32_t*)P.srt_idx.p,
                            (const uint32_t*)P.cell_off.p + P.n_cells, n,
+                           (int32_t)(P.kern.type == HG_KERNEL_ELLIPTICAL),
                            (double4*)P.srt_coord.p);
         HG_STEP(hipGetLastError());
     }
