@@ -108,8 +108,9 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_final(const Tin* in, int64_t n,
 }
 
 // Short arrays in one workgroup: tiles of SCAN_B scanned in turn with a
-// running carry (three launches of a few microseconds each otherwise).
-constexpr int64_t SCAN_ONE_MAX = 8 * SCAN_B;
+// running carry (three launches of a few microseconds each otherwise; past
+// two tiles the three launches are quicker than the serial tiles).
+constexpr int64_t SCAN_ONE_MAX = 2 * SCAN_B;
 
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(SCAN_T) void k_scan_one(const Tin* in, int64_t n, Tout* out) {
@@ -1451,8 +1452,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     if (P.opts.device_mem_cap > 0) {
         // slot list, entries, chunk pointers, and the slot compaction's
         // transient arrays (flag, new position, compacted list: 16 B a slot);
-        // the entry blocks pad each (group, chunk) run to four entries
-        size_t need = (size_t)P.total_slots * (4 + 16) + (size_t)P.ent_cap * 20 +
+        // the entry blocks take 20 B an entry in the FP32 form (12 B in the
+        // 16-bit forms) and pad each (group, chunk) run to four entries
+        const size_t blk_entry = P.opts.precision == HG_PREC_FP32 ? 20 : 12;
+        size_t need = (size_t)P.total_slots * (4 + 16) + (size_t)P.ent_cap * (20 + blk_entry) +
                       (size_t)P.chunk_ptrs * (4 + 60);
         size_t have = 0;
         for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
