@@ -560,6 +560,30 @@ KernelArgs kernel_args(const Plan& P) {
     return ka;
 }
 
+// e^x for x <= 0, to within 3e-13 relative: ample for a weight that is then
+// rounded to FP32 (it changes about one rounding in a million, by an ulp).
+// x = n ln 2 + r with |r| <= ln 2 / 2, r from one fused multiply-add (for the
+// n that matter, |n| <= 160, the error of ln 2 in a double shifts r by under
+// 4e-15), e^r by its Taylor series to r^10 (remainder below 2.4e-13), scaled
+// by 2^n.  x is clamped at -800, where e^x is already 0 in FP64.
+__device__ inline double exp_w(double x) {
+    x = fmax(x, -800.0);
+    const double n = rint(x * 1.4426950408889634);  // x / ln 2
+    const double r = fma(-n, 0.6931471805599453, x);
+    double p = 1.0 / 3628800.0;  // 1/10!
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
 // What the elliptical kernel needs of a pair beyond d^2: sin(dRA/2) as the
 // haversine took it, dRA = RA_n - RA_p itself (for its whole turns), and the
 // cosines and sines of the two declinations.
@@ -578,11 +602,11 @@ struct PairGeom {
 // sin dRA = 2 sin(r/2) cos(r/2) and cos dRA = 1 - 2 sin^2(r/2).
 template <int KT>
 __device__ inline double kernel_weight(const KernelArgs& ka, double d2, const PairGeom& g) {
-    if (KT == HG_KERNEL_GAUSS) return exp(-d2 * ka.inv_two_s2);
+    if (KT == HG_KERNEL_GAUSS) return exp_w(-d2 * ka.inv_two_s2);
     if (KT == HG_KERNEL_GAUSS_SINC) {
         const double x = sqrt(d2) * ka.pi_b;
         const double sinc = x > 0.0 ? sin(x) / x : 1.0;
-        return sinc * exp(-d2 * ka.inv_a2);
+        return sinc * exp_w(-d2 * ka.inv_a2);
     }
     const double turns = rint(g.dra * (0.5 / kPi));
     const double sh = ((int64_t)turns & 1) ? -g.sa : g.sa;  // sin(r/2)
@@ -594,7 +618,7 @@ __device__ inline double kernel_weight(const KernelArgs& ka, double d2, const Pa
     const double ct = nn / sqrt(r2), st = e / sqrt(r2);
     const double cu = ct * ka.cos_pa + st * ka.sin_pa;  // cos(theta - pa)
     const double sv = st * ka.cos_pa - ct * ka.sin_pa;  // sin(theta - pa)
-    return exp(-d2 * (cu * cu * ka.inv_two_smaj2 + sv * sv * ka.inv_two_smin2));
+    return exp_w(-d2 * (cu * cu * ka.inv_two_smaj2 + sv * sv * ka.inv_two_smin2));
 }
 
 // One wave per pixel group.  Lanes walk the group's candidates in slot order;
@@ -612,7 +636,10 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     uint32_t* __restrict__ pg_cnt, int32_t* __restrict__ pix_count, double* __restrict__ pix_W,
     float* __restrict__ pix_Wf, unsigned long long* __restrict__ nnz_total) {
     extern __shared__ int sh_gather[];
-    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index through a scalar register, so that the group's scalars
+    // (its entry base among them) come by scalar loads, outside the vector
+    // memory counter that the candidate loads are waited on by
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     int64_t pg = (int64_t)blockIdx.x * GATHER_WAVES + wave;
     if (pg >= npg) return;  // uniform per wave; no block barrier below
     int npc = 2 * pg_rings;
@@ -652,18 +679,33 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     double wsum[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t base_out = pg_base[pg];
     int written = 0;
-    int lo = 0;  // the piece holding candidate v; v only grows, so lo only advances
+    // Candidate v's coordinates and slot are loaded one pass ahead of their
+    // use, so that the load's latency overlaps the previous pass's arithmetic.
+    // lo: the piece holding the candidate loaded last; v only grows, so lo
+    // only advances (each search stops by pref[npc] = total > v).
+    int lo = 0;
+    double4 cn = make_double4(0.0, 0.0, 0.0, 0.0);
+    uint32_t sn = 0;
+    if (lane < total) {
+        while (pref[lo + 1] <= lane) lo++;
+        const int off = lane - pref[lo];
+        cn = srt_coord[ppos[lo] + off];
+        sn = (uint32_t)(pslot[lo] + off);
+    }
     for (int v0 = 0; v0 < total; v0 += 64) {
         int v = v0 + lane;
         bool active = v < total;
         uint32_t mask = 0;
         float w[4] = {0.f, 0.f, 0.f, 0.f};
-        uint32_t slot = 0;
+        const double4 c = cn;
+        const uint32_t slot = sn;
+        if (v + 64 < total) {
+            while (pref[lo + 1] <= v + 64) lo++;
+            const int off = v + 64 - pref[lo];
+            cn = srt_coord[ppos[lo] + off];
+            sn = (uint32_t)(pslot[lo] + off);
+        }
         if (active) {
-            while (pref[lo + 1] <= v) lo++;  // stops by pref[npc] = total > v
-            int off = v - pref[lo];
-            double4 c = srt_coord[ppos[lo] + off];
-            slot = (uint32_t)(pslot[lo] + off);
             double sd0, sd1, sa[4];
             half_sines(0.5 * (c.y - pdec0), 0.5 * (c.y - pdec1), 0.5 * (c.x - pra[0]),
                        0.5 * (c.x - pra[1]), sd0, sd1, sa[0], sa[1]);
