@@ -174,7 +174,10 @@ int hg_grid_setup(const double* ra_deg, const double* dec_deg, int64_t n, const 
  *           a cell has no neighbour).
  *   Asynchronous on hip_stream: the caller keeps values and out alive until
  *   the stream has passed this point.  With HG_FLAG_TIME_CHANNELS the kernel
- *   time is recorded with HIP events on the same stream.
+ *   time is recorded with HIP events on the same stream.  The first call with
+ *   a given number of 256-channel blocks also uploads, on hip_stream, the
+ *   order in which the kernel's workgroups take the plan's tiles (a few KB,
+ *   kept by the plan until hg_grid_finish).
  */
 int hg_grid_channels(hg_plan* p, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
                      float* out, void* hip_stream);

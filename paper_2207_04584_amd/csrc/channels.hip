@@ -651,18 +651,17 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ blk_base,
     const uint16_t* __restrict__ blk_pgoff, const void* __restrict__ ent_w,
     const void* __restrict__ ent_s, const float* __restrict__ pix_Wf, float* __restrict__ out,
-    int32_t out_vec, int32_t ucap, int32_t nbuf) {
+    int32_t out_vec, int32_t ucap, int32_t nbuf, const int64_t* __restrict__ order) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous run of (tile, channel block) so that a tile's channel blocks
-    // (which share its entry blocks) and neighbouring tiles (which share halo
-    // samples) meet in the same L2.
-    int64_t nwg = gridDim.x, b = blockIdx.x;
-    int64_t q8 = nwg / 8, r8 = nwg % 8, xcd = b % 8, idx = b / 8;
-    int64_t logical = xcd * q8 + (xcd < r8 ? xcd : r8) + idx;
+    // Workgroup b takes the plan's item order[b] (tile * ncb + channel block),
+    // laid out as for the batched form: a tile's channel blocks on one XCD,
+    // tiles placed longest first over the XCDs, each XCD's items by decreasing
+    // cost; -1 marks an idle workgroup.
+    const int64_t item = order[blockIdx.x];
+    if (item < 0) return;
     grid_item<FORM, DT, VEC>(values, ld, nchan, npgx, npgy, ntx, nx, ny, chunk, tile_base,
                              slot_idx, tile_blk, blk_base, blk_pgoff, ent_w, ent_s, pix_Wf, out,
-                             out_vec, ucap, nbuf, logical / ncb, logical % ncb, smem);
+                             out_vec, ucap, nbuf, item / ncb, item % ncb, smem);
 }
 
 // Batched form: one launch over the (field, tile, channel block) items of many
@@ -709,8 +708,7 @@ size_t lds_shm(bool m16, int chunk, int ucap, int nbuf) {
 }
 
 template <int FORM, int DT, bool VEC>
-hipError_t launch_typed(const FieldDesc& d, int64_t ntiles, hipStream_t s) {
-    int64_t nwg = (int64_t)d.ncb * ntiles;
+hipError_t launch_typed(const FieldDesc& d, const int64_t* order, int64_t nwg, hipStream_t s) {
     size_t shm = lds_shm(FORM == FORM_M16, d.chunk, d.ucap, d.nbuf);
     auto kern = k_channels<FORM, DT, VEC>;
     if (shm > 65536) {
@@ -721,7 +719,7 @@ hipError_t launch_typed(const FieldDesc& d, int64_t ntiles, hipStream_t s) {
     hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(CH_THREADS), shm, s, d.values, d.ld,
                        d.nchan, d.ncb, d.npgx, d.npgy, d.ntx, d.nx, d.ny, d.chunk, d.tile_base,
                        d.slot_idx, d.tile_blk, d.blk_base, d.blk_pgoff, d.ent_w, d.ent_s,
-                       d.pix_Wf, d.out, d.out_vec, d.ucap, d.nbuf);
+                       d.pix_Wf, d.out, d.out_vec, d.ucap, d.nbuf, order);
     return hipGetLastError();
 }
 
@@ -784,21 +782,25 @@ hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t ncha
                            float* out, hipStream_t s) {
     bool vec = values_vec(P, values, ld, dtype);
     FieldDesc d = field_desc(P, values, ld, nchan, out);
+    const int64_t* order = nullptr;
+    int64_t nwg = 0;
+    hipError_t e = launch_order(P, d.ncb, s, &order, &nwg);
+    if (e != hipSuccess) return e;
     if (P.opts.precision != HG_PREC_FP32) {
         if (dtype == HG_BF16)
-            return vec ? launch_typed<FORM_M16, HG_BF16, true>(d, P.ntiles, s)
-                       : launch_typed<FORM_M16, HG_BF16, false>(d, P.ntiles, s);
-        return vec ? launch_typed<FORM_M16, HG_F16, true>(d, P.ntiles, s)
-                   : launch_typed<FORM_M16, HG_F16, false>(d, P.ntiles, s);
+            return vec ? launch_typed<FORM_M16, HG_BF16, true>(d, order, nwg, s)
+                       : launch_typed<FORM_M16, HG_BF16, false>(d, order, nwg, s);
+        return vec ? launch_typed<FORM_M16, HG_F16, true>(d, order, nwg, s)
+                   : launch_typed<FORM_M16, HG_F16, false>(d, order, nwg, s);
     }
     if (dtype == HG_F32)
-        return vec ? launch_typed<FORM_F32, HG_F32, true>(d, P.ntiles, s)
-                   : launch_typed<FORM_F32, HG_F32, false>(d, P.ntiles, s);
+        return vec ? launch_typed<FORM_F32, HG_F32, true>(d, order, nwg, s)
+                   : launch_typed<FORM_F32, HG_F32, false>(d, order, nwg, s);
     if (dtype == HG_BF16)
-        return vec ? launch_typed<FORM_F32, HG_BF16, true>(d, P.ntiles, s)
-                   : launch_typed<FORM_F32, HG_BF16, false>(d, P.ntiles, s);
-    return vec ? launch_typed<FORM_F32, HG_F16, true>(d, P.ntiles, s)
-               : launch_typed<FORM_F32, HG_F16, false>(d, P.ntiles, s);
+        return vec ? launch_typed<FORM_F32, HG_BF16, true>(d, order, nwg, s)
+                   : launch_typed<FORM_F32, HG_BF16, false>(d, order, nwg, s);
+    return vec ? launch_typed<FORM_F32, HG_F16, true>(d, order, nwg, s)
+               : launch_typed<FORM_F32, HG_F16, false>(d, order, nwg, s);
 }
 
 bool channel_lds_fits(bool m16, int chunk, int blk_max) {

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -143,6 +144,16 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// The order in which the channel kernel's workgroups take a plan's (tile,
+// channel block) items, for one channel-block count: item b of the launch is
+// tile * ncb + cb, or -1 for an idle workgroup (see launch_order).
+struct LaunchOrder {
+    DevBuf items;               // int64 [n] on the device
+    std::vector<int64_t> host;  // the same on the host, the upload's source
+    hipEvent_t ready = nullptr; // recorded after the upload
+    int64_t n = 0;
+};
+
 // Rings for host-streamed channel blocks (hg_grid_channels_host): two device
 // slots of values and maps, two pinned host slots for callers whose buffers
 // are pageable, and the two copy streams.  Kept by the plan across calls.
@@ -194,6 +205,8 @@ struct Plan {
     int64_t n_blocks = 0;
     int32_t blk_max = 0;  // most units (entries, or groups of four) in one block
     DevBuf tile_blk;     // int64 [ntiles+1] first block of each tile
+    std::vector<int64_t> tile_blk_host;       // the same, on the host (launch order costs)
+    std::map<int32_t, LaunchOrder> orders;    // launch orders by channel-block count
     DevBuf blk_base;     // int64 [n_blocks+1] first entry of each block
     DevBuf blk_pgoff;    // uint16 [n_blocks][PGOFF_STRIDE] per-group offsets in the block
     DevBuf e2_w;         // float [units][4 pixels][4 entries] weights, block order
@@ -277,6 +290,10 @@ __host__ __device__ inline double col_ra_hi(const hg_map& m, int64_t i) {
         return ((double)(m.pix0 + i) + 0.5) * (kPi / (2.0 * (double)m.nside));
     return pix_ra(m, i, 0);
 }
+
+// The launch order of a plan's channel kernel for ncb channel blocks, built
+// and uploaded on stream s at its first use (runtime.hip).
+hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** items, int64_t* n);
 
 // kernel launchers (setup.hip, channels.hip, literal.hip)
 hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hipStream_t s,

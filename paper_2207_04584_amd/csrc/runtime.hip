@@ -172,6 +172,11 @@ void plan_free(Plan& P) {
     }
     P.ev_pending.clear();
     P.ev_free.clear();
+    for (auto& kv : P.orders) {
+        dev_free(kv.second.items);
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    }
+    P.orders.clear();
 }
 
 int64_t plan_bytes(const Plan& P) {
@@ -183,6 +188,7 @@ int64_t plan_bytes(const Plan& P) {
                             &P.e3_w, &P.e3_s})
         s += (int64_t)b->bytes;
     for (int k = 0; k < RING_SLOTS; k++) s += (int64_t)(P.ring.vals[k].bytes + P.ring.out[k].bytes);
+    for (const auto& kv : P.orders) s += (int64_t)kv.second.items.bytes;
     return s;
 }
 
@@ -525,6 +531,44 @@ std::vector<BatchItem> plan_batch_items(const std::vector<std::vector<int64_t>>&
 }
 
 }  // namespace
+
+// The single-field launch uses the batched form's layout (plan_batch_items
+// with one field): idle workgroups pad the XCDs' lists to equal length.  The
+// order is built and uploaded on the first launch with a given channel-block
+// count and kept with the plan; a later launch on another stream waits for
+// the upload's event.
+hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** items, int64_t* n) {
+    if (P.tile_blk_host.size() != (size_t)P.ntiles + 1) return hipErrorNotInitialized;
+    auto it = P.orders.find(ncb);
+    if (it == P.orders.end()) {
+        LaunchOrder o;
+        int64_t n_items = 0;
+        const std::vector<BatchItem> pos = plan_batch_items({P.tile_blk_host}, {ncb}, n_items);
+        o.host.resize(pos.size());
+        for (size_t i = 0; i < pos.size(); i++)
+            o.host[i] = pos[i].field < 0 ? -1 : pos[i].tile * ncb + pos[i].cb;
+        o.n = (int64_t)pos.size();
+        hipError_t e = dev_alloc(o.items, sizeof(int64_t) * (o.host.empty() ? 1 : o.host.size()));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&o.ready, hipEventDisableTiming);
+        if (e == hipSuccess && !o.host.empty())
+            e = hipMemcpyAsync(o.items.p, o.host.data(), sizeof(int64_t) * o.host.size(),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(o.ready, s);
+        if (e != hipSuccess) {
+            dev_free(o.items);
+            if (o.ready) (void)hipEventDestroy(o.ready);
+            return e;
+        }
+        it = P.orders.emplace(ncb, std::move(o)).first;
+    } else {
+        hipError_t e = hipStreamWaitEvent(s, it->second.ready, 0);
+        if (e != hipSuccess) return e;
+    }
+    *items = (const int64_t*)it->second.items.p;
+    *n = it->second.n;
+    return hipSuccess;
+}
+
 }  // namespace hg
 
 using namespace hg;

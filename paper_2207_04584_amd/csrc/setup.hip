@@ -1655,6 +1655,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
             HG_STEP(hipGetLastError());
         }
     }
+    // per-tile chunk counts for the channel kernel's launch order
+    P.tile_blk_host.assign((size_t)P.ntiles + 1, 0);
+    HG_STEP(hipMemcpyAsync(P.tile_blk_host.data(), P.tile_blk.p, sizeof(int64_t) * (P.ntiles + 1),
+                           hipMemcpyDeviceToHost, s));
     HG_STEP(hipStreamSynchronize(s));
     cleanup();
     return hipSuccess;
