@@ -867,7 +867,20 @@ __global__ __launch_bounds__(256) void k_mark_used(
     const int lane = threadIdx.x & 63;
     const int64_t tb = tile_base[pg_tile(pg, npgx, ntx)];
     const uint32_t* es = ent_slot + pg_base[pg];
-    for (uint32_t t = lane; t < pg_cnt[pg]; t += 64) used[tb + (es[t] & SLOT_MASK)] = 1u;
+    const uint32_t n = pg_cnt[pg];
+    // four entries a lane per pass, their loads in flight together (a group
+    // of a wide support holds thousands of entries)
+    for (uint32_t t0 = 0; t0 < n; t0 += 256) {
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t t = t0 + lane + 64 * k;
+            w[k] = t < n ? es[t] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (t0 + lane + 64 * k < n) used[tb + (w[k] & SLOT_MASK)] = 1u;
+    }
 }
 
 __global__ void k_tile_rebase(const int64_t* __restrict__ tile_base, int64_t ntiles,
@@ -894,10 +907,25 @@ __global__ __launch_bounds__(256) void k_remap_entries(
     const int64_t tile = pg_tile(pg, npgx, ntx);
     const int64_t tb = tile_base[tile], tb2 = tile_base2[tile];
     uint32_t* es = ent_slot + pg_base[pg];
-    for (uint32_t t = lane; t < pg_cnt[pg]; t += 64) {
-        uint32_t w = es[t];
-        uint32_t slot = (uint32_t)(newpos[tb + (w & SLOT_MASK)] - tb2);
-        es[t] = slot | (w & ~SLOT_MASK);
+    const uint32_t n = pg_cnt[pg];
+    // four entries a lane per pass: their loads, then their position lookups,
+    // each in flight together
+    for (uint32_t t0 = 0; t0 < n; t0 += 256) {
+        uint32_t w[4];
+        int64_t np[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t t = t0 + lane + 64 * k;
+            w[k] = t < n ? es[t] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            np[k] = t0 + lane + 64 * k < n ? newpos[tb + (w[k] & SLOT_MASK)] : tb2;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t t = t0 + lane + 64 * k;
+            if (t < n) es[t] = (uint32_t)(np[k] - tb2) | (w[k] & ~SLOT_MASK);
+        }
     }
 }
 
