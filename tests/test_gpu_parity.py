@@ -211,6 +211,29 @@ def test_runs_are_deterministic():
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
 
 
+def test_launch_orders_per_channel_block_count_and_stream():
+    """A plan keeps one launch order per channel-block count: calls that
+    alternate between counts, and a call on a second stream (which waits for
+    the order's upload), give the same maps as a fresh plan."""
+    f = synth.config("cfg1")
+    vals = synth.sky_values(f, 600, device=DEV)
+    with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"]) as p:
+        ref600 = torch.nan_to_num(p.grid(vals), 7.0)
+    with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"]) as p:
+        a = p.grid(vals[:, :5])  # one channel block
+        b = p.grid(vals)  # three
+        c = p.grid(vals[:, :300])  # two
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            d = p.grid(vals, stream=side)  # the three-block order again, on another stream
+        torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(b, 7.0), ref600)
+    assert torch.equal(torch.nan_to_num(d, 7.0), ref600)
+    assert torch.equal(torch.nan_to_num(a, 7.0), ref600[:5])
+    assert torch.equal(torch.nan_to_num(c, 7.0), ref600[:300])
+
+
 def test_cfg2_full_size_sampled_parity():
     """1e6 drift-scan samples, 300 x 300 map, 1024 FP32 channels: the bench
     workload and launch configuration; reference on sampled pixels."""
