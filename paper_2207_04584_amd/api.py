@@ -408,13 +408,18 @@ def grid_from_host(ra_deg, dec_deg, map, kernel, values, out=None, precision=HG_
     ra = torch.as_tensor(ra_deg, dtype=torch.float64).to(dev, non_blocking=True)
     dec = torch.as_tensor(dec_deg, dtype=torch.float64).to(dev, non_blocking=True)
     # the values follow the coordinates over the bus (setup waits only for
-    # those), and their buffer is free once the current stream's earlier work is
+    # those), and their buffer is free once the current stream's earlier work
+    # is done
     side.wait_stream(cur)
     with torch.cuda.stream(side):
         ev[0].record()
         dev_values.copy_(values, non_blocking=True)
         ev[1].record()
-    plan = Plan(ra, dec, map, kernel, precision=precision, chunk=chunk, time_channels=True)
+    try:
+        plan = Plan(ra, dec, map, kernel, precision=precision, chunk=chunk, time_channels=True)
+    except Exception:
+        side.synchronize()  # the copy still writes dev_values, which may be freed on return
+        raise
     try:
         cur.wait_stream(side)
         plan.grid(dev_values, dev_out)
@@ -424,6 +429,7 @@ def grid_from_host(ra_deg, dec_deg, map, kernel, values, out=None, precision=HG_
         cur.synchronize()
         st = plan.stats()
     finally:
+        side.synchronize()
         plan.close()
     return out, {"h2d_ms": ev[0].elapsed_time(ev[1]), "setup_ms": st["setup_ms"],
                  "kernel_ms": st["last_channels_ms"], "d2h_ms": ev[2].elapsed_time(ev[3]),
