@@ -63,9 +63,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(f, vals_host, n_pix, seed=7):
+def cpu_baseline(f, vals_host, n_pix, seed=7, gpu_out=None):
     """The reference gridder as it stands, single-threaded, on a random subset
-    of the map's pixels with all channels; scaled to the full map."""
+    of the map's pixels with all channels; scaled to the full map.  With
+    gpu_out (the timed path's last map, host [C][P]) the same pixels also give
+    the path's error against the reference: per channel max |V - V_ref| over
+    max |V_ref|, and the same with RMS norms, worst channel."""
     import numpy as np
 
     import oracle
@@ -73,15 +76,27 @@ def cpu_baseline(f, vals_host, n_pix, seed=7):
     P = m["nx"] * m["ny"]
     pix = np.sort(np.random.default_rng(seed).choice(P, n_pix, replace=False))
     t0 = time.perf_counter()
-    oracle.grid(f["ra"], f["dec"], vals_host, "f32", m, f["kernel"]["fwhm_deg"],
-                f["kernel"]["support_deg"], pix=pix, kernel=f["kernel"])
+    Vr, cnt, _, _ = oracle.grid(f["ra"], f["dec"], vals_host, "f32", m, f["kernel"]["fwhm_deg"],
+                                f["kernel"]["support_deg"], pix=pix, kernel=f["kernel"])
     dt = time.perf_counter() - t0
     full_s = dt * P / n_pix
     n, C = vals_host.shape
-    return {"value": n * C / full_s / 1e9, "unit": "G sample*channel updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n_pix} of {P} pixels x all {C} channels ({dt:.1f} s), scaled by "
-                      f"{P / n_pix:.1f} to the full map"}
+    res = {"value": n * C / full_s / 1e9, "unit": "G sample*channel updates/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"{n_pix} of {P} pixels x all {C} channels ({dt:.1f} s), scaled by "
+                     f"{P / n_pix:.1f} to the full map"}
+    if gpu_out is not None:
+        ok = cnt > 0
+        V = gpu_out[:, pix][:, ok].astype(np.float64)
+        R = Vr[:, ok]
+        d = np.abs(V - R)
+        e_max = float((d.max(1) / np.maximum(np.abs(R).max(1), 1e-300)).max())
+        e_rms = float((np.sqrt((d ** 2).mean(1)) /
+                       np.maximum(np.sqrt((R ** 2).mean(1)), 1e-300)).max())
+        nan_match = bool((np.isnan(gpu_out[:, pix]) == np.isnan(Vr)).all())
+        res["parity"] = {"e_max": e_max, "e_rms": e_rms, "nan_match": nan_match,
+                         "pixels": int(ok.sum())}
+    return res
 
 
 def measured_traffic(workload):
@@ -240,8 +255,10 @@ def run_drift(args):
     if not args.no_cpu_baseline:
         log(f"cpu baseline: reference gridder on {args.cpu_pixels} pixels")
         vals_host = vals.cpu().numpy()
-        res["cpu_baseline"] = cpu_baseline(f, vals_host, args.cpu_pixels)
-        log(f"cpu baseline: {res['cpu_baseline']['sample']}")
+        res["cpu_baseline"] = cpu_baseline(f, vals_host, args.cpu_pixels,
+                                           gpu_out=out.reshape(C, -1).cpu().numpy())
+        log(f"cpu baseline: {res['cpu_baseline']['sample']}; parity "
+            f"{res['cpu_baseline'].get('parity')}")
     return res
 
 
@@ -540,7 +557,8 @@ def run_paper(args):
     }
     if not args.no_cpu_baseline:
         log(f"cpu baseline: reference gridder on {args.cpu_pixels} pixels")
-        res["cpu_baseline"] = cpu_baseline(f, vals.numpy(), args.cpu_pixels)
+        res["cpu_baseline"] = cpu_baseline(f, vals.numpy(), args.cpu_pixels,
+                                           gpu_out=out.reshape(C, -1).numpy())
         log(f"cpu baseline: {res['cpu_baseline']['sample']}")
     return res
 
