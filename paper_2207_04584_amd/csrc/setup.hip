@@ -634,7 +634,7 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     const double4* __restrict__ srt_coord, int32_t npgx, int64_t npg, hg_map m, double h_r,
     KernelArgs ka, int32_t prec, uint32_t* __restrict__ ent_slot, float4* __restrict__ ent_w,
     uint32_t* __restrict__ pg_cnt, int32_t* __restrict__ pix_count, double* __restrict__ pix_W,
-    float* __restrict__ pix_Wf, unsigned long long* __restrict__ nnz_total) {
+    float* __restrict__ pix_Wf) {
     extern __shared__ int sh_gather[];
     // the wave index through a scalar register, so that the group's scalars
     // (its entry base among them) come by scalar loads, outside the vector
@@ -774,7 +774,6 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
         }
         written += __popcll(bal);
     }
-    int tot = 0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         int c = cnt[k];
@@ -785,7 +784,6 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
         }
         cnt[k] = c;
         wsum[k] = s;
-        tot += c;
     }
     if (lane == 0) {
         pg_cnt[pg] = (uint32_t)written;
@@ -799,8 +797,24 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 pix_Wf[p] = (float)wsum[k];
             }
         }
-        atomicAdd(nnz_total, (unsigned long long)tot);
     }
+}
+
+// sum of a[0..n) into *out, which starts at 0: a grid-stride pass, a
+// workgroup reduction, one atomic per workgroup (the total of the pixels'
+// neighbour counts, kept out of the gather, where one atomic per pixel group
+// on a single address serialised)
+__global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ a, int64_t n,
+                                                    unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long red[4];
+    unsigned long long t = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        t += (unsigned long long)a[i];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, red[0] + red[1] + red[2] + red[3]);
 }
 
 // the gather instance for a kernel shape, support size and map kind
@@ -1566,7 +1580,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const int64_t*)P.pg_base.p, (const double4*)P.srt_coord.p, P.npgx,
                            P.npg, P.map, P.h_r, ka, P.opts.precision, (uint32_t*)P.ent_slot.p,
                            (float4*)P.ent_w.p, (uint32_t*)P.pg_cnt.p, (int32_t*)P.pix_count.p,
-                           (double*)P.pix_W.p, (float*)P.pix_Wf.p, nnz_total);
+                           (double*)P.pix_W.p, (float*)P.pix_Wf.p);
+        HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_sum_counts, dim3(256), dim3(256), 0, s,
+                           (const int32_t*)P.pix_count.p, P.npix, nnz_total);
         HG_STEP(hipGetLastError());
     }
     // 5b: drop the slots no pixel of their tile uses, then recount chunks
