@@ -1332,7 +1332,9 @@ __global__ void k_sorted_coords_dev(const double* __restrict__ ra_deg,
 }
 
 // Runs the whole setup.  Allocation sizes that depend on the data are read
-// back once (one stream synchronisation in the middle, one at the end).
+// back as they are needed (the candidate arrays', the compacted slots' and
+// blocks', the entry blocks'), each with one stream synchronisation, and the
+// launch order's chunk counts with the one at the end.
 hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hipStream_t s,
                         std::string& err, int& status) {
     const double eps = 1e-9;
