@@ -379,6 +379,19 @@ def _values_arg(values, n):
     return values, (values.stride(0) if values.shape[0] > 1 else values.shape[1])
 
 
+_side_streams = {}
+
+
+def _side_stream(dev):
+    """One copy stream per device, made once: a stream made per call lands on
+    a different hardware queue each time, sometimes the current stream's."""
+    torch = _torch()
+    key = dev.index
+    if key not in _side_streams:
+        _side_streams[key] = torch.cuda.Stream(device=dev)
+    return _side_streams[key]
+
+
 def grid_from_host(ra_deg, dec_deg, map, kernel, values, out=None, precision=HG_PREC_FP32,
                    chunk=0, dev_values=None, dev_out=None):
     """Eq. 1 end to end from host memory, with the values' copy to the device
@@ -403,7 +416,7 @@ def grid_from_host(ra_deg, dec_deg, map, kernel, values, out=None, precision=HG_
     if out is None:
         out = torch.empty((nchan, ny, nx), dtype=torch.float32, pin_memory=True)
     cur = torch.cuda.current_stream()
-    side = torch.cuda.Stream()
+    side = _side_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ra = torch.as_tensor(ra_deg, dtype=torch.float64).to(dev, non_blocking=True)
     dec = torch.as_tensor(dec_deg, dtype=torch.float64).to(dev, non_blocking=True)
