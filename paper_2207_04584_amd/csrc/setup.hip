@@ -727,16 +727,18 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 hk[k] = sd * sd + pc * c.z * sa_k * sa_k;
                 if (ok && hk[k] <= h_r) mask |= 1u << k;
             }
-            // One exp per pass with the pixels rotated through the first
-            // place, so the kernel holds one inlined copy of exp rather than
-            // four (which cost a third of the occupancy in registers).  The
-            // elliptical kernel's pair geometry rotates with them (unused by
-            // the other shapes, so it costs them nothing).
+            // The four pixels' weights in turn, each pixel rotated through the
+            // first place.  The Gaussian's exponential is short enough to be
+            // inlined four times (the rotations then cost nothing); the other
+            // shapes keep one inlined copy, which four would cost occupancy.
+            // The elliptical kernel's pair geometry rotates with the pixels
+            // (unused by the other shapes, so it costs them nothing).
+            constexpr int PIX_UNROLL = KT == HG_KERNEL_GAUSS ? 4 : 1;
             double h0 = hk[0], h1 = hk[1], h2 = hk[2], h3 = hk[3];
             double s0 = sa[0], s1 = sa[1], s2 = sa[2], s3 = sa[3];
             double r0 = c.x - pra[0], r1 = c.x - pra[1], r2 = c.x - pra[2], r3 = c.x - pra[3];
             uint32_t mk = mask;
-#pragma unroll 1
+#pragma unroll PIX_UNROLL
             for (int k = 0; k < 4; k++) {
                 float wf = 0.f;
                 if (mk & 1u) {
