@@ -287,7 +287,7 @@ def batch_inputs(args):
 
 
 def run_fifo(args):
-    """Survey row f3: the 64 fields through the paper's style of pipeline
+    """The 64 fields through the paper's style of pipeline
     (pipeline.grid_fields_fifo: a FIFO of fields served by host threads with
     a stream each, setup then channel kernel per field), to set the batched
     form against on the same fields and form."""
@@ -394,7 +394,7 @@ def run_batch(args):
 
 
 def run_literal(args):
-    """Survey row f2: the drift workload through Algorithm 1 as the paper
+    """The drift workload through Algorithm 1 as the paper
     states it (hg_grid_channels_literal: one launch per channel, gamma cells
     per thread), to set the tiled matrix-core path against.  A sweep over
     gamma and workgroup size on 16 channels picks the configuration the

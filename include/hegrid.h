@@ -48,7 +48,7 @@ extern "C" {
 #define HG_ERR_STATE 2       /* call not valid for this plan's state      */
 #define HG_ERR_NOMEM 3       /* device allocation failed or over the cap  */
 #define HG_ERR_DEVICE 4      /* no usable device / HIP runtime error      */
-#define HG_ERR_UNSUPPORTED 5 /* valid request this build does not handle  */
+#define HG_ERR_UNSUPPORTED 5 /* valid request the library does not handle */
 #define HG_ERR_INTERNAL 6    /* bug: an unexpected condition              */
 
 /* value dtypes (hg_grid_channels) */

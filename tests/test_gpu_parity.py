@@ -267,7 +267,7 @@ def test_memory_cap_and_bad_coordinates():
 
 # ---------------------------------------------------------------------------
 # Precision forms: BF16 / FP16 weights x values on MFMA, FP32 accumulation, W from
-# the same rounded weights.  Bound (the benchmark spec): <= 2e-3 relative.  The weights
+# the same rounded weights.  Bound: <= 2e-3 relative.  The weights
 # carry the format's rounding (2^-9 for BF16, 2^-12 for FP16 at most, relative).
 MFMA = {"bf16": (1, torch.bfloat16, 2.0 ** -8), "f16": (2, torch.float16, 2.0 ** -11)}
 MFMA_TOL = 2e-3

@@ -295,7 +295,7 @@ def test_bad_arguments_are_rejected():
         oracle.grid([0.0], [0.0], np.zeros((1, 1)), "f64", bad, 0.05, 0.1)
 
 
-# --- other kernel shapes of Eq. 1 (survey row f4): closed forms and invariants
+# --- other kernel shapes of Eq. 1: closed forms and invariants
 
 def one_pair_weight(ra_s, dec_s, ra_p, dec_p, fwhm, support, kernel):
     """W of a one-cell map at (ra_p, dec_p) holding one sample: the pair's weight."""
