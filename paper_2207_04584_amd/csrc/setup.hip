@@ -728,18 +728,16 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 if (ok && hk[k] <= h_r) mask |= 1u << k;
             }
             // The four pixels' weights in turn, each pixel rotated through the
-            // first place.  The Gaussian and elliptical weights are short enough
-            // to be inlined four times (the rotations then cost nothing, and
-            // fewer registers are live than in the loop); the sinc's sine is
-            // not, so that shape keeps one inlined copy.  The elliptical
+            // first place; the loop is unrolled, so the rotations are only
+            // renamings (four inlined copies of each shape's weight hold fewer
+            // live registers than one copy in a loop did).  The elliptical
             // kernel's pair geometry rotates with the pixels (unused by the
             // other shapes, so it costs them nothing).
-            constexpr int PIX_UNROLL = KT == HG_KERNEL_GAUSS_SINC ? 1 : 4;
             double h0 = hk[0], h1 = hk[1], h2 = hk[2], h3 = hk[3];
             double s0 = sa[0], s1 = sa[1], s2 = sa[2], s3 = sa[3];
             double r0 = c.x - pra[0], r1 = c.x - pra[1], r2 = c.x - pra[2], r3 = c.x - pra[3];
             uint32_t mk = mask;
-#pragma unroll PIX_UNROLL
+#pragma unroll
             for (int k = 0; k < 4; k++) {
                 float wf = 0.f;
                 if (mk & 1u) {
