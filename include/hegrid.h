@@ -17,7 +17,13 @@
  *   - map: plate carree in coordinate degrees; pixel (i, j) is centred at
  *     RA = ra0 + (i - (nx-1)/2) dra, Dec = dec0 + (j - (ny-1)/2) ddec; or a
  *     patch of a HEALPix grid (hg_map.proj; Eq. 1 leaves the cell set G open);
- *   - a cell with no sample in its support gets NaN (count 0, W 0).
+ *   - a cell with no sample in its support gets NaN (count 0, W 0);
+ *   - values are assumed finite (Eq. 1 has no per-sample flags).  A NaN or
+ *     infinite value reaches every cell of its sample's support, and also the
+ *     other cells of the 2 x 2 cell groups that hold such a cell: the kernels
+ *     multiply a group's four cells together, with weight 0 where a cell is
+ *     outside the support, and 0 x NaN is NaN.  Cells farther away are not
+ *     affected.
  *
  * The work is split the way the paper's shared-component design splits it
  * (Sec. 4.3.1): everything that depends only on the sample positions -- sky-cell
@@ -154,7 +160,14 @@ typedef struct {
  * Algorithm 1, shared component of Sec. 4.3.1).
  *   ra_deg, dec_deg: DEVICE pointers, n FP64 values each (degrees).  Read only;
  *                    the caller keeps ownership.  Non-finite values or
- *                    |Dec| > 90 make setup fail with HG_ERR_ARG.
+ *                    |Dec| > 90 make setup fail with HG_ERR_ARG.  The
+ *                    coordinates are device pointers because every step of
+ *                    setup (binning, sort, look-up table, neighbour search)
+ *                    runs on the device; a caller holding host arrays copies
+ *                    them first, on its own stream, where the copy can overlap
+ *                    other work (the paper's CPU pre-processing, Sec. 4.1.1, is
+ *                    moved to the GPU here).  Host memory is refused
+ *                    (HG_ERR_ARG).
  *   n:               sample count, 0 <= n < 2^31.
  *   k, m:            kernel and map (host structs, copied).
  *   o:               options (may be NULL for defaults).
@@ -171,7 +184,8 @@ int hg_grid_setup(const double* ra_deg, const double* dec_deg, int64_t n, const 
  *           at values[s*ld + c]; nchan <= ld (nchan = 0 does nothing; values
  *           may be NULL when the plan has n = 0).  The caller keeps ownership.
  *   out:    DEVICE pointer, FP32 [nchan][ny][nx]; fully overwritten (NaN where
- *           a cell has no neighbour).
+ *           a cell has no neighbour).  values and out must be device memory
+ *           of the plan's device (else HG_ERR_ARG, before any launch).
  *   Asynchronous on hip_stream: the caller keeps values and out alive until
  *   the stream has passed this point.  With HG_FLAG_TIME_CHANNELS the kernel
  *   time is recorded with HIP events on the same stream.  The first call with
@@ -233,25 +247,34 @@ int hg_grid_channels_host(hg_plan* p, const void* host_values, int64_t ld, int32
 int hg_grid_channels_literal(hg_plan* p, const float* values, int64_t ld, int32_t nchan,
                              float* out, int32_t gamma, int32_t block_threads, void* hip_stream);
 
-/* Synchronise the device, free everything the plan holds.  NULL is a no-op.
-   A plan borrowed from a batch is refused with HG_ERR_STATE. */
+/* End of a plan: the shared component (look-up table, coordinates and
+   neighbour structure, Sec. 4.3.1) is released once no channel needs it.
+   Synchronises the device, then frees everything the plan holds.  NULL is a
+   no-op.  A plan borrowed from a batch is refused with HG_ERR_STATE. */
 int hg_grid_finish(hg_plan* p);
 
-/* Plan statistics (host struct).  Synchronises to read channel timings. */
+/* Plan statistics (host struct): the sizes of the shared component of
+   Sec. 4.3.1 (samples used, cells, staged slots, device bytes), the number of
+   (cell, sample) pairs in support -- the terms of Eq. 1's sums -- and
+   timings.  Synchronises to read channel timings. */
 int hg_plan_stats(hg_plan* p, hg_stats* s);
 
-/* Per-pixel neighbour counts, HOST int32 [ny*nx] (flat index j*nx + i). */
+/* Per-pixel neighbour counts |N(g)|, HOST int32 [ny*nx] (flat index j*nx + i):
+   the number of samples s_n with d(g, s_n) <= R, the terms of Eq. 1's sums
+   for cell g (the inclusive test of Algorithm 1). */
 int hg_plan_counts(const hg_plan* p, int32_t* host_counts);
 
-/* Per-pixel weight sums W (FP64 sum of the FP32 weights the kernels use),
-   HOST double [ny*nx]. */
+/* Per-pixel weight sums W_g = sum_n w(g; s_n) of Eq. 1, the normaliser of
+   every channel's map (FP64 sum of the FP32 weights the kernels use),
+   HOST double [ny*nx]; 0 where the cell has no neighbour. */
 int hg_plan_weight_sums(const hg_plan* p, double* host_W);
 
 /*
- * Neighbour lists in CSR form, HOST arrays: row_ptr[ny*nx + 1]; for the t-th
- * neighbour of pixel p (ascending original sample index) idx[t] and its FP32
- * weight w[t] (either may be NULL).  *nnz receives the total; idx and w are
- * written only when cap >= *nnz.
+ * Neighbour lists N(g) of Eq. 1 (the samples that pass Algorithm 1's
+ * inclusive test d <= R) in CSR form, HOST arrays: row_ptr[ny*nx + 1]; for the
+ * t-th neighbour of pixel p (ascending original sample index) idx[t] and its
+ * FP32 weight w[t] = w(g; s_n) (either may be NULL).  *nnz receives the total;
+ * idx and w are written only when cap >= *nnz.
  */
 int hg_plan_neighbours(const hg_plan* p, int64_t* row_ptr, int64_t* idx, float* w, int64_t cap,
                        int64_t* nnz);
@@ -327,21 +350,31 @@ typedef struct {
 int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, const hg_opts* o,
                     void* hip_stream, hg_batch** out);
 
-/* Grid every field (asynchronous on hip_stream; one graph launch). */
+/* Grid every field: Eq. 1 for every channel of every field, the work the
+   paper's two-level FIFO scheduler hands to CPU processes and GPU streams
+   (Sec. 4.2.2), as one graph launch.  Asynchronous on hip_stream; reads the
+   values and writes the outputs bound at hg_batch_create. */
 int hg_batch_run(hg_batch* b, void* hip_stream);
 
-/* Synchronise the device and free the batch and its plans.  NULL is a no-op. */
+/* End of a batch (as hg_grid_finish for each field's shared component,
+   Sec. 4.3.1): synchronise the device and free the batch and its plans.
+   NULL is a no-op. */
 int hg_batch_destroy(hg_batch* b);
 
-/* Batch statistics (host struct).  Synchronises to read run timings. */
+/* Batch statistics (host struct): fields, work items, samples, (cell,
+   sample) pairs in support (the terms of Eq. 1 over all fields), bytes and
+   timings.  Synchronises to read run timings. */
 int hg_batch_stats(hg_batch* b, hg_batch_info* s);
 
-/* Borrow field i's plan (for hg_plan_counts, hg_plan_neighbours, hg_grid_channels
-   ...); it stays owned by the batch, and hg_grid_finish on it fails. */
+/* Borrow field i's plan, the field's shared component of Sec. 4.3.1 (for
+   hg_plan_counts, hg_plan_neighbours, hg_grid_channels ...); it stays owned
+   by the batch, and hg_grid_finish on it fails. */
 int hg_batch_plan(hg_batch* b, int32_t i, hg_plan** out);
 
 /* Text of the last failure on this thread ("" if none); valid until the next
-   call on the same thread. */
+   call on the same thread.  The paper defines no error reporting; this
+   belongs to the boundary's conventions (status codes, no exceptions across
+   the interface), stated at the top of this header. */
 const char* hg_last_error(void);
 
 #ifdef __cplusplus

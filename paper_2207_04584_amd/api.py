@@ -241,8 +241,7 @@ class Plan:
         ny, nx = self.shape
         if out is None:
             out = torch.empty((nchan, ny, nx), dtype=torch.float32, device=values.device)
-        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != nchan * ny * nx:
-            raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 [C][ny][nx] tensor")
+        _out_arg(out, nchan, ny, nx, values.device)
         rc = lib().hg_grid_channels(self._handle(), ctypes.c_void_p(values.data_ptr()), ld, nchan,
                                     _dtype_code(values), ctypes.c_void_p(out.data_ptr()),
                                     _stream_ptr(stream))
@@ -297,6 +296,7 @@ class Plan:
         ny, nx = self.shape
         if out is None:
             out = torch.empty((nchan, ny, nx), dtype=torch.float32, device=values.device)
+        _out_arg(out, nchan, ny, nx, values.device)
         rc = lib().hg_grid_channels_literal(self._handle(),
                                             ctypes.c_void_p(values.data_ptr() if self.n else 0),
                                             ld, nchan, ctypes.c_void_p(out.data_ptr()), int(gamma),
@@ -377,6 +377,18 @@ def _values_arg(values, n):
         raise HegridError(HG_ERR_ARG, "values must be a cuda tensor [n][C] with unit channel "
                           "stride")
     return values, (values.stride(0) if values.shape[0] > 1 else values.shape[1])
+
+
+def _out_arg(out, nchan, ny, nx, device):
+    """out must be a contiguous float32 [C][ny][nx] tensor on the values'
+    device: the kernel writes through its address, which for host memory
+    would be a GPU memory fault rather than an error."""
+    torch = _torch()
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != nchan * ny * nx:
+        raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 [C][ny][nx] tensor")
+    if out.device.type != "cuda" or out.device != device:
+        raise HegridError(HG_ERR_ARG, f"out must be on the values' device ({device}), not "
+                          f"{out.device}")
 
 
 _side_streams = {}
@@ -484,10 +496,7 @@ class Batch:
                 if out is None:
                     out = torch.empty((nchan, m["ny"], m["nx"]), dtype=torch.float32,
                                       device=vals.device)
-                if (out.dtype != torch.float32 or not out.is_contiguous()
-                        or out.numel() != nchan * m["ny"] * m["nx"]):
-                    raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 "
-                                      "[C][ny][nx] tensor")
+                _out_arg(out, nchan, m["ny"], m["nx"], vals.device)
             self._keep += [ra, dec, vals, out]
             self.outs.append(out)
             self.fields.append({"map": dict(m), "kernel": dict(k), "n": n, "nchan": nchan})

@@ -210,6 +210,25 @@ hipError_t resolve_timing(Plan& P) {
 
 bool finite(double x) { return std::isfinite(x); }
 
+// A buffer the kernels read or write must be device memory of the device they
+// run on (hipMalloc, or managed).  Host memory is refused before anything is
+// enqueued: pageable memory would fault the GPU (no XNACK here), and
+// page-locked memory would be read over the host link.
+int require_device(const void* p, int dev, const char* what) {
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // pageable host memory is reported as an error
+        return fail(HG_ERR_ARG, std::string(what) + " is not device memory");
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(HG_ERR_ARG, std::string(what) + " is host memory; a device pointer is required");
+    if (a.type == hipMemoryTypeDevice && a.device != dev)
+        return fail(HG_ERR_ARG, std::string(what) + " is on device " + std::to_string(a.device) +
+                                    ", the plan on device " + std::to_string(dev));
+    return HG_OK;
+}
+
 int validate_map(const hg_map* m) {
     if (!m) return fail(HG_ERR_ARG, "NULL map");
     if (m->nx <= 0 || m->ny <= 0) return fail(HG_ERR_ARG, "map nx and ny must be > 0");
@@ -587,6 +606,10 @@ int hg_grid_setup(const double* ra_deg, const double* dec_deg, int64_t n, const 
         if (rc) return rc;
         rc = ensure_device();
         if (rc) return rc;
+        if (n > 0) {
+            if ((rc = require_device(ra_deg, cur_device(), "ra_deg"))) return rc;
+            if ((rc = require_device(dec_deg, cur_device(), "dec_deg"))) return rc;
+        }
         return make_plan(ra_deg, dec_deg, n, k, m, o, (hipStream_t)hip_stream, out);
     });
 }
@@ -608,6 +631,9 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
             return fail(HG_ERR_UNSUPPORTED, "a BF16-MFMA plan grids BF16 values");
         if (P.opts.precision == HG_PREC_MFMA_F16 && dtype != HG_F16)
             return fail(HG_ERR_UNSUPPORTED, "an FP16-MFMA plan grids FP16 values");
+        int rc = require_device(out, P.device, "out");
+        if (!rc && P.n > 0) rc = require_device(values, P.device, "values");
+        if (rc) return rc;
         hipError_t e = hipSetDevice(P.device);
         if (e != hipSuccess) return fail_hip(e, "grid_channels");
         hipStream_t s = (hipStream_t)hip_stream;
@@ -654,6 +680,9 @@ int hg_grid_channels_literal(hg_plan* h, const float* values, int64_t ld, int32_
         if (nchan == 0) return HG_OK;
         if (!out || (!values && P.n > 0)) return fail(HG_ERR_ARG, "values and out must not be NULL");
         if (ld < nchan) return fail(HG_ERR_ARG, "ld must be >= nchan");
+        int rc = require_device(out, P.device, "out");
+        if (!rc && P.n > 0) rc = require_device(values, P.device, "values");
+        if (rc) return rc;
         hipError_t e = hipSetDevice(P.device);
         if (e == hipSuccess)
             e = launch_literal(P, values, ld, nchan, out, gamma, block_threads,
@@ -863,6 +892,17 @@ int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, cons
         }
         int rc = ensure_device();
         if (rc) return rc;
+        for (int32_t i = 0; i < nfields && !rc; i++) {
+            const hg_field& f = fields[i];
+            const int dev = cur_device();
+            if (f.n > 0) {
+                rc = require_device(f.ra_deg, dev, "ra_deg");
+                if (!rc) rc = require_device(f.dec_deg, dev, "dec_deg");
+            }
+            if (!rc && f.nchan > 0) rc = require_device(f.out, dev, "out");
+            if (!rc && f.nchan > 0 && f.n > 0) rc = require_device(f.values, dev, "values");
+            if (rc) return fail(rc, "field " + std::to_string(i) + ": " + g_err);
+        }
         auto t0 = std::chrono::steady_clock::now();
         hg_batch* b = new hg_batch();
         b->device = cur_device();
@@ -1024,6 +1064,8 @@ int hg_ang2pix_ring(int32_t nside, const double* ra_deg, const double* dec_deg, 
         if (n == 0) return HG_OK;
         int rc = ensure_device();
         if (rc) return rc;
+        for (const void* q : {(const void*)ra_deg, (const void*)dec_deg, (const void*)pix})
+            if ((rc = require_device(q, cur_device(), "ra_deg, dec_deg and pix"))) return rc;
         hipError_t e = launch_ang2pix(nside, ra_deg, dec_deg, n, pix, (hipStream_t)hip_stream);
         if (e != hipSuccess) return fail_hip(e, "ang2pix_ring");
         return HG_OK;

@@ -304,3 +304,18 @@ def test_valid_batch_without_device_reports_device_error():
     rc, h = _batch([_field(), _field()])
     assert rc == api.HG_ERR_DEVICE
     assert not h.value
+
+
+def test_binding_refuses_a_host_output_tensor():
+    """The kernels write through `out`'s address, so a host tensor must be
+    refused by the binding (HG_ERR_ARG) before any library call; so must one
+    on another device or of the wrong shape."""
+    import torch
+    dev = torch.device("cuda", 0)  # a device object needs no GPU
+    with pytest.raises(api.HegridError) as e:
+        api._out_arg(torch.empty(3, 2, 2, dtype=torch.float32), 3, 2, 2, dev)
+    assert e.value.status == api.HG_ERR_ARG and "device" in str(e.value)
+    with pytest.raises(api.HegridError):
+        api._out_arg(torch.empty(3, 2, 2, dtype=torch.float64), 3, 2, 2, dev)
+    with pytest.raises(api.HegridError):
+        api._out_arg(torch.empty(2, 2, 2, dtype=torch.float32), 3, 2, 2, dev)

@@ -172,3 +172,57 @@ def test_batch_workload_against_reference(precision, tol):
             worst = max(worst, e_max)
             assert e_max <= tol, f"field {i}: e_max {e_max:g} > {tol:g}"
     print(f"  worst e_max {worst:.3g}", flush=True)
+
+
+def test_batch_workload_full_size_against_reference():
+    """The 64-field batching workload at full size (sample counts 1e4..2e6,
+    maps 32..512, 256/1024/4096 FP16 channels, FWHM U(2, 5) arcmin; about
+    3e10 sample x channels) in the FP16 MFMA form, one graph-held launch.
+    Reference: two channels of every field on 80 sampled pixels and the map
+    corners (counts bit-exact there), plus the smallest field's every pixel.  The
+    densest field (about 3e5 neighbours per pixel) does not fit two staged
+    64-slot chunks in LDS, so its plan must come from the shorter-chunk
+    fallback of setup; that is asserted."""
+    fs = synth.batch_fields(64)
+    fields = []
+    for f in fs:
+        fields.append({"ra": f["ra"], "dec": f["dec"], "map": f["map"], "kernel": f["kernel"],
+                       "values": synth.sky_values(f, f["nchan"], device=DEV, dtype="f16")})
+    torch.cuda.synchronize()
+    nc = sum(len(f["ra"]) * f["nchan"] for f in fs)
+    print(f"\n  64 fields, sum N*C = {nc:.3e}", flush=True)
+    rng = np.random.default_rng(44)
+    small = min(range(64), key=lambda i: len(fs[i]["ra"]) * fs[i]["map"]["nx"] ** 2)
+    worst = 0.0
+    with api.Batch(fields, precision=2, time_runs=True) as b:
+        outs = b.run()
+        torch.cuda.synchronize()
+        st = b.stats()
+        print(f"  items {st['n_items']} nnz {st['nnz']} run {st['last_run_ms']:.1f} ms "
+              f"setup {st['setup_ms']:.1f} ms", flush=True)
+        dens = [b.plan(i).stats() for i in range(64)]
+        densest = max(range(64), key=lambda i: dens[i]["nnz"] / (fs[i]["map"]["nx"] ** 2))
+        print(f"  densest field {densest}: {dens[densest]['nnz'] / fs[densest]['map']['nx'] ** 2:.0f}"
+              f" neighbours per pixel, chunk {dens[densest]['chunk']}", flush=True)
+        assert dens[densest]["chunk"] < 64, "the densest field should need shorter chunks"
+        for i, f in enumerate(fs):
+            C = f["nchan"]
+            P = f["map"]["nx"] * f["map"]["ny"]
+            chans = np.array([int(rng.integers(C)), C - 1])
+            nx = f["map"]["nx"]
+            pix = None if i == small else np.unique(np.concatenate(
+                [rng.choice(P, 80, replace=False), [0, nx - 1, P - nx, P - 1]]))
+            hv, code = to_host_values(fields[i]["values"][:, chans].contiguous())
+            Vr, cr, _, margin = oracle.grid(f["ra"], f["dec"], hv, code, f["map"],
+                                            f["kernel"]["fwhm_deg"], f["kernel"]["support_deg"],
+                                            pix=pix)
+            assert margin > 1e-12, f"field {i}: closest call {margin:g}"
+            cnt = b.plan(i).counts()
+            sel = np.arange(P) if pix is None else pix
+            np.testing.assert_array_equal(cnt[sel], cr, err_msg=f"field {i}")
+            V = outs[i].reshape(C, -1)[torch.from_numpy(chans).to(DEV)].cpu().numpy()[:, sel]
+            np.testing.assert_array_equal(np.isnan(V), np.isnan(Vr), err_msg=f"field {i}")
+            e_max, _ = norm_err(V, Vr, cr > 0)
+            worst = max(worst, e_max)
+            assert e_max <= 2e-3, f"field {i}: e_max {e_max:g}"
+    print(f"  worst e_max {worst:.3g} over 64 fields", flush=True)

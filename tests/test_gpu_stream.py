@@ -129,3 +129,83 @@ def test_streamed_cube_against_reference():
     e_max, e_rms = norm_err(V, Vr, cr > 0)
     print(f"  e_max={e_max:.3g} e_rms={e_rms:.3g}", flush=True)
     assert e_max <= 2e-3
+
+
+def cube_slab(f, C, lo, hi, dev_slab, block=4096):
+    """Channels [lo, hi) of the cube as one contiguous BF16 [n][hi - lo]
+    device array, generated block by block (each block's FP32 intermediate
+    is 16 GB at 1e6 samples)."""
+    for b0 in range(lo, hi, block):
+        b1 = min(hi, b0 + block)
+        v = synth.sky_values(f, C, device=DEV, dtype="bf16", chan_lo=b0, chan_hi=b1)
+        dev_slab[:, b0 - lo:b1 - lo].copy_(v)
+        del v
+    return dev_slab
+
+
+def test_cfg5_full_size_streamed():
+    """The large-cube workload at its real size: 1e6 samples of 19 interleaved
+    drift-scan beams, a 600 x 600 map, 65,536 BF16 channels streamed from
+    page-locked host memory in 16 blocks of 4096, the copies in and out
+    overlapped with the kernel (hg_grid_channels_host, BF16 MFMA form).  The
+    host cannot hold the whole cube (131 GB of values and 94 GB of maps), so
+    it goes through in slabs of several blocks, each one call.  Reference:
+    16 channels of blocks 0, 7 and 15 on 400 sampled pixels and the corners."""
+    import psutil
+    avail = psutil.virtual_memory().available
+    # torch rounds page-locked allocations up to a power of two: slabs of
+    # 8192 channels take 2 x 17 GB, of 16384 2 x 34 GB
+    if avail < 60e9:
+        pytest.skip(f"needs about 60 GB of free host memory, {avail / 1e9:.0f} GB available")
+    f = synth.config("cfg5")
+    C, block = 65536, 4096
+    slab = 16384 if avail > 150e9 else 8192
+    n = f["ra"].shape[0]
+    m = f["map"]
+    P = m["nx"] * m["ny"]
+    print(f"\n  {n} samples, {C} channels, slabs of {slab} ({avail / 1e9:.0f} GB host free)",
+          flush=True)
+    rng = np.random.default_rng(55)
+    offs = np.sort(rng.choice(block, 16, replace=False))
+    check = {b: b * block + offs for b in (0, 7, 15)}
+    pix = np.unique(np.concatenate([rng.choice(P, 400, replace=False),
+                                    [0, m["nx"] - 1, P - m["nx"], P - 1]]))
+    vals_h = torch.empty((n, slab), dtype=torch.bfloat16, pin_memory=True)
+    out_h = torch.empty((slab, m["ny"], m["nx"]), dtype=torch.float32, pin_memory=True)
+    dev_slab = torch.empty((n, slab), dtype=torch.bfloat16, device=DEV)
+    got, ref_vals, infos = {}, {}, []
+    with api.Plan(f["ra"], f["dec"], m, f["kernel"], precision=api.HG_PREC_MFMA_BF16) as p:
+        cnt = p.counts()
+        for s0 in range(0, C, slab):
+            cube_slab(f, C, s0, s0 + slab, dev_slab)
+            vals_h.copy_(dev_slab)
+            torch.cuda.synchronize()
+            _, info = p.grid_host(vals_h, out=out_h, block=block)
+            infos.append(info)
+            print(f"  slab {s0 // slab}: {info['blocks']} blocks, wall {info['wall_ms']:.0f} ms, "
+                  f"h2d {info['h2d_ms']:.0f} ms, kernels {info['kernel_ms']:.0f} ms, "
+                  f"d2h {info['d2h_ms']:.0f} ms", flush=True)
+            assert info["pinned"] == 1 and info["blocks"] == slab // block
+            for b, ch in check.items():
+                if s0 <= ch[0] < s0 + slab:
+                    loc = torch.from_numpy(ch - s0)
+                    got[b] = out_h.reshape(slab, -1)[loc][:, pix].numpy().copy()
+                    ref_vals[b] = to_host_values(vals_h[:, loc].contiguous())
+    del vals_h, out_h, dev_slab
+    torch.cuda.synchronize()
+    if hasattr(torch._C, "_host_emptyCache"):
+        torch._C._host_emptyCache()  # return the page-locked slabs to the system
+    assert sum(i["blocks"] for i in infos) == C // block
+    worst = 0.0
+    for b, ch in check.items():
+        hv, code = ref_vals[b]
+        Vr, cr, _, margin = oracle.grid(f["ra"], f["dec"], hv, code, m, f["kernel"]["fwhm_deg"],
+                                        f["kernel"]["support_deg"], pix=pix)
+        assert margin > 1e-12
+        np.testing.assert_array_equal(cnt[pix], cr)
+        np.testing.assert_array_equal(np.isnan(got[b]), np.isnan(Vr))
+        e_max, e_rms = norm_err(got[b], Vr, cr > 0)
+        worst = max(worst, e_max)
+        print(f"  block {b}: e_max={e_max:.3g} e_rms={e_rms:.3g}", flush=True)
+        assert e_max <= 2e-3
+    print(f"  worst e_max {worst:.3g}", flush=True)

@@ -323,6 +323,34 @@ def test_elliptical_axes_on_the_equator():
         assert w_n == pytest.approx(math.exp(-d * d / (2 * s_north ** 2)), rel=1e-12)
 
 
+def test_elliptical_position_angle_handedness():
+    """The position angle turns from north through east.  With the major
+    axis at PA 45 deg, a sample to the north-east of a cell on the equator
+    lies on the major axis and one to the north-west on the minor axis, so
+    their weights are the two 1-D Gaussians; a bearing measured north
+    through west would swap them.  The sample at (RA a, Dec e) seen from
+    (0, 0) has east and north components cos(e) sin(a) and sin(e), so
+    tan(e) = sin(a) puts it at bearing exactly 45 deg (and -a at -45 deg);
+    its distance is atan2 of the cross and dot products of the two unit
+    vectors, |(0, -sin e, cos e sin a)| and cos(e) cos(a)."""
+    fwhm_maj, fwhm_min, R = 4.0 / 60, 1.5 / 60, 0.2
+    s_maj, s_min = (f * math.pi / 180 / math.sqrt(8 * math.log(2)) for f in (fwhm_maj, fwhm_min))
+    e = math.radians(1.3 / 60)
+    a = math.asin(math.tan(e))
+    d = math.atan2(math.hypot(math.sin(e), math.cos(e) * math.sin(a)), math.cos(e) * math.cos(a))
+    k = {"type": 2, "p1": fwhm_min, "p2": 45.0}
+    w_ne = one_pair_weight(math.degrees(a), math.degrees(e), 0.0, 0.0, fwhm_maj, R, k)
+    w_nw = one_pair_weight(-math.degrees(a), math.degrees(e), 0.0, 0.0, fwhm_maj, R, k)
+    assert w_ne == pytest.approx(math.exp(-d * d / (2 * s_maj ** 2)), rel=1e-12)
+    assert w_nw == pytest.approx(math.exp(-d * d / (2 * s_min ** 2)), rel=1e-12)
+    # the same pair at PA -45 deg (major axis north-west) swaps the two
+    k2 = dict(k, p2=-45.0)
+    assert one_pair_weight(math.degrees(a), math.degrees(e), 0.0, 0.0, fwhm_maj, R,
+                           k2) == pytest.approx(w_nw, rel=1e-9)
+    assert one_pair_weight(-math.degrees(a), math.degrees(e), 0.0, 0.0, fwhm_maj, R,
+                           k2) == pytest.approx(w_ne, rel=1e-9)
+
+
 def test_elliptical_round_beam_is_the_gaussian_and_half_turn_symmetric():
     ra, dec, vals, m, k = _field(31, n=800, dec0=47.0)
     g = oracle.neighbours(ra, dec, m, k["fwhm_deg"], k["support_deg"])
