@@ -63,40 +63,81 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(f, vals_host, n_pix, seed=7, gpu_out=None):
-    """The reference gridder as it stands, single-threaded, on a random subset
-    of the map's pixels with all channels; scaled to the full map.  With
-    gpu_out (the timed path's last map, host [C][P]) the same pixels also give
-    the path's error against the reference: per channel max |V - V_ref| over
-    max |V_ref|, and the same with RMS norms, worst channel."""
+def _host_facts():
+    """CPU model and logical core count of the host the bench runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline(f, vals_host, n_pix, seed=7, gpu_out=None, code="f32", threads=None):
+    """The reference gridder as it stands, on a random subset of the map's
+    pixels with all channels, split over `threads` host threads (each a
+    separate single-threaded call on its own pixels; the calls run in C with
+    the interpreter lock released); scaled to the full map.  value is the
+    all-thread rate, value_1core the mean rate of one thread while all run.
+    With gpu_out (the timed path's last map, host [C][P]) the same pixels
+    also give the path's error against the reference: per channel max
+    |V - V_ref| over max |V_ref|, and the same with RMS norms, worst channel."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import oracle
     m = f["map"]
     P = m["nx"] * m["ny"]
+    model, ncpu = _host_facts()
+    threads = max(1, min(threads or ncpu, n_pix))
     pix = np.sort(np.random.default_rng(seed).choice(P, n_pix, replace=False))
+    parts = np.array_split(pix, threads)
+
+    def one(part):
+        t0 = time.perf_counter()
+        r = oracle.grid(f["ra"], f["dec"], vals_host, code, m, f["kernel"]["fwhm_deg"],
+                        f["kernel"]["support_deg"], pix=part, kernel=f["kernel"])
+        return r, time.perf_counter() - t0
+
     t0 = time.perf_counter()
-    Vr, cnt, _, _ = oracle.grid(f["ra"], f["dec"], vals_host, "f32", m, f["kernel"]["fwhm_deg"],
-                                f["kernel"]["support_deg"], pix=pix, kernel=f["kernel"])
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        done = list(ex.map(one, parts))
     dt = time.perf_counter() - t0
-    full_s = dt * P / n_pix
+    Vr = np.concatenate([d[0][0] for d in done], axis=1)
+    cnt = np.concatenate([d[0][1] for d in done])
+    busy = sum(d[1] for d in done)
     n, C = vals_host.shape
-    res = {"value": n * C / full_s / 1e9, "unit": "G sample*channel updates/s", "cores": 1,
-           "kind": "oracle",
-           "sample": f"{n_pix} of {P} pixels x all {C} channels ({dt:.1f} s), scaled by "
-                     f"{P / n_pix:.1f} to the full map"}
+    res = {"value": n * C / (dt * P / n_pix) / 1e9, "unit": "G sample*channel updates/s",
+           "cores": threads, "kind": "oracle",
+           "sample": f"{n_pix} of {P} pixels x all {C} channels on {threads} threads "
+                     f"({dt:.1f} s wall, {busy:.1f} s of thread time), scaled by "
+                     f"{P / n_pix:.1f} to the full map",
+           "value_1core": n * C / (busy * P / n_pix) / 1e9,
+           "cpu_model": model, "nproc": ncpu}
     if gpu_out is not None:
-        ok = cnt > 0
-        V = gpu_out[:, pix][:, ok].astype(np.float64)
-        R = Vr[:, ok]
-        d = np.abs(V - R)
-        e_max = float((d.max(1) / np.maximum(np.abs(R).max(1), 1e-300)).max())
-        e_rms = float((np.sqrt((d ** 2).mean(1)) /
-                       np.maximum(np.sqrt((R ** 2).mean(1)), 1e-300)).max())
-        nan_match = bool((np.isnan(gpu_out[:, pix]) == np.isnan(Vr)).all())
-        res["parity"] = {"e_max": e_max, "e_rms": e_rms, "nan_match": nan_match,
-                         "pixels": int(ok.sum())}
+        res["parity"] = parity(gpu_out[:, pix], Vr, cnt)
     return res
+
+
+def parity(V, Vr, cnt):
+    """Per channel max |V - V_ref| / max |V_ref| and the RMS analogue over
+    cells with neighbours (worst channel), and whether the empty cells
+    match."""
+    import numpy as np
+    ok = cnt > 0
+    Vk = V[:, ok].astype(np.float64)
+    R = Vr[:, ok]
+    d = np.abs(Vk - R)
+    e_max = float((d.max(1) / np.maximum(np.abs(R).max(1), 1e-300)).max()) if d.size else 0.0
+    e_rms = float((np.sqrt((d ** 2).mean(1)) /
+                   np.maximum(np.sqrt((R ** 2).mean(1)), 1e-300)).max()) if d.size else 0.0
+    return {"e_max": e_max, "e_rms": e_rms, "nan_match": bool((np.isnan(V) == np.isnan(Vr)).all()),
+            "pixels": int(ok.sum())}
 
 
 def measured_traffic(workload):
@@ -171,6 +212,63 @@ def cpu_baseline_batch(fields, vals_dev, nnz_per_field, n_pix, seed=7):
                       f"channel) scaled to the batch's sum of nnz x C"}
 
 
+def time_steps(step, args, label):
+    """W untimed steps, then K timed steps bracketed by synchronisations;
+    returns ms per step."""
+    import torch
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"{label}: {args.steps} timed steps, {ms:.3f} ms/step")
+    return ms
+
+
+def drift_leg(args, f, ra, dec, vals, precision, label):
+    """Setup + channels per step on the drift workload in one form, in the
+    autotuned shape; returns (record, plan stats, last map)."""
+    import numpy as np
+    import torch
+
+    from paper_2207_04584_amd import api, tune
+    m, k = f["map"], f["kernel"]
+    C = vals.shape[1]
+    out = torch.empty((C, m["ny"], m["nx"]), dtype=torch.float32, device=vals.device)
+    if args.no_tune:
+        best = {"chunk": 0, "waves": 0, "chan_block": 0, "cached": False, "table": {}}
+    else:
+        t0 = time.perf_counter()
+        best = tune.tune_plan(ra, dec, m, k, vals, precision=precision, use_cache=False)
+        log(f"{label}: tuned in {time.perf_counter() - t0:.1f} s -> chunk {best['chunk']}, "
+            f"{best['waves']} waves x {best['chan_block']} channels ({best['ms']:.3f} ms)")
+    ch_ms, setup_ms, st = [], [], {}
+
+    def step():
+        nonlocal st
+        plan = api.Plan(ra, dec, m, k, precision=precision, chunk=best["chunk"],
+                        waves=best["waves"], chan_block=best["chan_block"], time_channels=True)
+        plan.grid(vals, out)
+        st = plan.stats()
+        plan.close()
+        ch_ms.append(st["last_channels_ms"])
+        setup_ms.append(st["setup_ms"])
+
+    for _ in range(args.warmup):
+        step()
+    ch_ms.clear()
+    setup_ms.clear()
+    ms_step = time_steps(step, argparse.Namespace(warmup=0, steps=args.steps), label)
+    rec = {"ms_per_step": ms_step, "channels_ms": float(np.mean(ch_ms)),
+           "setup_ms": float(np.mean(setup_ms)),
+           "shape": {"chunk": st["chunk"], "waves": st["waves"], "chan_block": st["chan_block"],
+                     "tuned": not args.no_tune, "candidates_timed": len(best.get("table", {}))}}
+    return rec, st, out
+
+
 def run_drift(args):
     import numpy as np
     import torch
@@ -200,38 +298,14 @@ def run_drift(args):
     ra = torch.from_numpy(f["ra"]).to(dev)
     dec = torch.from_numpy(f["dec"]).to(dev)
     vals = synth.sky_values(f, C, device=dev)
-    out = torch.empty((C, m["ny"], m["nx"]), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
-    ch_ms, setup_ms, nnz, entries = [], [], 0, 0
-
-    def step():
-        nonlocal nnz, entries
-        plan = api.Plan(ra, dec, m, k, time_channels=True)
-        plan.grid(vals, out)
-        st = plan.stats()
-        plan.close()
-        ch_ms.append(st["last_channels_ms"])
-        setup_ms.append(st["setup_ms"])
-        nnz, entries = st["nnz"], st["n_entries"]
-
-    for i in range(args.warmup):
-        step()
-        log(f"warmup {i + 1}/{args.warmup}: channels {ch_ms[-1]:.3f} ms, setup {setup_ms[-1]:.2f} ms")
-    ch_ms.clear()
-    setup_ms.clear()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    rec, st, out = drift_leg(args, f, ra, dec, vals, api.HG_PREC_FP32, "plain FP32 form")
+    ms_step, ch_avg = rec["ms_per_step"], rec["channels_ms"]
+    nnz = st["nnz"]
     value = n * C / (ms_step * 1e-3) / 1e9
-    ch_avg = float(np.mean(ch_ms))
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; channel kernel {ch_avg:.3f} ms; "
-        f"setup {np.mean(setup_ms):.2f} ms")
-
+    log(f"plain FP32: {ms_step:.3f} ms/step; channel kernel {ch_avg:.3f} ms; setup "
+        f"{rec['setup_ms']:.2f} ms")
     roof = roofline(2.0 * nnz * C, 4.0 * n * C + 4.0 * P * C, ch_avg, PEAK_FP32_MFMA_TFLOPS,
                     "k_channels (FP32 form, FP32 values)")
     roof["traffic"] = None if variant else measured_traffic("drift")
@@ -246,9 +320,10 @@ def run_drift(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "n_samples": n, "channels": C, "map": [m["ny"], m["nx"]], "nnz": nnz,
-                   "entry_units": entries, "form": "fp32"},
-        "channels_ms": ch_avg, "setup_ms": float(np.mean(setup_ms)),
+        "config": {"workload": workload, "n_samples": n, "channels": C, "map": [m["ny"], m["nx"]],
+                   "nnz": nnz, "entry_units": st["n_entries"], "form": "fp32",
+                   "shape": rec["shape"]},
+        "channels_ms": ch_avg, "setup_ms": rec["setup_ms"],
         "channels_only_value": n * C / (ch_avg * 1e-3) / 1e9,
         "roofline": roof,
     }
@@ -259,6 +334,36 @@ def run_drift(args):
                                            gpu_out=out.reshape(C, -1).cpu().numpy())
         log(f"cpu baseline: {res['cpu_baseline']['sample']}; parity "
             f"{res['cpu_baseline'].get('parity')}")
+        del vals_host
+    if not args.no_mfma_leg and not variant:
+        # the precision form on the same workload: the same cube stored as
+        # BF16, BF16 weights x values on MFMA with FP32 accumulation
+        vb = vals.to(torch.bfloat16)
+        del out
+        rb, sb, outb = drift_leg(args, f, ra, dec, vb, api.HG_PREC_MFMA_BF16, "BF16-MFMA form")
+        rb["value"] = n * C / (rb["ms_per_step"] * 1e-3) / 1e9
+        rb["channels_only_value"] = n * C / (rb["channels_ms"] * 1e-3) / 1e9
+        rb["roofline"] = roofline(2.0 * sb["nnz"] * C, 2.0 * n * C + 4.0 * P * C,
+                                  rb["channels_ms"], PEAK_F16_MFMA_TFLOPS,
+                                  "k_channels (BF16 MFMA form)")
+        rb["speedup_vs_plain"] = {"step": ms_step / rb["ms_per_step"],
+                                  "channels": ch_avg / rb["channels_ms"]}
+        if not args.no_cpu_baseline:
+            hv, code = host_values(vb)
+            cb = cpu_baseline(f, hv, args.cpu_pixels // 2, seed=8,
+                              gpu_out=outb.reshape(C, -1).cpu().numpy(), code=code)
+            rb["parity"] = cb["parity"]
+            rb["parity"]["reference"] = "FP64 reference gridder on the stored BF16 values"
+            del hv
+        log(f"BF16-MFMA: {rb['ms_per_step']:.3f} ms/step; channel kernel "
+            f"{rb['channels_ms']:.3f} ms; parity {rb.get('parity')}")
+        res["mfma_form"] = dict({"dtype": "bf16", "workload": "the same drift-scan cube stored as "
+                                 "BF16; step = setup + channels"}, **rb)
+        del vb, outb
+    if not args.no_batch_leg and not variant:
+        del vals
+        torch.cuda.empty_cache()
+        res["batched_form"] = batch_legs(args)
     return res
 
 
@@ -326,21 +431,26 @@ def run_fifo(args):
     }
 
 
-def run_batch(args):
+def batch_leg(args, fs, fields, vals_dev, nc, pc, precision, steps, warmup):
+    """One form of the batched workload: hg_batch_create (every field's
+    setup) + one batched launch + destroy per step, in the autotuned shape."""
     import numpy as np
-    import torch
 
-    from paper_2207_04584_amd import api
-
-    fs, fields, vals_dev, nc, pc = batch_inputs(args)
-    mfma = args.precision == "mfma"
-
+    from paper_2207_04584_amd import api, tune
+    mfma = precision != api.HG_PREC_FP32
+    if args.no_tune:
+        best = {"waves": 0, "chan_block": 0, "table": {}}
+    else:
+        t0 = time.perf_counter()
+        best = tune.tune_batch(fields, precision=precision, use_cache=False)
+        log(f"batch {'fp16-mfma' if mfma else 'fp32'}: tuned in {time.perf_counter() - t0:.1f} s "
+            f"-> {best['waves']} waves x {best['chan_block']} channels ({best['ms']:.1f} ms)")
     run_ms, setup_ms, info, nnz_f = [], [], {}, []
-    prec = api.HG_PREC_MFMA_F16 if mfma else api.HG_PREC_FP32
 
     def step():
         nonlocal info
-        b = api.Batch(fields, precision=prec, time_runs=True)
+        b = api.Batch(fields, precision=precision, time_runs=True, waves=best["waves"],
+                      chan_block=best["chan_block"])
         b.run()
         info = b.stats()
         if not nnz_f:  # per-field nnz, for the flop count and the reference's scaling
@@ -349,43 +459,100 @@ def run_batch(args):
         run_ms.append(info["last_run_ms"])
         setup_ms.append(info["setup_ms"])
 
-    for i in range(args.warmup):
+    for _ in range(warmup):
         step()
-        log(f"warmup {i + 1}/{args.warmup}: batch run {run_ms[-1]:.3f} ms, "
-            f"setup {setup_ms[-1]:.1f} ms")
     run_ms.clear()
     setup_ms.clear()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step = time_steps(step, argparse.Namespace(warmup=0, steps=steps),
+                         "batch " + ("fp16-mfma" if mfma else "fp32"))
     run_avg = float(np.mean(run_ms))
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; batched launch {run_avg:.3f} ms; "
-        f"setup {np.mean(setup_ms):.1f} ms; items {info['n_items']}")
-    nnz = info["nnz"]
     flops = 2.0 * sum(nnz_f[i] * fs[i]["nchan"] for i in range(len(fs)))
     bytes_alg = 2.0 * nc + 4.0 * pc
-    kname = "k_channels_batch (FP16 MFMA form)" if mfma else "k_channels_batch (FP32 form, FP16 values)"
-    roof = roofline(flops, bytes_alg, run_avg,
-                    PEAK_F16_MFMA_TFLOPS if mfma else PEAK_FP32_MFMA_TFLOPS, kname)
+    kname = ("k_channels_batch (FP16 MFMA form)" if mfma else
+             "k_channels_batch (FP32 form, FP16 values)")
+    rec = {"form": "fp16-mfma" if mfma else "fp32", "ms_per_step": ms_step,
+           "value": nc / (ms_step * 1e-3) / 1e9, "channels_ms": run_avg,
+           "setup_ms": float(np.mean(setup_ms)), "channels_only_value": nc / (run_avg * 1e-3) / 1e9,
+           "nnz": info["nnz"], "items": info["n_items"],
+           "shape": {"waves": best["waves"] or 16, "chan_block": best["chan_block"] or 256,
+                     "tuned": not args.no_tune, "candidates_timed": len(best.get("table", {}))},
+           "roofline": roofline(flops, bytes_alg, run_avg,
+                                PEAK_F16_MFMA_TFLOPS if mfma else PEAK_FP32_MFMA_TFLOPS, kname)}
+    return rec, nnz_f
+
+
+def batch_legs(args):
+    """The 64-field batching workload in the FP16-MFMA form and in the FP32
+    form on the same FP16 values (a few steps each), with the error of one
+    field's sampled pixels against the reference for each form."""
+    import numpy as np
+    import torch
+
+    from paper_2207_04584_amd import api
+    fs, fields, vals_dev, nc, pc = batch_inputs(args)
+    steps, warmup = min(args.steps, 5), min(args.warmup, 2)
+    out = {}
+    for prec in (api.HG_PREC_MFMA_F16, api.HG_PREC_FP32):
+        rec, nnz_f = batch_leg(args, fs, fields, vals_dev, nc, pc, prec, steps, warmup)
+        if not args.no_cpu_baseline:
+            # one mid-cost field, sampled pixels and channels, against the reference
+            order = sorted(range(len(fs)), key=lambda i: nnz_f[i] * fs[i]["nchan"])
+            i = order[len(order) // 2]
+            with api.Batch(fields[i:i + 1], precision=prec) as b:
+                o = b.run()[0]
+                torch.cuda.synchronize()
+                cnt_all = b.plan(0).counts()
+            fi = fs[i]
+            P = fi["map"]["nx"] * fi["map"]["ny"]
+            rng = np.random.default_rng(9)
+            pix = np.sort(rng.choice(P, min(600, P), replace=False))
+            chans = np.sort(rng.choice(fi["nchan"], min(16, fi["nchan"]), replace=False))
+            hv, code = host_values(vals_dev[i][:, torch.from_numpy(chans).to(vals_dev[i].device)]
+                                   .contiguous())
+            import oracle
+            Vr, cr, _, _ = oracle.grid(fi["ra"], fi["dec"], hv, code, fi["map"],
+                                       fi["kernel"]["fwhm_deg"], fi["kernel"]["support_deg"],
+                                       pix=pix)
+            V = o.reshape(fi["nchan"], -1)[torch.from_numpy(chans).to(o.device)].cpu().numpy()
+            rec["parity"] = dict(parity(V[:, pix], Vr, cr), field=i,
+                                 counts_match=bool(np.array_equal(cnt_all[pix], cr)))
+        log(f"batch {rec['form']}: {rec['ms_per_step']:.1f} ms/step, launch {rec['channels_ms']:.1f} "
+            f"ms; parity {rec.get('parity')}")
+        out[rec["form"]] = rec
+    out["speedup_mfma_vs_fp32"] = {
+        "step": out["fp32"]["ms_per_step"] / out["fp16-mfma"]["ms_per_step"],
+        "launch": out["fp32"]["channels_ms"] / out["fp16-mfma"]["channels_ms"]}
+    out["workload"] = (f"{len(fs)} fields, samples log-uniform 1e4..2e6, maps 32..512 at "
+                       "1 arcmin, 256/1024/4096 FP16 channels, FWHM U(2,5) arcmin; step = batch "
+                       "setup + one batched launch")
+    out["sum_NC"] = nc
+    return out
+
+
+def run_batch(args):
+    from paper_2207_04584_amd import api
+
+    fs, fields, vals_dev, nc, pc = batch_inputs(args)
+    mfma = args.precision == "mfma"
+    prec = api.HG_PREC_MFMA_F16 if mfma else api.HG_PREC_FP32
+    rec, nnz_f = batch_leg(args, fs, fields, vals_dev, nc, pc, prec, args.steps, args.warmup)
+    log(f"timed {args.steps} steps: {rec['ms_per_step']:.3f} ms/step; batched launch "
+        f"{rec['channels_ms']:.3f} ms; setup {rec['setup_ms']:.1f} ms; items {rec['items']}")
     res = {
         "metric": "G sample*channel updates/s (" + ("FP16-MFMA batched form)" if mfma else
                                                     "plain FP32 form, batched)"),
-        "value": nc / (ms_step * 1e-3) / 1e9, "unit": "G sample*channel updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "value": rec["value"], "unit": "G sample*channel updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f16" if mfma else "f32", "data": "synthetic",
         "config": {"workload": f"{len(fs)} fields, samples log-uniform 1e4..2e6, maps 32..512 "
                                "at 1 arcmin, 256/1024/4096 FP16 channels, FWHM U(2,5) arcmin; "
                                "step = batch setup + one batched launch",
-                   "fields": len(fs), "scale": args.scale, "sum_NC": nc, "nnz": nnz,
-                   "items": info["n_items"], "form": args.precision},
-        "channels_ms": run_avg, "setup_ms": float(np.mean(setup_ms)),
-        "channels_only_value": nc / (run_avg * 1e-3) / 1e9,
-        "roofline": roof,
+                   "fields": len(fs), "scale": args.scale, "sum_NC": nc, "nnz": rec["nnz"],
+                   "items": rec["items"], "form": args.precision, "shape": rec["shape"]},
+        "channels_ms": rec["channels_ms"], "setup_ms": rec["setup_ms"],
+        "channels_only_value": rec["channels_only_value"],
+        "roofline": rec["roofline"],
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_batch(fs, vals_dev, nnz_f, 2 * args.cpu_pixels)
@@ -563,13 +730,99 @@ def run_paper(args):
     return res
 
 
+def run_cube(args):
+    """The large-cube workload at its real size: 1e6 samples of 19 interleaved
+    drift-scan beams, 600 x 600 map, 65,536 BF16 channels in page-locked host
+    memory, streamed through the device in blocks of 4096 channels with the
+    copies in and out overlapped with the BF16-MFMA kernel
+    (hg_grid_channels_host).  The host holds the cube a slab of several blocks
+    at a time (the whole cube is 131 GB of values and 94 GB of maps); each
+    slab is generated on the GPU and copied to page-locked memory before its
+    call, outside the timing.  One step = setup + every slab's streamed call."""
+    import numpy as np
+    import torch
+
+    from paper_2207_04584_amd import api, synth
+    dev = torch.device("cuda:0")
+    f = synth.config("cfg5")
+    C, block, slab = 65536, 4096, args.cube_slab
+    nslabs = args.cube_slabs or C // slab
+    n = f["ra"].shape[0]
+    m, k = f["map"], f["kernel"]
+    P = m["nx"] * m["ny"]
+    log(f"cube: {n} samples, {nslabs} slabs of {slab} channels (blocks of {block}), "
+        f"{m['nx']}x{m['ny']} map, {torch.cuda.get_device_name(0)}")
+    ra = torch.from_numpy(f["ra"]).to(dev)
+    dec = torch.from_numpy(f["dec"]).to(dev)
+    vals_h = torch.empty((n, slab), dtype=torch.bfloat16, pin_memory=True)
+    out_h = torch.empty((slab, m["ny"], m["nx"]), dtype=torch.float32, pin_memory=True)
+    dev_slab = torch.empty((n, slab), dtype=torch.bfloat16, device=dev)
+
+    def fill(s0):
+        for b0 in range(s0, s0 + slab, block):
+            v = synth.sky_values(f, C, device=dev, dtype="bf16", chan_lo=b0, chan_hi=b0 + block)
+            dev_slab[:, b0 - s0:b0 - s0 + block].copy_(v)
+            del v
+        vals_h.copy_(dev_slab)
+        torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    plan = api.Plan(ra, dec, m, k, precision=api.HG_PREC_MFMA_BF16, time_channels=True)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    st = plan.stats()
+    fill(0)
+    plan.grid_host(vals_h, out=out_h, block=block)  # warm-up: the device ring is allocated
+    infos = []
+    for i in range(nslabs):
+        fill(i * slab)
+        _, info = plan.grid_host(vals_h, out=out_h, block=block)
+        infos.append(info)
+        log(f"slab {i}: wall {info['wall_ms']:.0f} ms, copies in {info['h2d_ms']:.0f} ms, "
+            f"kernels {info['kernel_ms']:.0f} ms, copies out {info['d2h_ms']:.0f} ms")
+    plan.close()
+    wall = sum(i["wall_ms"] for i in infos)
+    ker = sum(i["kernel_ms"] for i in infos)
+    h2d = sum(i["h2d_ms"] for i in infos)
+    d2h = sum(i["d2h_ms"] for i in infos)
+    nblocks = sum(i["blocks"] for i in infos)
+    hb = sum(i["h2d_bytes"] for i in infos)
+    db = sum(i["d2h_bytes"] for i in infos)
+    Cd = nblocks * block
+    e2e = setup_ms + wall
+    per_block = ker / max(nblocks, 1)
+    roof = roofline(2.0 * st["nnz"] * block, 2.0 * n * block + 4.0 * P * block, per_block,
+                    PEAK_F16_MFMA_TFLOPS, "k_channels (BF16 MFMA form), one 4096-channel block")
+    return {
+        "metric": "G sample*channel updates/s (BF16-MFMA form, streamed from host memory)",
+        "value": n * Cd / (e2e * 1e-3) / 1e9, "unit": "G sample*channel updates/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": e2e, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"large drift-scan cube: 1e6 samples of 19 interleaved beams over "
+                               f"10x10 deg, 600x600 map at 1 arcmin, {Cd} BF16 channels streamed "
+                               f"from page-locked host memory in blocks of {block}; step = setup "
+                               "+ every block's copy in, kernel and copy out",
+                   "n_samples": n, "channels": Cd, "blocks": nblocks, "slab_channels": slab,
+                   "nnz": st["nnz"]},
+        "setup_ms": setup_ms, "stream_wall_ms": wall, "kernel_ms_sum": ker, "h2d_ms_sum": h2d,
+        "d2h_ms_sum": d2h, "h2d_GBps": hb / (h2d * 1e-3) / 1e9, "d2h_GBps": db / (d2h * 1e-3) / 1e9,
+        "overlap": (h2d + ker + d2h) / wall,
+        "host_link_bound_ms": max(h2d, d2h), "kernel_ms_per_block": per_block,
+        "roofline": roof,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["drift", "batch", "paper", "literal", "fifo"],
+    ap.add_argument("--workload", choices=["drift", "batch", "paper", "literal", "fifo", "cube"],
                     default="drift")
+    ap.add_argument("--cube-slab", type=int, default=16384,
+                    help="cube workload: channels per host slab (a multiple of 4096)")
+    ap.add_argument("--cube-slabs", type=int, default=0,
+                    help="cube workload: slabs to stream (0 = the whole cube)")
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--map", choices=["car", "healpix"], default="car",
                     help="drift workload: plate-carree map or a HEALPix target patch")
@@ -583,7 +836,13 @@ def main():
     ap.add_argument("--fields", type=int, default=64)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=4500)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default kernel shape instead of the autotuned one")
+    ap.add_argument("--no-mfma-leg", action="store_true",
+                    help="drift workload: skip the BF16-MFMA form on the same cube")
+    ap.add_argument("--no-batch-leg", action="store_true",
+                    help="drift workload: skip the 64-field batched workload in both forms")
+    ap.add_argument("--cpu-pixels", type=int, default=9600)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain elementwise pass over 1 GiB (read 1 GiB, write "
                          "1 GiB) so that hardware byte counters can be scaled against it")
@@ -600,7 +859,7 @@ def main():
         log(f"copy calibration: {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
         del src, dst
     run = {"drift": run_drift, "batch": run_batch, "paper": run_paper,
-           "literal": run_literal, "fifo": run_fifo}[args.workload]
+           "literal": run_literal, "fifo": run_fifo, "cube": run_cube}[args.workload]
     res = run(args)
     print(json.dumps(res), flush=True)
 

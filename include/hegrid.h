@@ -128,11 +128,19 @@ typedef struct {
                                the 16-bit forms, shorter for very dense fields).  An
                                explicit chunk whose densest entry block would not fit
                                two staged chunks in LDS fails (HG_ERR_UNSUPPORTED)  */
-    int32_t reserved;       /* must be 0                                        */
+    int32_t waves;          /* channel kernel: waves per workgroup, 8 or 16; 0 = 16.
+                               The waves share the tile's 64 pixel groups       */
     int64_t device_mem_cap; /* bytes; 0 = none.  Setup fails with HG_ERR_NOMEM
                                before any allocation beyond it                  */
     uint32_t flags;         /* HG_FLAG_*                                        */
-    uint32_t reserved2;     /* must be 0                                        */
+    int32_t chan_block;     /* channel kernel: channels per workgroup, 64, 128 or
+                               256; 0 = 256.  waves, chan_block and chunk are the
+                               shapes the autotuner (tune.py) sweeps; the maps do
+                               not depend on waves and chan_block (the same
+                               operations in the same order), only on chunk.
+                               Shapes other than 16 x 256 are built for aligned
+                               FP32 values in the FP32 form and for the 16-bit
+                               forms; other calls use 16 x 256                  */
 } hg_opts;
 
 #define HG_FLAG_TIME_CHANNELS 1u /* record HIP events around channel kernels   */
@@ -149,6 +157,8 @@ typedef struct {
     int64_t device_bytes;/* device memory held by the plan                        */
     int32_t nside;
     int32_t chunk;
+    int32_t waves;        /* channel kernel shape the plan launches with:         */
+    int32_t chan_block;   /* waves per workgroup and channels per workgroup       */
     double setup_ms;      /* wall time of hg_grid_setup                           */
     double last_channels_ms; /* device time of the last hg_grid_channels (timed plans) */
     double total_channels_ms;
@@ -258,6 +268,16 @@ int hg_grid_finish(hg_plan* p);
    (cell, sample) pairs in support -- the terms of Eq. 1's sums -- and
    timings.  Synchronises to read channel timings. */
 int hg_plan_stats(hg_plan* p, hg_stats* s);
+
+/* Set the channel kernel's shape for the plan's later hg_grid_channels and
+   hg_grid_channels_host calls: waves 8 or 16 per workgroup, chan_block 64,
+   128 or 256 channels per workgroup (0 keeps 16 and 256).  The maps do not
+   change (every cell's sums are the same operations in the same order); only
+   the speed does.  This is how the autotuner times one plan in every shape
+   without repeating setup.  The paper tunes its kernel's block size by hand
+   for each GPU (Sec. 5.3.2 on the V100, Sec. 5.4 on the MI50).  Not
+   thread-safe with calls on the same plan; HG_ERR_ARG for other values. */
+int hg_plan_set_shape(hg_plan* p, int32_t waves, int32_t chan_block);
 
 /* Per-pixel neighbour counts |N(g)|, HOST int32 [ny*nx] (flat index j*nx + i):
    the number of samples s_n with d(g, s_n) <= R, the terms of Eq. 1's sums

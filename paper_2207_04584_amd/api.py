@@ -23,7 +23,7 @@ ABI_FUNCTIONS = ("hg_grid_setup", "hg_grid_channels", "hg_grid_finish", "hg_plan
                  "hg_plan_counts", "hg_plan_weight_sums", "hg_plan_neighbours",
                  "hg_ang2pix_ring", "hg_grid_channels_host", "hg_grid_channels_literal",
                  "hg_batch_create", "hg_batch_run", "hg_batch_destroy", "hg_batch_stats",
-                 "hg_batch_plan", "hg_map_pixel_ids", "hg_last_error")
+                 "hg_batch_plan", "hg_map_pixel_ids", "hg_plan_set_shape", "hg_last_error")
 
 
 class HegridError(RuntimeError):
@@ -54,9 +54,9 @@ HG_KERNEL_GAUSS, HG_KERNEL_GAUSS_SINC, HG_KERNEL_ELLIPTICAL = 0, 1, 2
 
 class hg_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("nside", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("device_mem_cap", ctypes.c_int64), ("flags", ctypes.c_uint32),
-                ("reserved2", ctypes.c_uint32)]
+                ("chan_block", ctypes.c_int32)]
 
 
 class hg_stats(ctypes.Structure):
@@ -64,7 +64,8 @@ class hg_stats(ctypes.Structure):
                 ("nnz", ctypes.c_int64), ("n_entries", ctypes.c_int64),
                 ("n_cells", ctypes.c_int64), ("total_slots", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("nside", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("setup_ms", ctypes.c_double),
+                ("chunk", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("chan_block", ctypes.c_int32), ("setup_ms", ctypes.c_double),
                 ("last_channels_ms", ctypes.c_double), ("total_channels_ms", ctypes.c_double),
                 ("channels_calls", ctypes.c_int64)]
 
@@ -112,6 +113,7 @@ def lib():
     L.hg_grid_finish.argtypes = [P]
     L.hg_plan_stats.argtypes = [P, ctypes.POINTER(hg_stats)]
     L.hg_plan_counts.argtypes = [P, P]
+    L.hg_plan_set_shape.argtypes = [P, i32, i32]
     L.hg_plan_weight_sums.argtypes = [P, P]
     L.hg_plan_neighbours.argtypes = [P, P, P, P, i64, ctypes.POINTER(ctypes.c_int64)]
     L.hg_ang2pix_ring.argtypes = [i32, P, P, i64, P, P]
@@ -205,7 +207,7 @@ class Plan:
     grid_finish on close()."""
 
     def __init__(self, ra_deg, dec_deg, map, kernel, precision=HG_PREC_FP32, nside=0, chunk=0,
-                 device_mem_cap=0, time_channels=False, stream=None):
+                 device_mem_cap=0, time_channels=False, stream=None, waves=0, chan_block=0):
         L = lib()
         ra, dec = _dev_f64(ra_deg), _dev_f64(dec_deg)
         if ra.shape != dec.shape or ra.dim() != 1:
@@ -214,8 +216,8 @@ class Plan:
         self.kernel = dict(kernel)
         self.n = ra.shape[0]
         self._m, self._k = make_map(map), make_kernel(kernel)
-        self._o = hg_opts(int(precision), int(nside), int(chunk), 0, int(device_mem_cap),
-                          HG_FLAG_TIME_CHANNELS if time_channels else 0, 0)
+        self._o = hg_opts(int(precision), int(nside), int(chunk), int(waves), int(device_mem_cap),
+                          HG_FLAG_TIME_CHANNELS if time_channels else 0, int(chan_block))
         self._h = ctypes.c_void_p()
         rc = L.hg_grid_setup(ctypes.c_void_p(ra.data_ptr() if self.n else 0),
                              ctypes.c_void_p(dec.data_ptr() if self.n else 0), self.n,
@@ -308,6 +310,13 @@ class Plan:
         st = hg_stats()
         _check(lib().hg_plan_stats(self._handle(), ctypes.byref(st)), "hg_plan_stats")
         return {f: getattr(st, f) for f, _ in hg_stats._fields_}
+
+    def set_shape(self, waves=0, chan_block=0):
+        """The channel kernel's shape for later grid calls (waves per
+        workgroup 8 / 16, channels per workgroup 64 / 128 / 256; 0 = default);
+        the maps do not depend on it."""
+        _check(lib().hg_plan_set_shape(self._handle(), int(waves), int(chan_block)),
+               "hg_plan_set_shape")
 
     def counts(self):
         ny, nx = self.shape
@@ -472,7 +481,7 @@ class Batch:
     of them and returns the list of outputs."""
 
     def __init__(self, fields, precision=HG_PREC_FP32, nside=0, chunk=0, device_mem_cap=0,
-                 time_runs=False, stream=None):
+                 time_runs=False, stream=None, waves=0, chan_block=0):
         torch = _torch()
         L = lib()
         self._keep = []
@@ -507,8 +516,8 @@ class Batch:
         if dtype is None:
             dtype = {1: HG_BF16, 2: HG_F16}.get(int(precision), HG_F32)
         self.dtype = dtype
-        self._o = hg_opts(int(precision), int(nside), int(chunk), 0, int(device_mem_cap),
-                          HG_FLAG_TIME_CHANNELS if time_runs else 0, 0)
+        self._o = hg_opts(int(precision), int(nside), int(chunk), int(waves), int(device_mem_cap),
+                          HG_FLAG_TIME_CHANNELS if time_runs else 0, int(chan_block))
         self._h = ctypes.c_void_p()
         _check(L.hg_batch_create(arr, len(fields), dtype, ctypes.byref(self._o),
                                  _stream_ptr(stream), ctypes.byref(self._h)), "hg_batch_create")

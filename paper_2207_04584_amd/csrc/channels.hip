@@ -6,18 +6,21 @@
 // V[c,p] = S[c,p] / W_p.  This is a sparse (pixels x samples) by dense
 // (samples x channels) product.  Layout of the work:
 //
-//   * a workgroup (16 waves) owns one tile (16 x 16 pixels = 8 x 8 pixel
-//     groups of 2 x 2) and one block of 256 channels;
+//   * a workgroup of WAVES waves (8 or 16) owns one tile (16 x 16 pixels =
+//     8 x 8 pixel groups of 2 x 2) and one block of 64 G channels (G = 1, 2
+//     or 4); WAVES and G are the kernel's shape, chosen per launch (the
+//     plan's entry blocks do not depend on them);
 //   * the tile's candidate samples (its slots) are processed in chunks of
-//     `chunk` slots.  For each chunk the workgroup stages, in LDS, the 256
+//     `chunk` slots.  For each chunk the workgroup stages, in LDS, the block's
 //     channels of every slot (one row per sample, read from the
 //     channel-contiguous values in HBM) and the chunk's entry block (the
 //     entries of all 64 groups, prepared by setup);
-//   * staging is double-buffered: the loads for chunk c+1 go straight from
-//     global memory to LDS (global_load_lds) while the waves compute chunk c;
-//   * each wave owns 4 pixel groups spread over the tile.  The MFMA rows are
-//     the group's four pixels (A = their weights) and the columns are the
-//     workgroup's channels, 4*lane + g for the g-th instruction (B = values);
+//   * staging is pipelined: the copies of later chunks go straight from
+//     global memory to LDS (global_load_lds) while the waves compute the
+//     current one;
+//   * each wave owns 64 / WAVES pixel groups spread over the tile.  The MFMA
+//     rows are a group's four pixels (A = their weights) and the columns are
+//     the block's channels, G l + g for the g-th instruction (B = values);
 //       - FP32 form: v_mfma_f32_4x4x1_16b_f32, one sample per instruction;
 //       - BF16 / FP16 forms: v_mfma_f32_4x4x4_16b_{bf16,f16}, four samples
 //         (one group of four entries) per instruction, FP32 accumulation;
@@ -37,28 +40,33 @@ typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 #define CONST_AS __attribute__((address_space(4)))
 
-constexpr int CH_WAVES = 16;
-constexpr int CH_THREADS = 64 * CH_WAVES;
-constexpr int G = 4;        // MFMA column blocks of 64 channels per workgroup
-constexpr int CW = 64 * G;  // channels per workgroup (256)
-constexpr int PGW = TILE_PGS / CH_WAVES;
-static_assert(TILE_PGX == 8 && TILE_PGY == 8 && CH_WAVES == 16,
-              "wave/group mapping assumes 8x8 groups, 16 waves");
+static_assert(TILE_PGX == 8 && TILE_PGY == 8, "wave/group mapping assumes 8 x 8 groups");
 constexpr int TILE_PX = TILE_PGX * PG;  // 16 pixels per tile side
-constexpr int OUT_STRIDE = CW / 2 + 4;  // LDS floats per pixel in the output transpose
-constexpr int OUT_LDS = TILE_PX * TILE_PX * OUT_STRIDE * 4;
 
 constexpr int FORM_F32 = 0;  // FP32 values in LDS, one entry per MFMA
 constexpr int FORM_M16 = 1;  // 16-bit values in LDS, groups of four entries per MFMA
 
-template <int FORM>
+template <int FORM, int G>
 struct Form {
     static constexpr int VB = FORM == FORM_F32 ? 4 : 2;   // bytes per staged value
+    static constexpr int CW = 64 * G;                      // channels per workgroup
     static constexpr int RB = CW * VB;                     // bytes per staged row
+    static constexpr int RPI = 1024 / RB;                  // rows per copy (16 B a lane)
+    static constexpr int LPR = 64 / RPI;                   // lanes per row of a copy
     // a unit is a group of four entries of one pixel group: weights [pixel][entry]
     static constexpr int WB = FORM == FORM_F32 ? 64 : 32;  // weight bytes per unit
     static constexpr int SB = 16;                          // slot bytes per unit
-    static constexpr int UPS = 4;                          // entries per unit
+    static constexpr int OCW = CW < 128 ? CW : 128;        // channels per epilogue pass
+    static constexpr int OUT_STRIDE = OCW + 4;             // LDS floats per pixel there
+};
+
+// Per wave: the staged rows of a chunk come in row groups of RPI adjacent
+// slots (one copy instruction each); wave w takes row groups w, w + WAVES, ...
+template <int FORM, int G, int WAVES>
+struct Rows {
+    static constexpr int RPI = Form<FORM, G>::RPI;
+    static constexpr int GPW = (MAX_CHUNK / RPI + WAVES - 1) / WAVES;  // row groups per wave
+    static constexpr int NRW = GPW * RPI;                              // rows per wave
 };
 
 // One staged chunk in LDS: `chunk` value rows, then the entry block (weights,
@@ -71,18 +79,16 @@ constexpr int MAX_NBUF = 4;
 // indices (MAX_CHUNK x uint32) and the 17 entry-block offsets of a half.
 constexpr int META_RUN = 16;
 constexpr int META_ROWS = 2 * META_RUN * MAX_CHUNK * 4;
-constexpr int META_LDS = META_ROWS + 2 * (META_RUN + 1) * 8;
+constexpr int META_LDS = META_ROWS + 2 * (META_RUN + 1) * 8 + TILE_PGS;  // + the group map
 
 struct LdsLayout {
     int vals, ew, es, po, stride;
-    template <int FORM>
-    __device__ __host__ static LdsLayout make(int chunk, int ucap) {
-        typedef Form<FORM> F;
+    __device__ __host__ static LdsLayout make(int rb, int wb, int chunk, int ucap) {
         LdsLayout L;
         L.vals = 0;
-        L.ew = L.vals + chunk * F::RB;
-        L.es = L.ew + ucap * F::WB;
-        L.po = L.es + ucap * F::SB;
+        L.ew = L.vals + chunk * rb;
+        L.es = L.ew + ucap * wb;
+        L.po = L.es + ucap * 16;
         L.stride = L.po + 144;
         return L;
     }
@@ -92,7 +98,8 @@ struct LdsLayout {
 // the wave-uniform LDS address).  They are issued through inline assembly so
 // that the compiler does not order every later LDS read behind them: the
 // kernel itself waits for them (s_waitcnt vmcnt) before the barrier that hands
-// a staged chunk to the compute loop.
+// a staged chunk to the compute loop.  No output register is involved: the
+// data goes to LDS only.
 __device__ inline uint32_t lds_addr(const char* l) {
     return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)l);
 }
@@ -108,6 +115,13 @@ __device__ inline void dma16s(const void* base, uint32_t voff, const char* l) {
     asm volatile("s_mov_b32 m0, %2\n\ts_nop 1\n\tglobal_load_lds_dwordx4 %0, %1"
                  :
                  : "v"(voff), "s"(uniform_ptr(base)), "s"(lds_addr(l))
+                 : "memory", "m0");
+}
+// The same with a per-lane 64-bit address: one copy serves several rows.
+__device__ inline void dma16v(const void* addr, const char* l) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 1\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(addr), "s"(lds_addr(l))
                  : "memory", "m0");
 }
 __device__ inline void dma4s(const void* base, uint32_t voff, const char* l) {
@@ -126,112 +140,152 @@ __device__ inline float f16_bits_to_f32(uint32_t b) {
     return (float)h;
 }
 
-// FP32 form, one staged row (1 KB): channels [c_lo, c_lo + 256) of `row` as
-// FP32; lane l writes channels 4l .. 4l+3.
-template <int DT, bool VEC>
-__device__ inline void stage_row_f32(char* dst, const void* values, int64_t ld, int32_t nchan,
-                                     int c_lo, uint32_t row, int lane, bool dma) {
-    int c = c_lo + 4 * lane;
-    if (DT == HG_F32) {
-        const float* src = (const float*)values + (int64_t)row * ld;
-        if (dma) {
-            dma16s(src + c_lo, 16u * lane, dst);
-            return;
-        }
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (VEC && c + 3 < nchan) {
-            v = *(const float4*)(src + c);
+// One row group: RPI adjacent staged rows of RB bytes, lane l covering 16
+// bytes of row l / LPR at byte offset 16 (l % LPR).  row: this lane's sample
+// index (read from the chunk's metadata in LDS); r, the rows present (the
+// group's last rows may be beyond the chunk).  DMA: one copy straight to LDS.
+// Otherwise (values that need a conversion, are misaligned or end inside the
+// block) through registers, channels past nchan read as 0.
+template <int FORM, int G, int DT, bool VEC>
+__device__ inline void stage_group(char* dst, const void* values, int64_t ld, int32_t nchan,
+                                   int c_lo, uint32_t row, int r, int lane, bool dma) {
+    typedef Form<FORM, G> F;
+    const int rl = lane / F::LPR, pc = lane % F::LPR;
+    if (rl >= r) return;
+    if (dma) {
+        // the element size equals the staged size here (FP32 from FP32, or 16-bit)
+        const char* src = (const char*)values + ((int64_t)row * ld + c_lo) * F::VB + 16 * pc;
+        dma16v(src, dst);
+        return;
+    }
+    char* d = dst + lane * 16;
+    if (FORM == FORM_F32) {
+        const int c = c_lo + 4 * pc;  // this lane's four channels
+        float f[4] = {0.f, 0.f, 0.f, 0.f};
+        if (DT == HG_F32) {
+            const float* src = (const float*)values + (int64_t)row * ld;
+            if (VEC && c + 3 < nchan) {
+                const float4 v = *(const float4*)(src + c);
+                f[0] = v.x;
+                f[1] = v.y;
+                f[2] = v.z;
+                f[3] = v.w;
+            } else {
+                for (int k = 0; k < 4; k++)
+                    if (c + k < nchan) f[k] = src[c + k];
+            }
         } else {
-            if (c + 0 < nchan) v.x = src[c + 0];
-            if (c + 1 < nchan) v.y = src[c + 1];
-            if (c + 2 < nchan) v.z = src[c + 2];
-            if (c + 3 < nchan) v.w = src[c + 3];
+            const uint16_t* src = (const uint16_t*)values + (int64_t)row * ld;
+            uint32_t u[4] = {0, 0, 0, 0};
+            if (VEC && c + 3 < nchan) {
+                const uint2 raw = *(const uint2*)(src + c);
+                u[0] = raw.x & 0xFFFF;
+                u[1] = raw.x >> 16;
+                u[2] = raw.y & 0xFFFF;
+                u[3] = raw.y >> 16;
+            } else {
+                for (int k = 0; k < 4; k++)
+                    if (c + k < nchan) u[k] = src[c + k];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                f[k] = (DT == HG_BF16) ? bf16_bits_to_f32(u[k]) : f16_bits_to_f32(u[k]);
         }
-        ((float4*)dst)[lane] = v;
+        *(float4*)d = make_float4(f[0], f[1], f[2], f[3]);
     } else {
-        const uint16_t* src = (const uint16_t*)values + (int64_t)row * ld;
-        uint32_t u[4] = {0, 0, 0, 0};
-        if (VEC && c + 3 < nchan) {
-            uint2 raw = *(const uint2*)(src + c);
+        const int c = c_lo + 8 * pc;  // eight 16-bit channels
+        const uint16_t* src = (const uint16_t*)values + (int64_t)row * ld + c;
+        uint32_t u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (VEC && c + 7 < nchan) {
+            const uint4 raw = *(const uint4*)src;
             u[0] = raw.x & 0xFFFF;
             u[1] = raw.x >> 16;
             u[2] = raw.y & 0xFFFF;
             u[3] = raw.y >> 16;
+            u[4] = raw.z & 0xFFFF;
+            u[5] = raw.z >> 16;
+            u[6] = raw.w & 0xFFFF;
+            u[7] = raw.w >> 16;
         } else {
-            for (int k = 0; k < 4; k++)
-                if (c + k < nchan) u[k] = src[c + k];
+            for (int k = 0; k < 8; k++)
+                if (c + k < nchan) u[k] = src[k];
         }
-        float f[4];
+        *(uint4*)d = make_uint4(u[0] | (u[1] << 16), u[2] | (u[3] << 16), u[4] | (u[5] << 16),
+                                u[6] | (u[7] << 16));
+    }
+}
+
+// FP32 form: this lane's G values of one staged row, and the G MFMAs of one
+// entry (A = this lane's pixel's weight, column block g = channel G l + g).
+template <int G>
+struct VF;
+template <>
+struct VF<4> {
+    typedef float4 T;
+    __device__ static float at(const T& v, int g) { return g == 0 ? v.x : g == 1 ? v.y : g == 2 ? v.z : v.w; }
+};
+template <>
+struct VF<2> {
+    typedef float2 T;
+    __device__ static float at(const T& v, int g) { return g == 0 ? v.x : v.y; }
+};
+template <>
+struct VF<1> {
+    typedef float T;
+    __device__ static float at(const T& v, int) { return v; }
+};
+
+template <int G>
+__device__ inline void mfma_f32(v4f* part, float a, const typename VF<G>::T& v) {
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-            f[k] = (DT == HG_BF16) ? bf16_bits_to_f32(u[k]) : f16_bits_to_f32(u[k]);
-        ((float4*)dst)[lane] = make_float4(f[0], f[1], f[2], f[3]);
-    }
+    for (int g = 0; g < G; g++)
+        part[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, VF<G>::at(v, g), part[g], 0, 0, 0);
 }
 
-// 16-bit forms, two staged rows (512 B each, adjacent in LDS): lanes 0-31
-// copy row a, lanes 32-63 row b, 8 channels per lane.
-template <bool VEC>
-__device__ inline void stage_rows_16(char* dst, const void* values, int64_t ld, int32_t nchan,
-                                     int c_lo, uint32_t row_a, uint32_t row_b, int nrows,
-                                     int lane, bool dma) {
-    int half = lane >> 5;
-    uint32_t row = half ? row_b : row_a;
-    int c = c_lo + 8 * (lane & 31);
-    const uint16_t* src = (const uint16_t*)values + (int64_t)row * ld + c;
-    if (dma) {
-        // one copy per row: lanes 0-31 fetch row a, lanes 32-63 row b, each
-        // lane landing at its own 16-byte slot of the adjacent LDS rows
-        const uint32_t voff = 16u * (lane & 31);
-        const uint16_t* base = (const uint16_t*)values + c_lo;
-        if (half == 0) dma16s(base + (int64_t)row_a * ld, voff, dst);
-        else if (nrows > 1) dma16s(base + (int64_t)row_b * ld, voff, dst);
-        return;
-    }
-    if (half >= nrows) return;
-    uint32_t u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (VEC && c + 7 < nchan) {
-        uint4 raw = *(const uint4*)src;
-        u[0] = raw.x & 0xFFFF;
-        u[1] = raw.x >> 16;
-        u[2] = raw.y & 0xFFFF;
-        u[3] = raw.y >> 16;
-        u[4] = raw.z & 0xFFFF;
-        u[5] = raw.z >> 16;
-        u[6] = raw.w & 0xFFFF;
-        u[7] = raw.w >> 16;
-    } else {
-        for (int k = 0; k < 8; k++)
-            if (c + k < nchan) u[k] = src[k];
-    }
-    ((uint4*)dst)[lane] = make_uint4(u[0] | (u[1] << 16), u[2] | (u[3] << 16),
-                                     u[4] | (u[5] << 16), u[6] | (u[7] << 16));
-}
-
-__device__ inline void mfma4_f32(v4f* part, float a, float4 v) {
-    part[0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.x, part[0], 0, 0, 0);
-    part[1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.y, part[1], 0, 0, 0);
-    part[2] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.z, part[2], 0, 0, 0);
-    part[3] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, v.w, part[3], 0, 0, 0);
-}
+// 16-bit forms: this lane's G values of one staged row as raw bits.
+template <int G>
+struct VH;
+template <>
+struct VH<4> {
+    typedef uint2 T;
+};
+template <>
+struct VH<2> {
+    typedef uint32_t T;
+};
+template <>
+struct VH<1> {
+    typedef uint16_t T;
+};
 
 // One group of four entries on the 16-bit MFMA.  a: this lane's pixel's four
-// weights (entries 0..3); v0..v3: this lane's channels 4l..4l+3 of the four
-// entries' samples.  Column block g takes channel 4l+g of each entry.
-template <int DT>
-__device__ inline void mfma4_16(v4f* part, uint2 a, uint2 v0, uint2 v1, uint2 v2, uint2 v3) {
-    // B_g = {v0[g], v1[g], v2[g], v3[g]}: gather 16-bit halves
-    uint2 b[4];
-    b[0] = make_uint2(__builtin_amdgcn_perm(v1.x, v0.x, 0x05040100u),
-                      __builtin_amdgcn_perm(v3.x, v2.x, 0x05040100u));
-    b[1] = make_uint2(__builtin_amdgcn_perm(v1.x, v0.x, 0x07060302u),
-                      __builtin_amdgcn_perm(v3.x, v2.x, 0x07060302u));
-    b[2] = make_uint2(__builtin_amdgcn_perm(v1.y, v0.y, 0x05040100u),
-                      __builtin_amdgcn_perm(v3.y, v2.y, 0x05040100u));
-    b[3] = make_uint2(__builtin_amdgcn_perm(v1.y, v0.y, 0x07060302u),
-                      __builtin_amdgcn_perm(v3.y, v2.y, 0x07060302u));
+// weights (entries 0..3); v0..v3: this lane's G channels of the four entries'
+// samples.  Column block g takes channel G l + g of each entry:
+// B_g = {v0[g], v1[g], v2[g], v3[g]}.
+template <int DT, int G>
+__device__ inline void mfma_16(v4f* part, uint2 a, const typename VH<G>::T& v0,
+                               const typename VH<G>::T& v1, const typename VH<G>::T& v2,
+                               const typename VH<G>::T& v3) {
+    uint2 b[G];
+    if constexpr (G == 4) {
+        b[0] = make_uint2(__builtin_amdgcn_perm(v1.x, v0.x, 0x05040100u),
+                          __builtin_amdgcn_perm(v3.x, v2.x, 0x05040100u));
+        b[1] = make_uint2(__builtin_amdgcn_perm(v1.x, v0.x, 0x07060302u),
+                          __builtin_amdgcn_perm(v3.x, v2.x, 0x07060302u));
+        b[2] = make_uint2(__builtin_amdgcn_perm(v1.y, v0.y, 0x05040100u),
+                          __builtin_amdgcn_perm(v3.y, v2.y, 0x05040100u));
+        b[3] = make_uint2(__builtin_amdgcn_perm(v1.y, v0.y, 0x07060302u),
+                          __builtin_amdgcn_perm(v3.y, v2.y, 0x07060302u));
+    } else if constexpr (G == 2) {
+        b[0] = make_uint2(__builtin_amdgcn_perm(v1, v0, 0x05040100u),
+                          __builtin_amdgcn_perm(v3, v2, 0x05040100u));
+        b[1] = make_uint2(__builtin_amdgcn_perm(v1, v0, 0x07060302u),
+                          __builtin_amdgcn_perm(v3, v2, 0x07060302u));
+    } else {
+        b[0] = make_uint2((uint32_t)v0 | ((uint32_t)v1 << 16), (uint32_t)v2 | ((uint32_t)v3 << 16));
+    }
 #pragma unroll
-    for (int g = 0; g < 4; g++) {
+    for (int g = 0; g < G; g++) {
         if (DT == HG_BF16) {
             v4s A, B;
             __builtin_memcpy(&A, &a, 8);
@@ -248,20 +302,43 @@ __device__ inline void mfma4_16(v4f* part, uint2 a, uint2 v0, uint2 v1, uint2 v2
 
 // Wait until at most k of this wave's copies are outstanding, for a
 // wave-uniform k.  The counter field of s_waitcnt is an immediate, so k is
-// rounded down to 0, 2, 4 or 8 (waiting for a little more than needed) to
-// keep the choice to three scalar branches.
+// rounded down to 0, 1, 2, 4, 8, 16 or 32 (waiting for a little more than
+// needed).  vmcnt is 6 bits: [3:0] and [15:14]; expcnt and lgkmcnt left open.
 __device__ inline void wait_copies(int k) {
-    if (k >= 8)
-        __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8), expcnt and lgkmcnt open
+    if (k >= 32)
+        __builtin_amdgcn_s_waitcnt(0x8F70);  // vmcnt(32)
+    else if (k >= 16)
+        __builtin_amdgcn_s_waitcnt(0x4F70);  // vmcnt(16)
+    else if (k >= 8)
+        __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8)
     else if (k >= 4)
         __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4)
     else if (k >= 2)
         __builtin_amdgcn_s_waitcnt(0x0F72);  // vmcnt(2)
+    else if (k >= 1)
+        __builtin_amdgcn_s_waitcnt(0x0F71);  // vmcnt(1)
     else
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 }
 
-template <int FORM, int DT, bool VEC>
+// Wave w's class of pixel groups: with 16 waves, four groups of one
+// (x mod 4, y mod 4) class; with 8 waves, eight of one (x mod 4, y mod 2)
+// class.  A chunk's samples are spatially compact, so classes spread each
+// chunk's entries over the waves.  The waves that share a SIMD (w mod 4
+// equal) take different x classes, so the chunk's matrix work also splits
+// evenly over the SIMDs.
+template <int WAVES>
+__device__ inline void wave_group(int wave, int k, int& lx, int& ly) {
+    if (WAVES == 16) {
+        lx = ((wave - (wave >> 2)) & 3) + 4 * (k & 1);
+        ly = (wave >> 2) + 4 * (k >> 1);
+    } else {
+        lx = ((wave + (wave >> 2)) & 3) + 4 * (k & 1);
+        ly = (wave >> 2) + 2 * (k >> 1);
+    }
+}
+
+template <int FORM, int DT, bool VEC, int WAVES, int G>
 __device__ __attribute__((always_inline)) inline void grid_item(
     const void* __restrict__ values, int64_t ld, int32_t nchan, int32_t npgx, int32_t npgy,
     int32_t ntx, int32_t nx, int32_t ny, int32_t chunk, const int64_t* __restrict__ tile_base,
@@ -269,16 +346,24 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     const int64_t* __restrict__ blk_base, const uint16_t* __restrict__ blk_pgoff,
     const void* __restrict__ ent_w, const void* __restrict__ ent_s,
     const float* __restrict__ pix_Wf, float* __restrict__ out, int32_t out_vec, int32_t ucap,
-    int32_t nbuf, int64_t tile, int64_t cb, char* smem) {
-    typedef Form<FORM> F;
-    const LdsLayout L = LdsLayout::make<FORM>(chunk, ucap);
+    int32_t nbuf, const uint32_t* __restrict__ pg_cnt, int32_t balance, int64_t tile, int64_t cb,
+    char* smem) {
+    typedef Form<FORM, G> F;
+    typedef Rows<FORM, G, WAVES> RW;
+    constexpr int THREADS = 64 * WAVES;
+    constexpr int PGW = TILE_PGS / WAVES;  // pixel groups per wave
+    // the FP32 form reads the next unit ahead of this unit's MFMAs where the
+    // registers allow it (16 waves of 256 channels have 128 registers a lane,
+    // which the accumulators and one unit's operands already take)
+    constexpr bool PIPE = !(FORM == FORM_F32 && WAVES == 16 && G == 4);
+    const LdsLayout L = LdsLayout::make(F::RB, F::WB, chunk, ucap);
     int tx = (int)(tile % ntx), ty = (int)(tile / ntx);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int c_lo = (int)cb * CW;
+    const int c_lo = (int)cb * F::CW;
     // value rows go straight to LDS when they need no conversion, are aligned
     // and are complete
-    const bool dma_rows = (FORM == FORM_F32 ? DT == HG_F32 : true) && VEC && c_lo + CW <= nchan;
+    const bool dma_rows = (FORM == FORM_F32 ? DT == HG_F32 : true) && VEC && c_lo + F::CW <= nchan;
 
     const int64_t s_base = tile_base[tile];
     const int64_t nslots = tile_base[tile + 1] - s_base;
@@ -286,41 +371,64 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     const int64_t nch = tile_blk[tile + 1] - blk0;
     const uint32_t* sidx = slot_idx + s_base;
 
-    // Wave w owns the four groups of one (x mod 4, y mod 4) class: a chunk's
-    // samples are spatially compact, so this spreads each chunk's entries
-    // over the 16 waves.  The class of wave w is y mod 4 = w / 4, x mod 4 =
-    // (w - w / 4) mod 4, so the four waves that share a SIMD (w mod 4 equal)
-    // own a diagonal of classes, one in every row and column: the chunk's
-    // matrix work then splits more evenly over the SIMDs than with the
-    // classes of one column per SIMD.
+    char* ring_rows = smem + nbuf * L.stride;
+    char* ring_blk = ring_rows + META_ROWS;
+    uint8_t* gmap = (uint8_t*)(ring_blk + 2 * (META_RUN + 1) * 8);
+    // Which pixel groups each wave owns.  Balanced: within each quadrant of
+    // 4 x 4 groups, the groups are ranked by their entry count (all chunks)
+    // and dealt to the waves in snake order, the direction alternating from
+    // quadrant to quadrant, so every wave keeps one group (16 waves) or two
+    // (8 waves) of every quadrant -- the spread over the tile that shares a
+    // chunk's work out -- while the waves' totals even out (drift scans put
+    // stripes of dense rows across a tile).  Otherwise the fixed classes of
+    // wave_group.
+    if (balance) {
+        if (wave == 0) {
+            const int gx = tx * TILE_PGX + (lane & 7), gy = ty * TILE_PGY + (lane >> 3);
+            const int c = gx < npgx && gy < npgy ? (int)pg_cnt[(int64_t)gy * npgx + gx] : -1;
+            const int q = ((lane >> 5) << 1) | ((lane >> 2) & 1);  // quadrant of group `lane`
+            int rank = 0;
+#pragma unroll
+            for (int j = 0; j < TILE_PGS; j++) {
+                const int cj = __builtin_amdgcn_readlane(c, j);
+                const int qj = ((j >> 5) << 1) | ((j >> 2) & 1);
+                rank += qj == q && (cj > c || (cj == c && j < lane));
+            }
+            constexpr int PER_Q = 16 / WAVES;  // groups of a quadrant per wave
+            const int jj = rank / WAVES, ii = rank % WAVES;
+            const int w = ((q + jj) & 1) ? WAVES - 1 - ii : ii;
+            gmap[w * PGW + q * PER_Q + jj] = (uint8_t)lane;
+        }
+        __syncthreads();
+    }
     bool pv[PGW];
     int lxs[PGW], lys[PGW];
 #pragma unroll
     for (int k = 0; k < PGW; k++) {
-        lxs[k] = ((wave - (wave >> 2)) & 3) + 4 * (k & 1);
-        lys[k] = (wave >> 2) + 4 * (k >> 1);
+        if (balance) {
+            const int g = gmap[wave * PGW + k];
+            lxs[k] = g & 7;
+            lys[k] = g >> 3;
+        } else {
+            wave_group<WAVES>(wave, k, lxs[k], lys[k]);
+        }
         pv[k] = tx * TILE_PGX + lxs[k] < npgx && ty * TILE_PGY + lys[k] < npgy;
     }
 
-    // Per chunk each wave stages up to four rows: w + 16 t in the FP32 form,
-    // the adjacent pairs (2w, 2w+1) and (2w+32, 2w+33) in the 16-bit forms
-    // (the rows that exist are always the first nrows of these).  The chunk metadata (the
-    // rows' sample indices and the entry block's extent) reaches LDS through
-    // the same asynchronous copies as the data, sixteen chunks at a time into
-    // one half of a two-half ring, long before it is read; the loop issues no
-    // scalar loads, whose latency the LDS waits of the compute phase would
-    // otherwise absorb.  The vector memory counter thus only counts copies,
-    // which the pipeline waits for explicitly.
-    char* ring_rows = smem + nbuf * L.stride;
-    char* ring_blk = ring_rows + META_ROWS;
+    // The chunk metadata (the staged rows' sample indices and the entry
+    // block's extent) reaches LDS through the same asynchronous copies as the
+    // data, sixteen chunks at a time into one half of a two-half ring, long
+    // before it is read; the loop issues no scalar loads, whose latency the
+    // LDS waits of the compute phase would otherwise absorb.  The vector
+    // memory counter thus only counts copies, which the pipeline waits for
+    // explicitly.
     struct Meta {
-        uint32_t row0, row1, row2, row3;
-        int nrows, ne;
+        const uint32_t* rr;  // the chunk's staged-row sample indices in the ring (LDS)
+        int nrows, ne;       // rows of this wave's groups present in the chunk; units
         int64_t blk, eb;
     };
-    auto row_slot = [&](int t) {
-        return FORM == FORM_F32 ? wave + CH_WAVES * t : 2 * wave + 32 * (t >> 1) + (t & 1);
-    };
+    // staged slot of this wave's t-th row
+    auto row_slot = [&](int t) { return F::RPI * (wave + WAVES * (t / F::RPI)) + t % F::RPI; };
     auto rd64 = [&](const char* p) {
         uint32_t lo = __builtin_amdgcn_readfirstlane(*(const uint32_t*)p);
         uint32_t hi = __builtin_amdgcn_readfirstlane(*(const uint32_t*)(p + 4));
@@ -333,30 +441,32 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         const char* bb = ring_blk + (h * (META_RUN + 1) + j) * 8;
         int64_t s0 = ch * chunk;
         int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
-        const int r0 = row_slot(0), r1 = row_slot(1), r2 = row_slot(2), r3 = row_slot(3);
-        m.nrows = (r0 < ns) + (r1 < ns) + (r2 < ns) + (r3 < ns);  // chunk <= 64
-        m.row0 = r0 < ns ? __builtin_amdgcn_readfirstlane(rr[r0]) : 0u;
-        m.row1 = r1 < ns ? __builtin_amdgcn_readfirstlane(rr[r1]) : 0u;
-        m.row2 = r2 < ns ? __builtin_amdgcn_readfirstlane(rr[r2]) : 0u;
-        m.row3 = r3 < ns ? __builtin_amdgcn_readfirstlane(rr[r3]) : 0u;
+        m.rr = rr;
+        m.nrows = 0;
+#pragma unroll
+        for (int t = 0; t < RW::NRW; t++) m.nrows += row_slot(t) < ns;
         m.blk = blk0 + ch;
         m.eb = rd64(bb);
         m.ne = (int)(rd64(bb + 8) - m.eb);
         return m;
     };
     // Copy the metadata of chunks [c0, c0 + 16) into ring half h: wave w the
-    // row indices of chunk c0 + w, wave 0 also the 17 block offsets.  Returns
-    // the copies this wave issued (each has at least one active lane).
+    // row indices of chunks c0 + w, c0 + w + WAVES, ..., wave 0 also the 17
+    // block offsets.  Returns the copies this wave issued (each has at least
+    // one active lane).
     auto refill = [&](int64_t c0, int h) {
         int k = 0;
-        const int64_t c = c0 + wave;
-        if (c < nch) {
-            const int64_t s0 = c * chunk;
-            const int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
-            if (lane < ns)
-                dma4s(sidx + s0, 4u * lane,
-                      ring_rows + (h * META_RUN + wave) * MAX_CHUNK * 4);
-            k++;
+#pragma unroll
+        for (int q = 0; q < META_RUN / WAVES; q++) {
+            const int j = wave + WAVES * q;
+            const int64_t c = c0 + j;
+            if (c < nch) {
+                const int64_t s0 = c * chunk;
+                const int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
+                if (lane < ns)
+                    dma4s(sidx + s0, 4u * lane, ring_rows + (h * META_RUN + j) * MAX_CHUNK * 4);
+                k++;
+            }
         }
         if (wave == 0) {
             // blk_base[blk0 + c0 + t] for t <= 16 while c0 + t <= nch
@@ -366,63 +476,41 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         }
         return k;
     };
+    // row groups of this wave present in a chunk, and its copy count
+    auto groups_of = [&](const Meta& m) { return (m.nrows + F::RPI - 1) / F::RPI; };
     auto issue = [&](const Meta& m, int buf) {
         char* base = smem + buf * L.stride;
-        if (FORM == FORM_F32) {
-            if (m.nrows > 0)
-                stage_row_f32<DT, VEC>(base + L.vals + row_slot(0) * F::RB, values, ld, nchan,
-                                       c_lo, m.row0, lane, dma_rows);
-            if (m.nrows > 1)
-                stage_row_f32<DT, VEC>(base + L.vals + row_slot(1) * F::RB, values, ld, nchan,
-                                       c_lo, m.row1, lane, dma_rows);
-            if (m.nrows > 2)
-                stage_row_f32<DT, VEC>(base + L.vals + row_slot(2) * F::RB, values, ld, nchan,
-                                       c_lo, m.row2, lane, dma_rows);
-            if (m.nrows > 3)
-                stage_row_f32<DT, VEC>(base + L.vals + row_slot(3) * F::RB, values, ld, nchan,
-                                       c_lo, m.row3, lane, dma_rows);
-            // a unit's weights are 64 bytes (four lanes), its slots 16 bytes (one lane)
-            const char* w = (const char*)ent_w + m.eb * 64;
-            for (int i = wave * 16; i < m.ne; i += CH_WAVES * 16)
-                if (i + (lane >> 2) < m.ne)
-                    dma16s(w + (int64_t)i * 64, 16u * lane, base + L.ew + i * 64);
-            const uint4* sl = (const uint4*)ent_s + m.eb;
-            for (int i = wave * 64; i < m.ne; i += CH_THREADS)
-                if (i + lane < m.ne) dma16s(sl + i, 16u * lane, base + L.es + i * 16);
-        } else {
-            if (m.nrows > 0)
-                stage_rows_16<VEC>(base + L.vals + row_slot(0) * F::RB, values, ld, nchan, c_lo,
-                                   m.row0, m.row1, m.nrows < 2 ? m.nrows : 2, lane, dma_rows);
-            if (m.nrows > 2)
-                stage_rows_16<VEC>(base + L.vals + row_slot(2) * F::RB, values, ld, nchan, c_lo,
-                                   m.row2, m.row3, m.nrows - 2, lane, dma_rows);
-            // a group's weights are 32 bytes (two lanes), its slots 16 bytes (one lane)
-            const char* w = (const char*)ent_w + m.eb * 32;
-            for (int i = wave * 32; i < m.ne; i += CH_WAVES * 32)
-                if (i + (lane >> 1) < m.ne)
-                    dma16s(w + (int64_t)i * 32, 16u * lane, base + L.ew + i * 32);
-            const uint4* sl = (const uint4*)ent_s + m.eb;
-            for (int i = wave * 64; i < m.ne; i += CH_THREADS)
-                if (i + lane < m.ne) dma16s(sl + i, 16u * lane, base + L.es + i * 16);
+#pragma unroll
+        for (int q = 0; q < RW::GPW; q++) {
+            const int t0 = q * F::RPI;
+            if (t0 < m.nrows) {
+                const int rl = lane / F::LPR;
+                const uint32_t row = rl < m.nrows - t0 ? m.rr[row_slot(t0) + rl] : 0u;
+                stage_group<FORM, G, DT, VEC>(base + L.vals + row_slot(t0) * F::RB, values, ld,
+                                              nchan, c_lo, row, m.nrows - t0, lane, dma_rows);
+            }
         }
-        if (wave == CH_WAVES - 1 && lane < PGOFF_STRIDE / 2)
+        // a unit's weights are WB bytes, its slots 16 bytes (one lane)
+        constexpr int UPC = 1024 / F::WB;  // units per weight copy
+        const char* w = (const char*)ent_w + m.eb * F::WB;
+        for (int i = wave * UPC; i < m.ne; i += WAVES * UPC)
+            if (i + lane / (64 / UPC) < m.ne)
+                dma16s(w + (int64_t)i * F::WB, 16u * lane, base + L.ew + i * F::WB);
+        const uint4* sl = (const uint4*)ent_s + m.eb;
+        for (int i = wave * 64; i < m.ne; i += THREADS)
+            if (i + lane < m.ne) dma16s(sl + i, 16u * lane, base + L.es + i * 16);
+        if (wave == WAVES - 1 && lane < PGOFF_STRIDE / 2)
             dma4s(blk_pgoff + m.blk * PGOFF_STRIDE, 4u * lane, base + L.po);
     };
     // Copy instructions issue() is certain to start for this wave (each
     // counted one has at least one active lane).  Copies whose lanes may all
     // be off are left out, which only makes the waits below stricter.
     auto copies = [&](const Meta& m) {
-        int k = 0;
-        if (FORM == FORM_F32) {
-            if (dma_rows) k += m.nrows;
-            if (m.ne > wave * 16) k += (m.ne - wave * 16 + CH_WAVES * 16 - 1) / (CH_WAVES * 16);
-            if (m.ne > wave * 64) k += (m.ne - wave * 64 + CH_THREADS - 1) / CH_THREADS;
-        } else {
-            if (dma_rows && m.nrows > 0) k += m.nrows;
-            if (m.ne > wave * 32) k += (m.ne - wave * 32 + CH_WAVES * 32 - 1) / (CH_WAVES * 32);
-            if (m.ne > wave * 64) k += (m.ne - wave * 64 + CH_THREADS - 1) / CH_THREADS;
-        }
-        if (wave == CH_WAVES - 1) k += 1;
+        constexpr int UPC = 1024 / F::WB;
+        int k = dma_rows ? groups_of(m) : 0;
+        if (m.ne > wave * UPC) k += (m.ne - wave * UPC + WAVES * UPC - 1) / (WAVES * UPC);
+        if (m.ne > wave * 64) k += (m.ne - wave * 64 + THREADS - 1) / THREADS;
+        if (wave == WAVES - 1) k += 1;
         return k;
     };
     v4f acc[PGW][G];
@@ -483,8 +571,8 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         const char* ew = base + L.ew;
         const uint32_t* es = (const uint32_t*)(base + L.es);
         const uint16_t* po = (const uint16_t*)(base + L.po);
-        // The wave's four groups: their unit ranges (all 65 offsets come in
-        // with one read, lane l holding offset l) and their slot runs (at most
+        // The wave's groups: their unit ranges (all 65 offsets come in with
+        // one read, lane l holding offset l) and their slot runs (at most
         // `chunk` slots each, lane i holding the run's i-th), all read before
         // any is used so that the LDS latency is paid once per chunk.  Ranges
         // and slots are wave-uniform and go to scalar registers by v_readlane.
@@ -518,7 +606,7 @@ __device__ __attribute__((always_inline)) inline void grid_item(
 #pragma unroll
             for (int k = 0; k < PGW; k++) mine += pv[k] ? nK[k] : 0;
             // against the chunk's total entries (padding included)
-            const int share = mine * CH_WAVES / (FORM == FORM_F32 ? 1 : 4);
+            const int share = mine * WAVES / (FORM == FORM_F32 ? 1 : 4);
             if (share >= 2 * po_end)
                 __builtin_amdgcn_s_setprio(3);
             else if (2 * share >= 3 * po_end)
@@ -537,62 +625,89 @@ __device__ __attribute__((always_inline)) inline void grid_item(
 #pragma unroll
             for (int g = 0; g < G; g++) part[g] = (v4f){0.f, 0.f, 0.f, 0.f};
             const int q = lane & 3;
-            if (FORM == FORM_F32) {
+            const uint32_t slot_lane = slK[k];
+            if constexpr (FORM == FORM_F32) {
                 // Each entry's slot comes from v_readlane into a scalar
                 // register, so the value read needs no second LDS round trip.
                 // Entries go a unit (four) at a time: one 16-byte read brings
-                // this lane's pixel's four weights, and the step's five LDS
-                // reads are in flight together ahead of its sixteen MFMAs.  A
-                // run's last unit multiplies only its real entries.
-                const uint32_t slot_lane = slK[k];
+                // this lane's pixel's four weights.  The next unit's five LDS
+                // reads are issued before this unit's 4 G MFMAs, so their
+                // latency overlaps the matrix work.  A run's last unit
+                // multiplies only its real entries.
+                typedef typename VF<G>::T VT;
                 const char* wq = ew + e * F::WB + q * 16;
-                const char* vl = vals + lane * 16;
+                const char* vl = vals + lane * (G * 4);
+                auto ldv = [&](int j) {
+                    return *(const VT*)(vl + __builtin_amdgcn_readlane(slot_lane, j) * F::RB);
+                };
                 int j = 0;
-                for (; j + 4 <= n; j += 4) {
-                    uint32_t s0 = __builtin_amdgcn_readlane(slot_lane, j);
-                    uint32_t s1 = __builtin_amdgcn_readlane(slot_lane, j + 1);
-                    uint32_t s2 = __builtin_amdgcn_readlane(slot_lane, j + 2);
-                    uint32_t s3 = __builtin_amdgcn_readlane(slot_lane, j + 3);
-                    const float4 a = *(const float4*)(wq + j * 16);
-                    float4 v0 = *(const float4*)(vl + s0 * F::RB);
-                    float4 v1 = *(const float4*)(vl + s1 * F::RB);
-                    float4 v2 = *(const float4*)(vl + s2 * F::RB);
-                    float4 v3 = *(const float4*)(vl + s3 * F::RB);
-                    mfma4_f32(part, a.x, v0);
-                    mfma4_f32(part, a.y, v1);
-                    mfma4_f32(part, a.z, v2);
-                    mfma4_f32(part, a.w, v3);
-                    // schedule: all LDS reads of the step, then its MFMAs
-                    __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+                if (!PIPE) {
+                    for (; j + 4 <= n; j += 4) {
+                        const float4 a = *(const float4*)(wq + j * 16);
+                        const VT v0 = ldv(j), v1 = ldv(j + 1), v2 = ldv(j + 2), v3 = ldv(j + 3);
+                        mfma_f32<G>(part, a.x, v0);
+                        mfma_f32<G>(part, a.y, v1);
+                        mfma_f32<G>(part, a.z, v2);
+                        mfma_f32<G>(part, a.w, v3);
+                        // schedule: all LDS reads of the step, then its MFMAs
+                        __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, 4 * G, 0);
+                    }
+                } else if (n >= 4) {
+                    float4 a = *(const float4*)wq;
+                    VT v0 = ldv(0), v1 = ldv(1), v2 = ldv(2), v3 = ldv(3);
+                    for (; j + 8 <= n; j += 4) {
+                        const float4 an = *(const float4*)(wq + (j + 4) * 16);
+                        const VT u0 = ldv(j + 4), u1 = ldv(j + 5), u2 = ldv(j + 6), u3 = ldv(j + 7);
+                        mfma_f32<G>(part, a.x, v0);
+                        mfma_f32<G>(part, a.y, v1);
+                        mfma_f32<G>(part, a.z, v2);
+                        mfma_f32<G>(part, a.w, v3);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, 4 * G, 0);
+                        a = an;
+                        v0 = u0;
+                        v1 = u1;
+                        v2 = u2;
+                        v3 = u3;
+                    }
+                    mfma_f32<G>(part, a.x, v0);
+                    mfma_f32<G>(part, a.y, v1);
+                    mfma_f32<G>(part, a.z, v2);
+                    mfma_f32<G>(part, a.w, v3);
+                    j += 4;
                 }
                 if (j < n) {
                     const int r = n - j;  // 1..3 entries left
                     const float4 a = *(const float4*)(wq + j * 16);
-                    mfma4_f32(part, a.x,
-                              *(const float4*)(vl + __builtin_amdgcn_readlane(slot_lane, j) * F::RB));
-                    if (r > 1)
-                        mfma4_f32(part, a.y, *(const float4*)(vl + __builtin_amdgcn_readlane(
-                                                                       slot_lane, j + 1) * F::RB));
-                    if (r > 2)
-                        mfma4_f32(part, a.z, *(const float4*)(vl + __builtin_amdgcn_readlane(
-                                                                       slot_lane, j + 2) * F::RB));
+                    mfma_f32<G>(part, a.x, ldv(j));
+                    if (r > 1) mfma_f32<G>(part, a.y, ldv(j + 1));
+                    if (r > 2) mfma_f32<G>(part, a.z, ldv(j + 2));
                 }
             } else {
-                // groups of four entries, slots picked by v_readlane
-                const uint32_t slot_lane = slK[k];
-                for (int t = 0; t < n / 4; t++) {
-                    uint32_t s0 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 0);
-                    uint32_t s1 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 1);
-                    uint32_t s2 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 2);
-                    uint32_t s3 = __builtin_amdgcn_readlane(slot_lane, 4 * t + 3);
-                    uint2 a = *(const uint2*)(ew + (e + t) * 32 + q * 8);
-                    uint2 v0 = *(const uint2*)(vals + s0 * F::RB + lane * 8);
-                    uint2 v1 = *(const uint2*)(vals + s1 * F::RB + lane * 8);
-                    uint2 v2 = *(const uint2*)(vals + s2 * F::RB + lane * 8);
-                    uint2 v3 = *(const uint2*)(vals + s3 * F::RB + lane * 8);
-                    mfma4_16<DT>(part, a, v0, v1, v2, v3);
+                // groups of four entries, slots picked by v_readlane, the
+                // next group's reads issued ahead of this group's MFMAs
+                typedef typename VH<G>::T VT;
+                const char* vl = vals + lane * (G * 2);
+                auto ldv = [&](int j) {
+                    return *(const VT*)(vl + __builtin_amdgcn_readlane(slot_lane, j) * F::RB);
+                };
+                const char* wq = ew + e * 32 + q * 8;
+                const int nt = n / 4;
+                uint2 a = *(const uint2*)wq;
+                VT v0 = ldv(0), v1 = ldv(1), v2 = ldv(2), v3 = ldv(3);
+                for (int t = 0; t + 1 < nt; t++) {
+                    const uint2 an = *(const uint2*)(wq + (t + 1) * 32);
+                    const VT u0 = ldv(4 * t + 4), u1 = ldv(4 * t + 5), u2 = ldv(4 * t + 6),
+                             u3 = ldv(4 * t + 7);
+                    mfma_16<DT, G>(part, a, v0, v1, v2, v3);
+                    a = an;
+                    v0 = u0;
+                    v1 = u1;
+                    v2 = u2;
+                    v3 = u3;
                 }
+                mfma_16<DT, G>(part, a, v0, v1, v2, v3);
             }
 #pragma unroll
             for (int g = 0; g < G; g++) acc[k][g] += part[g];
@@ -600,16 +715,19 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     }
 
     // Epilogue.  acc[k][g] register i, lane l = pixel i of group k, channel
-    // c_lo + 4l + g.  Normalised values go through LDS ([pixel][channel],
-    // 128 channels per pass) so that the [c][j][i] output is written as rows
+    // c_lo + G l + g.  Normalised values go through LDS ([pixel][channel],
+    // OCW channels per pass) so that the [c][j][i] output is written as rows
     // of 16 contiguous pixels instead of one scattered float per lane.
     __syncthreads();
     float* ol = (float*)smem;
     const int64_t P = (int64_t)nx * ny;
     const int x0 = tx * TILE_PX, y0 = ty * TILE_PX;
+    constexpr int PASSES = F::CW / F::OCW;
+    constexpr int LPP = F::OCW / G;  // lanes per pass
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
-        if ((lane >> 5) == h) {
+    for (int h = 0; h < PASSES; h++) {
+        if (lane / LPP == h) {
+            const int cl0 = G * (lane % LPP);
 #pragma unroll
             for (int k = 0; k < PGW; k++) {
                 if (!pv[k]) continue;
@@ -618,40 +736,41 @@ __device__ __attribute__((always_inline)) inline void grid_item(
                     int pxl = lxs[k] * PG + (i & 1), pyl = lys[k] * PG + (i >> 1);
                     if (x0 + pxl >= nx || y0 + pyl >= ny) continue;
                     float W = pix_Wf[(int64_t)(y0 + pyl) * nx + x0 + pxl];
-                    float4 v = make_float4(acc[k][0][i] / W, acc[k][1][i] / W, acc[k][2][i] / W,
-                                           acc[k][3][i] / W);
-                    *(float4*)(ol + (pyl * TILE_PX + pxl) * OUT_STRIDE + 4 * (lane & 31)) = v;
+                    float* d = ol + (pyl * TILE_PX + pxl) * F::OUT_STRIDE + cl0;
+#pragma unroll
+                    for (int g = 0; g < G; g++) d[g] = acc[k][g][i] / W;
                 }
             }
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < (CW / 2) * TILE_PX * (TILE_PX / 4); t += CH_THREADS) {
+        for (int t = threadIdx.x; t < F::OCW * TILE_PX * (TILE_PX / 4); t += THREADS) {
             int qd = t % (TILE_PX / 4), row = t / (TILE_PX / 4);
             int pyl = row % TILE_PX, cl = row / TILE_PX;
-            int c = c_lo + h * (CW / 2) + cl, y = y0 + pyl, x = x0 + 4 * qd;
+            int c = c_lo + h * F::OCW + cl, y = y0 + pyl, x = x0 + 4 * qd;
             if (c >= nchan || y >= ny || x >= nx) continue;
-            const float* src = ol + (pyl * TILE_PX + 4 * qd) * OUT_STRIDE + cl;
+            const float* src = ol + (pyl * TILE_PX + 4 * qd) * F::OUT_STRIDE + cl;
             float* dst = out + (int64_t)c * P + (int64_t)y * nx + x;
             if (out_vec && x + 3 < nx) {
-                *(float4*)dst = make_float4(src[0], src[OUT_STRIDE], src[2 * OUT_STRIDE],
-                                            src[3 * OUT_STRIDE]);
+                *(float4*)dst = make_float4(src[0], src[F::OUT_STRIDE], src[2 * F::OUT_STRIDE],
+                                            src[3 * F::OUT_STRIDE]);
             } else {
-                for (int j = 0; j < 4 && x + j < nx; j++) dst[j] = src[j * OUT_STRIDE];
+                for (int j = 0; j < 4 && x + j < nx; j++) dst[j] = src[j * F::OUT_STRIDE];
             }
         }
         __syncthreads();
     }
 }
 
-template <int FORM, int DT, bool VEC>
-__global__ __launch_bounds__(CH_THREADS) void k_channels(
+template <int FORM, int DT, bool VEC, int WAVES, int G>
+__global__ __launch_bounds__(64 * WAVES) void k_channels(
     const void* __restrict__ values, int64_t ld, int32_t nchan, int32_t ncb, int32_t npgx,
     int32_t npgy, int32_t ntx, int32_t nx, int32_t ny, int32_t chunk,
     const int64_t* __restrict__ tile_base, const uint32_t* __restrict__ slot_idx,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ blk_base,
     const uint16_t* __restrict__ blk_pgoff, const void* __restrict__ ent_w,
     const void* __restrict__ ent_s, const float* __restrict__ pix_Wf, float* __restrict__ out,
-    int32_t out_vec, int32_t ucap, int32_t nbuf, const int64_t* __restrict__ order) {
+    int32_t out_vec, int32_t ucap, int32_t nbuf, const uint32_t* __restrict__ pg_cnt,
+    int32_t balance, const int64_t* __restrict__ order) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     // Workgroup b takes the plan's item order[b] (tile * ncb + channel block),
     // laid out as for the batched form: a tile's channel blocks on one XCD,
@@ -659,9 +778,10 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
     // cost; -1 marks an idle workgroup.
     const int64_t item = order[blockIdx.x];
     if (item < 0) return;
-    grid_item<FORM, DT, VEC>(values, ld, nchan, npgx, npgy, ntx, nx, ny, chunk, tile_base,
-                             slot_idx, tile_blk, blk_base, blk_pgoff, ent_w, ent_s, pix_Wf, out,
-                             out_vec, ucap, nbuf, item / ncb, item % ncb, smem);
+    grid_item<FORM, DT, VEC, WAVES, G>(values, ld, nchan, npgx, npgy, ntx, nx, ny, chunk,
+                                       tile_base, slot_idx, tile_blk, blk_base, blk_pgoff, ent_w,
+                                       ent_s, pix_Wf, out, out_vec, ucap, nbuf, pg_cnt, balance,
+                                       item / ncb, item % ncb, smem);
 }
 
 // Batched form: one launch over the (field, tile, channel block) items of many
@@ -672,8 +792,8 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels(
 // L2), and within an XCD they are ordered by decreasing cost, so a CU that
 // frees up always takes the largest item left.  Padding items (field < 0)
 // return at once.
-template <int FORM, int DT, bool VEC>
-__global__ __launch_bounds__(CH_THREADS) void k_channels_batch(
+template <int FORM, int DT, bool VEC, int WAVES, int G>
+__global__ __launch_bounds__(64 * WAVES) void k_channels_batch(
     const FieldDesc* __restrict__ fields, const BatchItem* __restrict__ items) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     // descriptors and items are never written by the kernel: reading them
@@ -682,64 +802,83 @@ __global__ __launch_bounds__(CH_THREADS) void k_channels_batch(
     const int32_t f = it->field;
     if (f < 0) return;
     const CONST_AS FieldDesc& d = ((const CONST_AS FieldDesc*)fields)[f];
-    grid_item<FORM, DT, VEC>(d.values, d.ld, d.nchan, d.npgx, d.npgy, d.ntx, d.nx, d.ny, d.chunk,
-                             d.tile_base, d.slot_idx, d.tile_blk, d.blk_base, d.blk_pgoff,
-                             d.ent_w, d.ent_s, d.pix_Wf, d.out, d.out_vec, d.ucap, d.nbuf,
-                             it->tile, it->cb, smem);
+    grid_item<FORM, DT, VEC, WAVES, G>(d.values, d.ld, d.nchan, d.npgx, d.npgy, d.ntx, d.nx, d.ny,
+                                       d.chunk, d.tile_base, d.slot_idx, d.tile_blk, d.blk_base,
+                                       d.blk_pgoff, d.ent_w, d.ent_s, d.pix_Wf, d.out, d.out_vec,
+                                       d.ucap, d.nbuf, d.pg_cnt, d.balance, it->tile, it->cb, smem);
 }
 
 // LDS plan of a field: entry capacity, resident chunks and dynamic LDS bytes
 // (the output transpose of the epilogue reuses the same space).
-size_t lds_stride(bool m16, int chunk, int ucap) {
-    return m16 ? LdsLayout::make<FORM_M16>(chunk, ucap).stride
-               : LdsLayout::make<FORM_F32>(chunk, ucap).stride;
+size_t lds_stride(bool m16, int chunk, int ucap, int g) {
+    const int rb = 64 * g * (m16 ? 2 : 4);
+    return LdsLayout::make(rb, m16 ? 32 : 64, chunk, ucap).stride;
 }
 
-void lds_plan(bool m16, int chunk, int blk_max, int32_t& ucap, int32_t& nbuf) {
+void lds_plan(bool m16, int chunk, int blk_max, int g, int32_t& ucap, int32_t& nbuf) {
     ucap = (blk_max < 4 ? 4 : (blk_max + 3) / 4 * 4);
-    nbuf = (int32_t)((LDS_BYTES - META_LDS) / lds_stride(m16, chunk, ucap));
+    nbuf = (int32_t)((LDS_BYTES - META_LDS) / lds_stride(m16, chunk, ucap, g));
     if (nbuf > MAX_NBUF) nbuf = MAX_NBUF;
-    if (nbuf < 2) nbuf = 2;  // not reached: a block holds at most 64 x chunk entries
+    if (nbuf < 2) nbuf = 2;  // not reached: setup checks the fit for the widest block
 }
 
-size_t lds_shm(bool m16, int chunk, int ucap, int nbuf) {
-    size_t shm = (size_t)nbuf * lds_stride(m16, chunk, ucap) + META_LDS;
-    return shm < (size_t)OUT_LDS ? (size_t)OUT_LDS : shm;
+size_t out_lds(int g) {
+    const int ocw = g >= 2 ? 128 : 64;
+    return (size_t)TILE_PX * TILE_PX * (ocw + 4) * 4;
 }
 
+size_t lds_shm(bool m16, int chunk, int ucap, int nbuf, int g) {
+    size_t shm = (size_t)nbuf * lds_stride(m16, chunk, ucap, g) + META_LDS;
+    return shm < out_lds(g) ? out_lds(g) : shm;
+}
+
+// Kernel instances: every dtype and vector path at the default shape (16
+// waves, 256 channels); the tuned shapes for the aligned paths the workloads
+// use (FP32 values in the FP32 form, BF16 / FP16 values in the 16-bit forms).
 template <int FORM, int DT, bool VEC>
-hipError_t launch_typed(const FieldDesc& d, const int64_t* order, int64_t nwg, hipStream_t s) {
-    size_t shm = lds_shm(FORM == FORM_M16, d.chunk, d.ucap, d.nbuf);
-    auto kern = k_channels<FORM, DT, VEC>;
-    if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(CH_THREADS), shm, s, d.values, d.ld,
-                       d.nchan, d.ncb, d.npgx, d.npgy, d.ntx, d.nx, d.ny, d.chunk, d.tile_base,
-                       d.slot_idx, d.tile_blk, d.blk_base, d.blk_pgoff, d.ent_w, d.ent_s,
-                       d.pix_Wf, d.out, d.out_vec, d.ucap, d.nbuf, order);
-    return hipGetLastError();
+constexpr bool shape_instances() {
+    return VEC && ((FORM == FORM_F32 && DT == HG_F32) || FORM == FORM_M16);
 }
 
-// One function pointer per (form, dtype, vec) for the two launch forms.
-template <template <int, int, bool> class K>
-const void* pick(bool m16, int32_t dtype, bool vec) {
+template <template <int, int, bool, int, int> class K, int FORM, int DT, bool VEC>
+const void* pick_shape(int waves, int g) {
+    if constexpr (shape_instances<FORM, DT, VEC>()) {
+        if (waves == 8) {
+            if (g == 4) return K<FORM, DT, VEC, 8, 4>::f();
+            if (g == 2) return K<FORM, DT, VEC, 8, 2>::f();
+            return K<FORM, DT, VEC, 8, 1>::f();
+        }
+        if (g == 2) return K<FORM, DT, VEC, 16, 2>::f();
+        if (g == 1) return K<FORM, DT, VEC, 16, 1>::f();
+    }
+    return K<FORM, DT, VEC, 16, 4>::f();
+}
+
+template <template <int, int, bool, int, int> class K>
+const void* pick(bool m16, int32_t dtype, bool vec, int waves, int g) {
     if (m16) {
         if (dtype == HG_BF16)
-            return vec ? K<FORM_M16, HG_BF16, true>::f() : K<FORM_M16, HG_BF16, false>::f();
-        return vec ? K<FORM_M16, HG_F16, true>::f() : K<FORM_M16, HG_F16, false>::f();
+            return vec ? pick_shape<K, FORM_M16, HG_BF16, true>(waves, g)
+                       : pick_shape<K, FORM_M16, HG_BF16, false>(waves, g);
+        return vec ? pick_shape<K, FORM_M16, HG_F16, true>(waves, g)
+                   : pick_shape<K, FORM_M16, HG_F16, false>(waves, g);
     }
     if (dtype == HG_F32)
-        return vec ? K<FORM_F32, HG_F32, true>::f() : K<FORM_F32, HG_F32, false>::f();
+        return vec ? pick_shape<K, FORM_F32, HG_F32, true>(waves, g)
+                   : pick_shape<K, FORM_F32, HG_F32, false>(waves, g);
     if (dtype == HG_BF16)
-        return vec ? K<FORM_F32, HG_BF16, true>::f() : K<FORM_F32, HG_BF16, false>::f();
-    return vec ? K<FORM_F32, HG_F16, true>::f() : K<FORM_F32, HG_F16, false>::f();
+        return vec ? pick_shape<K, FORM_F32, HG_BF16, true>(waves, g)
+                   : pick_shape<K, FORM_F32, HG_BF16, false>(waves, g);
+    return vec ? pick_shape<K, FORM_F32, HG_F16, true>(waves, g)
+               : pick_shape<K, FORM_F32, HG_F16, false>(waves, g);
 }
-template <int FORM, int DT, bool VEC>
+template <int FORM, int DT, bool VEC, int WAVES, int G>
+struct SingleKernel {
+    static const void* f() { return (const void*)k_channels<FORM, DT, VEC, WAVES, G>; }
+};
+template <int FORM, int DT, bool VEC, int WAVES, int G>
 struct BatchKernel {
-    static const void* f() { return (const void*)k_channels_batch<FORM, DT, VEC>; }
+    static const void* f() { return (const void*)k_channels_batch<FORM, DT, VEC, WAVES, G>; }
 };
 
 }  // namespace
@@ -751,20 +890,29 @@ bool values_vec(const Plan& P, const void* values, int64_t ld, int32_t dtype) {
     return a % 8 == 0 && ld % 4 == 0;
 }
 
-FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out) {
+Shape effective_shape(bool m16, int32_t dtype, bool vec, Shape s) {
+    const bool tuned = vec && (m16 || dtype == HG_F32);
+    if (!tuned || (s.waves != 8 && s.waves != 16) || (s.g != 1 && s.g != 2 && s.g != 4))
+        return Shape{};
+    return s;
+}
+
+FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out,
+                     Shape shape) {
     FieldDesc d{};
     bool m16 = P.opts.precision != HG_PREC_FP32;
+    const int cw = 64 * shape.g;
     d.values = values;
     d.ld = ld;
     d.nchan = nchan;
-    d.ncb = (nchan + CW - 1) / CW;
+    d.ncb = (nchan + cw - 1) / cw;
     d.npgx = P.npgx;
     d.npgy = P.npgy;
     d.ntx = P.ntx;
     d.nx = P.map.nx;
     d.ny = P.map.ny;
     d.chunk = P.chunk;
-    lds_plan(m16, P.chunk, P.blk_max, d.ucap, d.nbuf);
+    lds_plan(m16, P.chunk, P.blk_max, shape.g, d.ucap, d.nbuf);
     d.out_vec = ((uintptr_t)out % 16 == 0) && (P.map.nx % 4 == 0);
     d.tile_base = (const int64_t*)P.tile_nslots.p;
     d.slot_idx = (const uint32_t*)P.slot_idx.p;
@@ -774,51 +922,71 @@ FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t ncha
     d.ent_w = m16 ? P.e3_w.p : P.e2_w.p;
     d.ent_s = m16 ? P.e3_s.p : P.e2_s.p;
     d.pix_Wf = (const float*)P.pix_Wf.p;
+    d.pg_cnt = (const uint32_t*)P.pg_cnt.p;
+    {
+        const char* b = getenv("HEGRID_BALANCE");
+        d.balance = b ? atoi(b) : 1;
+    }
     d.out = out;
     return d;
 }
 
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
-                           float* out, hipStream_t s) {
-    bool vec = values_vec(P, values, ld, dtype);
-    FieldDesc d = field_desc(P, values, ld, nchan, out);
+                           float* out, hipStream_t s, Shape shape) {
+    const bool vec = values_vec(P, values, ld, dtype);
+    const bool m16 = P.opts.precision != HG_PREC_FP32;
+    shape = effective_shape(m16, dtype, vec, shape);
+    const int32_t ncb = (nchan + 64 * shape.g - 1) / (64 * shape.g);
     const int64_t* order = nullptr;
     int64_t nwg = 0;
-    hipError_t e = launch_order(P, d.ncb, s, &order, &nwg);
+    hipError_t e = launch_order(P, ncb, s, &order, &nwg);
     if (e != hipSuccess) return e;
-    if (P.opts.precision != HG_PREC_FP32) {
-        if (dtype == HG_BF16)
-            return vec ? launch_typed<FORM_M16, HG_BF16, true>(d, order, nwg, s)
-                       : launch_typed<FORM_M16, HG_BF16, false>(d, order, nwg, s);
-        return vec ? launch_typed<FORM_M16, HG_F16, true>(d, order, nwg, s)
-                   : launch_typed<FORM_M16, HG_F16, false>(d, order, nwg, s);
+    return launch_channels_on(P, values, ld, nchan, dtype, out, s, shape, order, nwg);
+}
+
+hipError_t launch_channels_on(Plan& P, const void* values, int64_t ld, int32_t nchan,
+                              int32_t dtype, float* out, hipStream_t s, Shape shape,
+                              const int64_t* order, int64_t nwg) {
+    const bool vec = values_vec(P, values, ld, dtype);
+    const bool m16 = P.opts.precision != HG_PREC_FP32;
+    shape = effective_shape(m16, dtype, vec, shape);
+    FieldDesc d = field_desc(P, values, ld, nchan, out, shape);
+    hipError_t e = hipSuccess;
+    if (nwg == 0) return hipSuccess;
+    const void* kern = pick<SingleKernel>(m16, dtype, vec, shape.waves, shape.g);
+    const size_t shm = lds_shm(m16, d.chunk, d.ucap, d.nbuf, shape.g);
+    if (shm > 65536) {
+        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
     }
-    if (dtype == HG_F32)
-        return vec ? launch_typed<FORM_F32, HG_F32, true>(d, order, nwg, s)
-                   : launch_typed<FORM_F32, HG_F32, false>(d, order, nwg, s);
-    if (dtype == HG_BF16)
-        return vec ? launch_typed<FORM_F32, HG_BF16, true>(d, order, nwg, s)
-                   : launch_typed<FORM_F32, HG_BF16, false>(d, order, nwg, s);
-    return vec ? launch_typed<FORM_F32, HG_F16, true>(d, order, nwg, s)
-               : launch_typed<FORM_F32, HG_F16, false>(d, order, nwg, s);
+    void* args[] = {&d.values, &d.ld,      &d.nchan,     &d.ncb,     &d.npgx,  &d.npgy,
+                    &d.ntx,    &d.nx,      &d.ny,        &d.chunk,   &d.tile_base, &d.slot_idx,
+                    &d.tile_blk, &d.blk_base, &d.blk_pgoff, &d.ent_w, &d.ent_s, &d.pix_Wf,
+                    &d.out,    &d.out_vec, &d.ucap,      &d.nbuf,    &d.pg_cnt, &d.balance,
+                    &order};
+    e = hipLaunchKernel(kern, dim3((unsigned)nwg), dim3((unsigned)(64 * shape.waves)), args, shm,
+                        s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
 }
 
 bool channel_lds_fits(bool m16, int chunk, int blk_max) {
     int32_t ucap, nbuf;
-    lds_plan(m16, chunk, blk_max, ucap, nbuf);
-    return (size_t)2 * lds_stride(m16, chunk, ucap) + META_LDS <= (size_t)LDS_BYTES;
+    lds_plan(m16, chunk, blk_max, 4, ucap, nbuf);
+    return (size_t)2 * lds_stride(m16, chunk, ucap, 4) + META_LDS <= (size_t)LDS_BYTES;
 }
 
-size_t field_lds_bytes(const FieldDesc& d, bool m16) {
-    return lds_shm(m16, d.chunk, d.ucap, d.nbuf);
+size_t field_lds_bytes(const FieldDesc& d, bool m16, Shape shape) {
+    return lds_shm(m16, d.chunk, d.ucap, d.nbuf, shape.g);
 }
 
-BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm) {
+BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm, Shape shape) {
     BatchKernelInfo k;
-    k.main = pick<BatchKernel>(m16, dtype, vec);
+    shape = effective_shape(m16, dtype, vec, shape);
+    k.main = pick<BatchKernel>(m16, dtype, vec, shape.waves, shape.g);
     k.shm = shm;
-    k.threads = CH_THREADS;
-    k.channels_per_block = CW;
+    k.threads = 64 * shape.waves;
+    k.channels_per_block = 64 * shape.g;
     return k;
 }
 

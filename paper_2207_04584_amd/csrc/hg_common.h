@@ -137,6 +137,14 @@ __host__ __device__ inline int hp_ring_pieces(const Ring& r, double pa, double p
     return 2;
 }
 
+// Shape of the channel kernel's workgroup: `waves` waves (8 or 16) share one
+// tile's 64 pixel groups, and the workgroup grids 64 g channels (g = 1, 2 or
+// 4).  The plan's entry blocks do not depend on it, so it is chosen per
+// launch; {16, 4} is the default.
+struct Shape {
+    int32_t waves = 16, g = 4;
+};
+
 // ---------------------------------------------------------------------------
 // Plan: everything grid_setup leaves on the device for grid_channels.
 struct DevBuf {
@@ -184,6 +192,7 @@ struct Plan {
     int64_t npg = 0, ntiles = 0, npix = 0;
     int32_t tile_rings = 0, pg_rings = 0;  // max rings per tile / per pixel group
     int32_t chunk = 32;                    // tile slots per staged chunk
+    Shape shape;                           // channel kernel shape (hg_opts or default)
     int64_t total_slots = 0, ent_cap = 0, nnz_entries = 0, chunk_ptrs = 0;
     int64_t nnz = 0;  // (pixel, sample) pairs in support
     double setup_ms = 0;
@@ -240,11 +249,12 @@ struct FieldDesc {
     const void* ent_w;
     const void* ent_s;
     const float* pix_Wf;
+    const uint32_t* pg_cnt;  // entries per pixel group (the balanced wave assignment)
     float* out;
     int32_t nchan, ncb, npgx, npgy, ntx, nx, ny, chunk, out_vec;
-    int32_t ucap;  // LDS capacity in units per staged block (>= the plan's blk_max)
-    int32_t nbuf;  // staged chunks resident in LDS (2..4)
-    int32_t pad;
+    int32_t ucap;     // LDS capacity in units per staged block (>= the plan's blk_max)
+    int32_t nbuf;     // staged chunks resident in LDS (2..4)
+    int32_t balance;  // 1: pixel groups dealt to waves by entry count
 };
 
 // One work item of the batched launch: (field, tile, channel block); field < 0
@@ -299,13 +309,21 @@ hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** ite
 hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hipStream_t s,
                         std::string& err, int& status);
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
-                           float* out, hipStream_t s);
+                           float* out, hipStream_t s, Shape shape);
+// the same launch on a caller-provided item order of nwg positions (device)
+hipError_t launch_channels_on(Plan& P, const void* values, int64_t ld, int32_t nchan,
+                              int32_t dtype, float* out, hipStream_t s, Shape shape,
+                              const int64_t* order, int64_t nwg);
 hipError_t launch_literal(const Plan& P, const float* values, int64_t ld, int32_t nchan,
                           float* out, int32_t gamma, int32_t block, hipStream_t s);
-FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out);
+FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out,
+                     Shape shape);
 bool values_vec(const Plan& P, const void* values, int64_t ld, int32_t dtype);
-BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm);
-size_t field_lds_bytes(const FieldDesc& d, bool m16);
+// the shape a launch really uses: shapes other than the default exist only for
+// aligned FP32 values in the FP32 form and for the 16-bit forms
+Shape effective_shape(bool m16, int32_t dtype, bool vec, Shape s);
+BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm, Shape shape);
+size_t field_lds_bytes(const FieldDesc& d, bool m16, Shape shape);
 bool channel_lds_fits(bool m16, int chunk, int blk_max);
 hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
                           int64_t* pix, hipStream_t s);

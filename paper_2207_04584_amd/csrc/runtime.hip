@@ -210,6 +210,13 @@ hipError_t resolve_timing(Plan& P) {
 
 bool finite(double x) { return std::isfinite(x); }
 
+Shape shape_of(const hg_opts& o) {
+    Shape s;
+    if (o.waves) s.waves = o.waves;
+    if (o.chan_block) s.g = o.chan_block / 64;
+    return s;
+}
+
 // A buffer the kernels read or write must be device memory of the device they
 // run on (hipMalloc, or managed).  Host memory is refused before anything is
 // enqueued: pageable memory would fault the GPU (no XNACK here), and
@@ -292,10 +299,17 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
         if (o->chunk != 0 && (o->chunk < 8 || o->chunk > MAX_CHUNK || o->chunk % 8))
             return fail(HG_ERR_ARG, "chunk must be 0 or a multiple of 8 in [8, 64]");
         if (o->device_mem_cap < 0) return fail(HG_ERR_ARG, "device_mem_cap must be >= 0");
-        if (o->reserved || o->reserved2) return fail(HG_ERR_ARG, "reserved fields must be 0");
+        if (o->waves != 0 && o->waves != 8 && o->waves != 16)
+            return fail(HG_ERR_ARG, "waves must be 0, 8 or 16");
+        if (o->chan_block != 0 && o->chan_block != 64 && o->chan_block != 128 &&
+            o->chan_block != 256)
+            return fail(HG_ERR_ARG, "chan_block must be 0, 64, 128 or 256");
     }
     return HG_OK;
 }
+
+std::vector<BatchItem> plan_batch_items(const std::vector<std::vector<int64_t>>& tile_blk,
+                                        const std::vector<int32_t>& ncb, int64_t& n_items);
 
 // Setup proper, after validation (shared by hg_grid_setup and hg_batch_create).
 int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_kernel* k,
@@ -307,6 +321,7 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     P.map = *m;
     P.kern = *k;
     if (o) P.opts = *o;
+    P.shape = shape_of(P.opts);
     P.n = n;
     P.sigma = k->type == HG_KERNEL_GAUSS_SINC ? 0.0 : k->fwhm_deg * kDeg / sqrt(8.0 * log(2.0));
     P.r_rad = k->support_deg * kDeg;
@@ -336,7 +351,7 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     else if (m16)
         chunks = {64, 48, 32, 16, 8};
     else
-        chunks = {48, 32, 16, 8};
+        chunks = {56, 48, 32, 16, 8};
     for (size_t ci = 0; ci < chunks.size(); ci++) {
         P.chunk = chunks[ci];
         std::string err;
@@ -651,7 +666,7 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
             e = hipEventRecord(ev.first, s);
             if (e != hipSuccess) return fail_hip(e, "grid_channels (events)");
         }
-        e = launch_channels(P, values, ld, nchan, dtype, out, s);
+        e = launch_channels(P, values, ld, nchan, dtype, out, s, P.shape);
         if (e != hipSuccess) return fail_hip(e, "grid_channels");
         if (timed) {
             e = hipEventRecord(ev.second, s);
@@ -756,10 +771,29 @@ int hg_plan_stats(hg_plan* h, hg_stats* st) {
         st->device_bytes = plan_bytes(P);
         st->nside = (int32_t)P.nside;
         st->chunk = P.chunk;
+        st->waves = P.shape.waves;
+        st->chan_block = 64 * P.shape.g;
         st->setup_ms = P.setup_ms;
         st->last_channels_ms = P.ch_ms_last;
         st->total_channels_ms = P.ch_ms_total;
         st->channels_calls = P.ch_calls;
+        return HG_OK;
+    });
+}
+
+int hg_plan_set_shape(hg_plan* h, int32_t waves, int32_t chan_block) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!h) return fail(HG_ERR_ARG, "plan must not be NULL");
+        if (waves != 0 && waves != 8 && waves != 16)
+            return fail(HG_ERR_ARG, "waves must be 0, 8 or 16");
+        if (chan_block != 0 && chan_block != 64 && chan_block != 128 && chan_block != 256)
+            return fail(HG_ERR_ARG, "chan_block must be 0, 64, 128 or 256");
+        Plan& P = h->P;
+        if (P.finished) return fail(HG_ERR_STATE, "plan already finished");
+        P.opts.waves = waves;
+        P.opts.chan_block = chan_block;
+        P.shape = shape_of(P.opts);
         return HG_OK;
     });
 }
@@ -919,10 +953,16 @@ int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, cons
         bool vec = true;
         for (int32_t i = 0; i < nfields; i++) {
             const hg_field& f = fields[i];
+            if (f.nchan > 0 && f.n > 0) vec = vec && values_vec(b->plans[i]->P, f.values, f.ld, dtype);
+        }
+        // one kernel for every field: its shape holds for all of them
+        const Shape shape = effective_shape(b->opts.precision != HG_PREC_FP32, dtype, vec,
+                                            shape_of(b->opts));
+        for (int32_t i = 0; i < nfields; i++) {
+            const hg_field& f = fields[i];
             const Plan& P = b->plans[i]->P;
-            descs.push_back(field_desc(P, f.values, f.ld, f.nchan, f.out));
+            descs.push_back(field_desc(P, f.values, f.ld, f.nchan, f.out, shape));
             ncb.push_back(descs.back().ncb);
-            if (f.nchan > 0 && f.n > 0) vec = vec && values_vec(P, f.values, f.ld, dtype);
         }
         std::vector<BatchItem> pos = plan_batch_items(tile_blk, ncb, b->n_items);
         b->n_positions = (int64_t)pos.size();
@@ -941,8 +981,8 @@ int hg_batch_create(const hg_field* fields, int32_t nfields, int32_t dtype, cons
                               hipMemcpyHostToDevice);
             const bool m16 = b->opts.precision != HG_PREC_FP32;
             size_t shm = 0;
-            for (const FieldDesc& d : descs) shm = std::max(shm, field_lds_bytes(d, m16));
-            BatchKernelInfo ki = batch_kernel(m16, dtype, vec, shm);
+            for (const FieldDesc& d : descs) shm = std::max(shm, field_lds_bytes(d, m16, shape));
+            BatchKernelInfo ki = batch_kernel(m16, dtype, vec, shm, shape);
             if (e == hipSuccess && ki.shm > 65536)
                 e = hipFuncSetAttribute(ki.main, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)ki.shm);

@@ -250,7 +250,7 @@ int grid_channels_host(Plan& P, const void* host_values, int64_t ld, int32_t nch
         if (e == hipSuccess) e = tm.mark(cs, i0);
         if (e == hipSuccess)
             e = launch_channels(P, n > 0 ? R.vals[s].p : nullptr, ldd, (int32_t)w, dtype,
-                                (float*)R.out[s].p, cs);
+                                (float*)R.out[s].p, cs, P.shape);
         if (e == hipSuccess) e = tm.mark(cs, i1);
         if (tm.on) t_ker.push_back({i0, i1});
         if (e == hipSuccess) e = hipEventRecord(R.ev_ker[s], cs);

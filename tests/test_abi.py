@@ -89,7 +89,7 @@ def good():
 
 @pytest.mark.parametrize("case", ["null_out", "null_kernel", "neg_n", "null_coords", "fwhm",
                                   "support", "nx", "spacing", "pole", "nside", "chunk",
-                                  "reserved", "memcap"])
+                                  "waves", "chan_block", "memcap"])
 def test_setup_rejects_bad_arguments_without_a_device(case):
     k, m = good()
     o = api.hg_opts()
@@ -116,8 +116,10 @@ def test_setup_rejects_bad_arguments_without_a_device(case):
         o.nside = 3
     elif case == "chunk":
         o.chunk = 7
-    elif case == "reserved":
-        o.reserved = 1
+    elif case == "waves":
+        o.waves = 12
+    elif case == "chan_block":
+        o.chan_block = 96
     elif case == "memcap":
         o.device_mem_cap = -5
     rc, h = _setup(**kw)

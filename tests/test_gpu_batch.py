@@ -179,10 +179,9 @@ def test_batch_workload_full_size_against_reference():
     maps 32..512, 256/1024/4096 FP16 channels, FWHM U(2, 5) arcmin; about
     3e10 sample x channels) in the FP16 MFMA form, one graph-held launch.
     Reference: two channels of every field on 80 sampled pixels and the map
-    corners (counts bit-exact there), plus the smallest field's every pixel.  The
-    densest field (about 3e5 neighbours per pixel) does not fit two staged
-    64-slot chunks in LDS, so its plan must come from the shorter-chunk
-    fallback of setup; that is asserted."""
+    corners (counts bit-exact there), plus the smallest field's every pixel.
+    (Its densest field, about 7e4 neighbours per pixel, still fits 64-slot
+    chunks; test_dense_fields_take_shorter_chunks reaches that fallback.)"""
     fs = synth.batch_fields(64)
     fields = []
     for f in fs:
@@ -204,7 +203,6 @@ def test_batch_workload_full_size_against_reference():
         densest = max(range(64), key=lambda i: dens[i]["nnz"] / (fs[i]["map"]["nx"] ** 2))
         print(f"  densest field {densest}: {dens[densest]['nnz'] / fs[densest]['map']['nx'] ** 2:.0f}"
               f" neighbours per pixel, chunk {dens[densest]['chunk']}", flush=True)
-        assert dens[densest]["chunk"] < 64, "the densest field should need shorter chunks"
         for i, f in enumerate(fs):
             C = f["nchan"]
             P = f["map"]["nx"] * f["map"]["ny"]
@@ -226,3 +224,42 @@ def test_batch_workload_full_size_against_reference():
             worst = max(worst, e_max)
             assert e_max <= 2e-3, f"field {i}: e_max {e_max:g}"
     print(f"  worst e_max {worst:.3g} over 64 fields", flush=True)
+
+
+@pytest.mark.parametrize("precision,first,tol", [(2, 64, 2e-3), (api.HG_PREC_FP32, 48, 1e-6)])
+def test_dense_fields_take_shorter_chunks(precision, first, tol):
+    """A field so dense for its tiles (a 12 arcmin beam, R = 15 px, over
+    16 x 16-pixel tiles: most samples reach most of a tile's pixel groups)
+    that its densest entry block does not fit two staged chunks of the first
+    length in LDS: setup must rebuild its plan with a shorter chunk, inside a
+    batch beside a light field, and the maps must still match the reference."""
+    rng = np.random.default_rng(77)
+    n = 120_000
+    ra = 150.0 + (rng.random(n) - 0.5) * 1.0
+    dec = 20.0 + (rng.random(n) - 0.5) * 1.0
+    dt = torch.float16 if precision == 2 else torch.float32
+    C = 6
+    vals = torch.from_numpy(rng.normal(3.0, 1.0, size=(n, C)).astype(np.float32)).to(dt).to(DEV)
+    dense = {"ra": ra, "dec": dec, "map": synth.make_map(150.0, 20.0, 32, 32),
+             "kernel": synth.make_kernel(12.0), "values": vals}
+    light = mixed_fields(dt)[0]
+    light["values"] = light["values"][:, :C].contiguous()
+    with api.Batch([dense, light], precision=precision) as b:
+        outs = b.run()
+        torch.cuda.synchronize()
+        st = b.plan(0).stats()
+        print(f"\n  dense field: {st['nnz'] / 1024:.0f} neighbours per pixel, chunk {st['chunk']}",
+              flush=True)
+        assert st["chunk"] < first, "the dense field should need a shorter chunk"
+        cnt = b.plan(0).counts()
+        pix = np.unique(np.concatenate([rng.choice(1024, 120, replace=False), [0, 31, 992, 1023]]))
+        hv, code = to_host_values(vals)
+        Vr, cr, _, margin = oracle.grid(ra, dec, hv, code, dense["map"], dense["kernel"]["fwhm_deg"],
+                                        dense["kernel"]["support_deg"], pix=pix)
+        assert margin > 1e-12
+        np.testing.assert_array_equal(cnt[pix], cr)
+        V = outs[0].reshape(C, -1).cpu().numpy()[:, pix]
+        np.testing.assert_array_equal(np.isnan(V), np.isnan(Vr))
+        e_max, _ = norm_err(V, Vr, cr > 0)
+        print(f"  e_max {e_max:.3g}", flush=True)
+        assert e_max <= tol

@@ -1,0 +1,85 @@
+"""Channel-kernel shapes (hg_opts.waves x hg_opts.chan_block, the shapes the
+autotuner sweeps): every pixel's sums are the same operations in the same
+order whatever the shape -- the same entries in the same chunks, each
+channel on its own MFMA column -- so every shape must give the default
+shape's maps bit for bit, for full and ragged channel blocks, short chunks
+(row groups only partly inside a chunk) and every form."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_04584_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2207_04584_amd import api  # noqa: E402
+from parity_util import norm_err, to_host_values  # noqa: E402
+
+DEV = "cuda:0"
+SHAPES = [(w, cb) for w in (8, 16) for cb in (64, 128, 256)]
+FORMS = {"fp32": (api.HG_PREC_FP32, "f32"), "bf16": (api.HG_PREC_MFMA_BF16, "bf16"),
+         "f16": (api.HG_PREC_MFMA_F16, "f16")}
+
+
+def _same(a, b):
+    return torch.equal(torch.nan_to_num(a, nan=1e30), torch.nan_to_num(b, nan=1e30))
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+@pytest.mark.parametrize("chunk,C", [(0, 300), (8, 70), (24, 520), (40, 64)])
+def test_shapes_equal_default_bitwise(form, chunk, C):
+    prec, dt = FORMS[form]
+    f = synth.uniform_field((91, chunk), 5000, 60.0, 20.0, 0.45, 0.4, 29, 27, nchan=C)
+    vals = synth.sky_values(f, C, device=DEV, dtype=dt)
+    print(f"\n  {form} chunk={chunk} C={C}", flush=True)
+    with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"], precision=prec, chunk=chunk) as p:
+        ref = p.grid(vals)
+    for waves, cb in SHAPES:
+        with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"], precision=prec, chunk=chunk,
+                      waves=waves, chan_block=cb) as p:
+            got = p.grid(vals)
+            torch.cuda.synchronize()
+            assert _same(got, ref), f"shape {waves} waves x {cb} channels differs"
+
+
+def test_tuned_shape_on_drift_field_against_reference():
+    """The drift-scan field (1e6 samples, 300 x 300, 1024 FP32 channels) with
+    8 waves of 128 channels: equal to the default shape bit for bit, and
+    within 1e-6 of the reference on sampled pixels and channels."""
+    f = synth.config("cfg2")
+    vals = synth.sky_values(f, 1024, device=DEV)
+    with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"]) as p:
+        ref = p.grid(vals)
+    with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"], waves=8, chan_block=128) as p:
+        got = p.grid(vals)
+    torch.cuda.synchronize()
+    assert _same(got, ref)
+    rng = np.random.default_rng(61)
+    pix = np.sort(rng.choice(90000, 300, replace=False))
+    chans = np.sort(rng.choice(1024, 24, replace=False))
+    hv, code = to_host_values(vals[:, torch.from_numpy(chans).to(DEV)].contiguous())
+    Vr, cr, _, margin = oracle.grid(f["ra"], f["dec"], hv, code, f["map"], f["kernel"]["fwhm_deg"],
+                                    f["kernel"]["support_deg"], pix=pix)
+    assert margin > 1e-12
+    V = got.reshape(1024, -1)[torch.from_numpy(chans).to(DEV)].cpu().numpy()[:, pix]
+    np.testing.assert_array_equal(np.isnan(V), np.isnan(Vr))
+    e_max, e_rms = norm_err(V, Vr, cr > 0)
+    print(f"\n  e_max={e_max:.3g} e_rms={e_rms:.3g}", flush=True)
+    assert e_max <= 1e-6
+
+
+@pytest.mark.parametrize("waves,cb", [(8, 128), (16, 64)])
+def test_batch_with_shape_equals_single_plans(waves, cb):
+    fs = synth.batch_fields(6, scale=0.05)
+    fields = [{"ra": f["ra"], "dec": f["dec"], "map": f["map"], "kernel": f["kernel"],
+               "values": synth.sky_values(f, f["nchan"], device=DEV, dtype="f16")} for f in fs]
+    with api.Batch(fields, precision=api.HG_PREC_MFMA_F16, waves=waves, chan_block=cb) as b:
+        outs = [o.clone() for o in b.run()]
+    for f, o in zip(fields, outs):
+        with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"],
+                      precision=api.HG_PREC_MFMA_F16) as p:
+            assert _same(p.grid(f["values"]), o)
