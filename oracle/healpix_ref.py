@@ -17,10 +17,12 @@ by the HEGrid paper in Sec. 4.1.1):
   * pixels are numbered ring by ring from the north pole, by increasing
     azimuth within a ring.
 
-ang2pix inverts that layout: in the belt the pixel edges are the lines
-nside (phi / (pi/2) + 1/2) -+ (3/4) nside z = const, in the caps the edges are
-the curves of constant  nside sqrt(3 (1 - |z|)) * t  and
-nside sqrt(3 (1 - |z|)) * (1 - t), t the azimuth fraction inside a base pixel.
+ang2pix inverts that layout by search, not by a closed formula: in the HEALPix
+projection (Calabretta & Roukema 2007, "Mapping on the HEALPix grid") every
+pixel is the same diamond about its projected centre, so the pixel holding a
+point is its nearest centre in the L1 metric of that plane, found among a few
+candidates from pix2ang.  The library's binning inverts the same layout by the
+closed formula of its edge lines; the two share no steps.
 """
 import numpy as np
 
@@ -78,39 +80,65 @@ def pix2ang(nside, pix):
     return z, phi
 
 
-def ang2pix(nside, z, phi):
-    """RING pixel containing the direction (z = cos theta, phi)."""
-    n = nside
-    z = np.asarray(z, dtype=np.float64)
-    phi = np.mod(np.asarray(phi, dtype=np.float64), 2.0 * np.pi)
-    tt = phi / (0.5 * np.pi)  # in [0, 4)
-    tt = np.where(tt >= 4.0, 0.0, tt)
+def _project(nside, z, phi, quad):
+    """HEALPix projection (Calabretta & Roukema 2007) in units where every
+    pixel is the diamond |X - Xc| + |Y - Yc| <= 1/2: X = 2 nside x / pi,
+    Y = 2 nside y / pi.  Belt (|z| <= 2/3): x = phi, y = (3 pi / 8) z.  Caps:
+    sigma = sqrt(3 (1 - |z|)), x = phi_c + (phi - phi_c) sigma,
+    y = +-(pi / 4)(2 - sigma), phi_c the centre of azimuth quadrant `quad`."""
+    n = float(nside)
     za = np.abs(z)
-    out = np.empty(z.shape, dtype=np.int64)
+    sig = np.sqrt(np.maximum(3.0 * (1.0 - za), 0.0))
+    phic = (quad + 0.5) * (0.5 * np.pi)
+    cap = za > 2.0 / 3.0
+    x = np.where(cap, phic + (phi - phic) * sig, phi)
+    y = np.where(cap, np.sign(z) * (0.25 * np.pi) * (2.0 - sig), (3.0 * np.pi / 8.0) * z)
+    return x * (2.0 * n / np.pi), y * (2.0 * n / np.pi)
 
-    belt = za <= 2.0 / 3.0
-    if belt.any():
-        t1 = n * (0.5 + tt[belt])
-        t2 = n * z[belt] * 0.75
-        jp = np.floor(t1 - t2).astype(np.int64)  # ascending edge index
-        jm = np.floor(t1 + t2).astype(np.int64)  # descending edge index
-        ir = n + 1 + jp - jm  # 1 .. 2n+1, counted from the z = 2/3 ring
-        kshift = 1 - (ir & 1)
-        ip = (jp + jm - n + kshift + 1) // 2
-        ip = np.mod(ip, 4 * n)
-        out[belt] = 2 * n * (n - 1) + (ir - 1) * 4 * n + ip
 
-    cap = ~belt
-    if cap.any():
-        tc = tt[cap]
-        tp = tc - np.floor(tc)
-        tmp = n * np.sqrt(3.0 * (1.0 - za[cap]))
-        jp = np.floor(tp * tmp).astype(np.int64)
-        jm = np.floor((1.0 - tp) * tmp).astype(np.int64)
-        ir = jp + jm + 1  # ring counted from the nearer pole
-        ip = np.floor(tc * ir).astype(np.int64)
-        ip = np.mod(ip, 4 * ir)
-        out[cap] = np.where(z[cap] > 0, 2 * ir * (ir - 1) + ip, npix(n) - 2 * ir * (ir + 1) + ip)
+def ang2pix(nside, z, phi):
+    """RING pixel containing the direction (z = cos theta, phi).
+
+    Inverted by search rather than by a closed formula: in the HEALPix
+    projection plane every pixel is a diamond of half-diagonal 1/2 about its
+    projected centre, so the diamond lattice is the Voronoi partition of the
+    centres in the L1 metric and the containing pixel is the L1-nearest
+    centre.  Candidates are three rings about the point's projected Y (ring i
+    sits at Y = nside - i/2) times three pixels about its azimuth in each
+    ring, their centres taken from pix2ang (the layout).  A polar-cap chart
+    holds only its own azimuth quadrant, so cap pixels of another quadrant
+    than the point's are not candidates; a point's X distance wraps with
+    period 4 nside."""
+    n = nside
+    z = np.asarray(z, dtype=np.float64).ravel()
+    phi = np.mod(np.asarray(phi, dtype=np.float64).ravel(), 2.0 * np.pi)
+    quad = np.minimum(np.floor(phi / (0.5 * np.pi)), 3.0)
+    X, Y = _project(n, z, phi, quad)
+    i0 = np.rint(2.0 * (n - Y)).astype(np.int64)
+    best = np.full(z.shape, np.inf)
+    out = np.full(z.shape, -1, dtype=np.int64)
+    ncap = 2 * n * (n - 1)
+    for di in (-1, 0, 1):
+        i = np.clip(i0 + di, 1, 4 * n - 1)
+        kk = np.minimum(np.minimum(i, 4 * n - i), n)  # pixels per ring / 4
+        nr = 4 * kk
+        first = np.where(i < n, 2 * i * (i - 1),
+                         np.where(i <= 3 * n, ncap + (i - n) * 4 * n, npix(n) - 2 * kk * (kk + 1)))
+        shift = np.where((i >= n) & (i <= 3 * n), (i - n + 1) % 2, 1)
+        # pixel whose centre azimuth (k + shift/2) 2 pi / nr is nearest phi
+        k0 = np.rint(phi * nr / (2.0 * np.pi) - 0.5 * shift).astype(np.int64)
+        for dk in (-1, 0, 1):
+            p = first + np.mod(k0 + dk, nr)
+            zc, pc = pix2ang(n, p)
+            qc = np.minimum(np.floor(pc / (0.5 * np.pi)), 3.0)
+            cap_c = np.abs(zc) > 2.0 / 3.0 + 1e-15
+            Xc, Yc = _project(n, zc, pc, quad)
+            dX = np.mod(X - Xc + 2.0 * n, 4.0 * n) - 2.0 * n
+            d = np.abs(dX) + np.abs(Y - Yc)
+            d = np.where(cap_c & (qc != quad), np.inf, d)
+            take = d < best
+            best = np.where(take, d, best)
+            out = np.where(take, p, out)
     return out
 
 
