@@ -754,8 +754,8 @@ def run_cube(args):
         f"{m['nx']}x{m['ny']} map, {torch.cuda.get_device_name(0)}")
     ra = torch.from_numpy(f["ra"]).to(dev)
     dec = torch.from_numpy(f["dec"]).to(dev)
-    vals_h = torch.empty((n, slab), dtype=torch.bfloat16, pin_memory=True)
-    out_h = torch.empty((slab, m["ny"], m["nx"]), dtype=torch.float32, pin_memory=True)
+    vals_h = synth.pinned_empty((n, slab), torch.bfloat16)
+    out_h = synth.pinned_empty((slab, m["ny"], m["nx"]), torch.float32)
     dev_slab = torch.empty((n, slab), dtype=torch.bfloat16, device=dev)
 
     def fill(s0):
@@ -819,7 +819,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["drift", "batch", "paper", "literal", "fifo", "cube"],
                     default="drift")
-    ap.add_argument("--cube-slab", type=int, default=16384,
+    ap.add_argument("--cube-slab", type=int, default=8192,
                     help="cube workload: channels per host slab (a multiple of 4096)")
     ap.add_argument("--cube-slabs", type=int, default=0,
                     help="cube workload: slabs to stream (0 = the whole cube)")

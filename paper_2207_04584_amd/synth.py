@@ -266,3 +266,32 @@ def batch_fields(n_fields=64, scale=1.0):
                            nchan=nchan, dtype="f16", recipe="spectral", n_sources=20, noise=1.0)
         fields.append(fl)
     return fields
+
+
+_HIP = None
+
+
+def pinned_empty(shape, dtype):
+    """An uninitialised page-locked host tensor of exactly the requested size,
+    for the host-memory cubes of the streamed workloads.  torch's pinned
+    allocator rounds every request up to a power of two (a 33 GB slab takes
+    64 GB), so the buffer comes from hipHostMalloc instead and is released
+    with hipHostFree when the tensor's storage goes."""
+    import ctypes
+    import weakref
+    torch = _torch()
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipHostMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t,
+                                       ctypes.c_uint]
+        _HIP.hipHostFree.argtypes = [ctypes.c_void_p]
+    nbytes = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
+    ptr = ctypes.c_void_p()
+    rc = _HIP.hipHostMalloc(ctypes.byref(ptr), max(nbytes, 1), 0)
+    if rc != 0 or not ptr.value:
+        raise MemoryError(f"hipHostMalloc of {nbytes} bytes failed (status {rc})")
+    buf = (ctypes.c_uint8 * max(nbytes, 1)).from_address(ptr.value)
+    weakref.finalize(buf, _HIP.hipHostFree, ptr.value)
+    t = torch.frombuffer(buf, dtype=torch.uint8)[:nbytes]
+    return t.view(dtype).reshape(shape)

@@ -25,7 +25,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2207_04584_amd import api  # noqa: E402
-from parity_util import norm_err, to_host_values  # noqa: E402
+from parity_util import abs_values, assert_fp32_bound, norm_err, to_host_values  # noqa: E402
 
 ARC = 1.0 / 60.0
 DEV = "cuda:0"
@@ -226,13 +226,18 @@ def test_batch_workload_full_size_against_reference():
     print(f"  worst e_max {worst:.3g} over 64 fields", flush=True)
 
 
-@pytest.mark.parametrize("precision,first,tol", [(2, 64, 2e-3), (api.HG_PREC_FP32, 48, 1e-6)])
+@pytest.mark.parametrize("precision,first,tol", [(2, 64, 2e-3), (api.HG_PREC_FP32, 48, None)])
 def test_dense_fields_take_shorter_chunks(precision, first, tol):
     """A field so dense for its tiles (a 12 arcmin beam, R = 15 px, over
     16 x 16-pixel tiles: most samples reach most of a tile's pixel groups)
     that its densest entry block does not fit two staged chunks of the first
     length in LDS: setup must rebuild its plan with a shorter chunk, inside a
-    batch beside a light field, and the maps must still match the reference."""
+    batch beside a light field, and the maps must still match the reference.
+    With about 26,000 neighbours per pixel, FP32 summation in any order errs
+    by up to gamma_K (K = 26,000: 1.5e-3) of the summed terms, so the FP32
+    form is held to that rounding bound cell by cell (the 1e-6 gate applies
+    to the workloads with a few hundred neighbours per pixel); the 16-bit
+    form keeps its 2e-3 gate."""
     rng = np.random.default_rng(77)
     n = 120_000
     ra = 150.0 + (rng.random(n) - 0.5) * 1.0
@@ -262,4 +267,10 @@ def test_dense_fields_take_shorter_chunks(precision, first, tol):
         np.testing.assert_array_equal(np.isnan(V), np.isnan(Vr))
         e_max, _ = norm_err(V, Vr, cr > 0)
         print(f"  e_max {e_max:.3g}", flush=True)
-        assert e_max <= tol
+        if tol is None:
+            Vabs = oracle.grid(ra, dec, abs_values(hv, code), code, dense["map"],
+                               dense["kernel"]["fwhm_deg"], dense["kernel"]["support_deg"],
+                               pix=pix)[0]
+            assert_fp32_bound(V, Vr, Vabs, cr)
+        else:
+            assert e_max <= tol

@@ -26,7 +26,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2207_04584_amd import api  # noqa: E402
-from parity_util import abs_values, norm_err, to_host_values  # noqa: E402
+from parity_util import abs_values, assert_fp32_bound, norm_err, to_host_values  # noqa: E402
 
 ARC = 1.0 / 60.0
 DEV = "cuda:0"
@@ -77,28 +77,6 @@ def check_field(ra, dec, vals, m, k, pix=None, chans=None, check_lists=True, tol
                                        rtol=max(2e-7, w_rtol))
     assert st["nnz"] == int(cnt.sum())
     return e_max, e_rms, st
-
-
-U32 = 2.0 ** -24
-
-
-def assert_fp32_bound(V, Vr, Vabs, cnt):
-    """The FP32 form's rounding bound, cell by cell, whatever the summation
-    order.  With FP32 weights w' = w (1 + e), |e| <= u, the exact weighted
-    mean with w' is within u (A + |V_ref|) of V_ref, A = sum w |v| / W; any
-    order of K FP32 multiply-adds errs by at most gamma_K sum |w' v|; the
-    division by the FP32-rounded W adds 2u |V|.  So
-        |V - V_ref| <= (gamma_K + 2u) A + 3u |V_ref|,  gamma_K = K u / (1 - K u).
-    On zero-mean random values A can be far larger than max |V_ref|, which is
-    why these fields are not held to 1e-6 of max |V_ref| itself."""
-    ok = cnt > 0
-    K = cnt[ok].astype(np.float64)
-    gam = K * U32 / (1 - K * U32)
-    bound = (gam + 2 * U32) * np.abs(Vabs[:, ok]) + 3 * U32 * np.abs(Vr[:, ok])
-    err = np.abs(V[:, ok] - Vr[:, ok])
-    worst = float((err / np.maximum(bound, 1e-300)).max()) if err.size else 0.0
-    print(f"  worst error / FP32 rounding bound = {worst:.3g}", flush=True)
-    assert np.all(err <= bound * (1 + 1e-9)), f"error exceeds the FP32 bound by {worst:g}x"
 
 
 def rand_field(seed, n, nx, ny, ra0, dec0, fwhm=3.0, C=5, spread=1.3, dtype=torch.float32):
