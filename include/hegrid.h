@@ -240,6 +240,32 @@ int hg_grid_channels_host(hg_plan* p, const void* host_values, int64_t ld, int32
                           hg_stream_info* info);
 
 /*
+ * hg_grid_channels_host for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: serving loops, harnesses that forbid it).  It
+ * allocates nothing: the two device slots of values and maps live in one
+ * fixed staging array of HG_NOALLOC_STAGING_BYTES that the library holds on
+ * every device it runs on until the process ends; the two copy streams and
+ * their events are made on the first call on a device and kept.
+ *   host_values, host_out: as for hg_grid_channels_host, but both must be
+ *     page-locked (hipHostMalloc or torch pin_memory); pageable buffers are
+ *     refused with HG_ERR_ARG (staging them would need pinned memory).
+ *   block: channels per block; 0 picks the widest block (at most 4096) whose
+ *     two value slots (n x block) and two map slots (block x ny x nx, FP32)
+ *     fit the array.  A block that does not fit is refused with HG_ERR_ARG,
+ *     before anything is enqueued.
+ *   The maps equal hg_grid_channels_host's (the same kernels and per-cell
+ *   operations).  Synchronous.  info receives the block count, bytes moved
+ *   and the wall time; its device times stay 0 (timing would make events).
+ *   Every call on a device shares that device's array and streams: calls
+ *   that overlap on one device race, so serialise them.
+ */
+#define HG_NOALLOC_STAGING_BYTES (256u << 20) /* bytes of the staging array per device */
+
+int hg_grid_channels_host_noalloc(hg_plan* p, const void* host_values, int64_t ld,
+                                  int32_t nchan, int32_t dtype, float* host_out, int32_t block,
+                                  void* hip_stream, hg_stream_info* info);
+
+/*
  * Algorithm 1 as the paper states it (Sec. 4.1.2, Fig. 7, with the cells per
  * thread of Sec. 4.3.3), a comparison path beside hg_grid_channels on the same
  * plan: one launch per channel; one thread per gamma output cells of one 2x2

@@ -23,7 +23,8 @@ ABI_FUNCTIONS = ("hg_grid_setup", "hg_grid_channels", "hg_grid_finish", "hg_plan
                  "hg_plan_counts", "hg_plan_weight_sums", "hg_plan_neighbours",
                  "hg_ang2pix_ring", "hg_grid_channels_host", "hg_grid_channels_literal",
                  "hg_batch_create", "hg_batch_run", "hg_batch_destroy", "hg_batch_stats",
-                 "hg_batch_plan", "hg_map_pixel_ids", "hg_plan_set_shape", "hg_last_error")
+                 "hg_batch_plan", "hg_map_pixel_ids", "hg_plan_set_shape", "hg_last_error",
+                 "hg_grid_channels_host_noalloc")
 
 
 class HegridError(RuntimeError):
@@ -120,6 +121,8 @@ def lib():
     L.hg_map_pixel_ids.argtypes = [ctypes.POINTER(hg_map), P]
     L.hg_grid_channels_host.argtypes = [P, P, i64, i32, i32, P, i32, P,
                                         ctypes.POINTER(hg_stream_info)]
+    L.hg_grid_channels_host_noalloc.argtypes = [P, P, i64, i32, i32, P, i32, P,
+                                                ctypes.POINTER(hg_stream_info)]
     L.hg_batch_create.argtypes = [ctypes.POINTER(hg_field), i32, i32, ctypes.POINTER(hg_opts), P,
                                   ctypes.POINTER(ctypes.c_void_p)]
     L.hg_batch_run.argtypes = [P, P]
@@ -279,6 +282,33 @@ class Plan:
                                          ctypes.c_void_p(out.data_ptr()), int(block),
                                          _stream_ptr(stream), ctypes.byref(info))
         _check(rc, "hg_grid_channels_host")
+        return out, {f: getattr(info, f) for f, _ in hg_stream_info._fields_}
+
+    def grid_host_noalloc(self, values, out, block=0, stream=None):
+        """hg_grid_channels_host_noalloc: as grid_host, through the library's
+        fixed per-device staging array (no device allocation).  values and
+        out must be page-locked host tensors (out float32 [C][ny][nx]);
+        returns (out, info)."""
+        torch = _torch()
+        if values.dim() == 1:
+            values = values.reshape(-1, 1)
+        if values.device.type != "cpu" or values.shape[0] != self.n or (
+                self.n > 0 and values.stride(1) != 1):
+            raise HegridError(HG_ERR_ARG, "values must be a host tensor [n][C] with unit "
+                              "channel stride")
+        nchan = values.shape[1]
+        ld = values.stride(0) if values.shape[0] > 1 else nchan
+        ny, nx = self.shape
+        if (out.dtype != torch.float32 or out.device.type != "cpu" or not out.is_contiguous()
+                or out.numel() != nchan * ny * nx):
+            raise HegridError(HG_ERR_ARG, "out must be a contiguous float32 host tensor "
+                              "[C][ny][nx]")
+        info = hg_stream_info()
+        rc = lib().hg_grid_channels_host_noalloc(
+            self._handle(), ctypes.c_void_p(values.data_ptr() if self.n else 0), ld, nchan,
+            _dtype_code(values), ctypes.c_void_p(out.data_ptr()), int(block),
+            _stream_ptr(stream), ctypes.byref(info))
+        _check(rc, "hg_grid_channels_host_noalloc")
         return out, {f: getattr(info, f) for f, _ in hg_stream_info._fields_}
 
     def grid_literal(self, values, out=None, gamma=4, block=256, stream=None):

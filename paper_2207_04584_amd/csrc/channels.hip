@@ -775,8 +775,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_channels(
     // Workgroup b takes the plan's item order[b] (tile * ncb + channel block),
     // laid out as for the batched form: a tile's channel blocks on one XCD,
     // tiles placed longest first over the XCDs, each XCD's items by decreasing
-    // cost; -1 marks an idle workgroup.
-    const int64_t item = order[blockIdx.x];
+    // cost; -1 marks an idle workgroup.  Without an order (NULL), workgroup b
+    // takes item b.
+    const int64_t item = order ? order[blockIdx.x] : (int64_t)blockIdx.x;
     if (item < 0) return;
     grid_item<FORM, DT, VEC, WAVES, G>(values, ld, nchan, npgx, npgy, ntx, nx, ny, chunk,
                                        tile_base, slot_idx, tile_blk, blk_base, blk_pgoff, ent_w,
@@ -968,6 +969,16 @@ hipError_t launch_channels_on(Plan& P, const void* values, int64_t ld, int32_t n
                         s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
+}
+
+hipError_t launch_channels_plain_order(Plan& P, const void* values, int64_t ld, int32_t nchan,
+                                      int32_t dtype, float* out, hipStream_t s, Shape shape) {
+    const bool vec = values_vec(P, values, ld, dtype);
+    const bool m16 = P.opts.precision != HG_PREC_FP32;
+    const Shape eff = effective_shape(m16, dtype, vec, shape);
+    const int64_t ncb = (nchan + 64 * eff.g - 1) / (64 * eff.g);
+    return launch_channels_on(P, values, ld, nchan, dtype, out, s, shape, nullptr,
+                              P.ntiles * ncb);
 }
 
 bool channel_lds_fits(bool m16, int chunk, int blk_max) {

@@ -314,6 +314,9 @@ hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t ncha
 hipError_t launch_channels_on(Plan& P, const void* values, int64_t ld, int32_t nchan,
                               int32_t dtype, float* out, hipStream_t s, Shape shape,
                               const int64_t* order, int64_t nwg);
+// the same launch with workgroup b on item b (no order buffer)
+hipError_t launch_channels_plain_order(Plan& P, const void* values, int64_t ld, int32_t nchan,
+                                      int32_t dtype, float* out, hipStream_t s, Shape shape);
 hipError_t launch_literal(const Plan& P, const float* values, int64_t ld, int32_t nchan,
                           float* out, int32_t gamma, int32_t block, hipStream_t s);
 FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t nchan, float* out,
@@ -335,6 +338,10 @@ int grid_channels_host(Plan& P, const void* host_values, int64_t ld, int32_t nch
                        float* host_out, int32_t block, hipStream_t s, hg_stream_info* info,
                        std::string& err);
 void ring_free(HostRing& R);
+// the same through the fixed per-device staging array (no allocation)
+int grid_channels_host_noalloc(Plan& P, const void* host_values, int64_t ld, int32_t nchan,
+                               int32_t dtype, float* host_out, int32_t block, hipStream_t s,
+                               hg_stream_info* info, std::string& err);
 
 // device memory (runtime.hip)
 hipError_t dev_alloc(DevBuf& b, size_t bytes);

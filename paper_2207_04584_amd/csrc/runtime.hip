@@ -738,6 +738,37 @@ int hg_grid_channels_host(hg_plan* h, const void* host_values, int64_t ld, int32
     });
 }
 
+int hg_grid_channels_host_noalloc(hg_plan* h, const void* host_values, int64_t ld,
+                                  int32_t nchan, int32_t dtype, float* host_out, int32_t block,
+                                  void* hip_stream, hg_stream_info* info) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!h) return fail(HG_ERR_ARG, "plan must not be NULL");
+        Plan& P = h->P;
+        if (P.finished) return fail(HG_ERR_STATE, "plan already finished");
+        if (nchan < 0) return fail(HG_ERR_ARG, "nchan must be >= 0");
+        if (dtype != HG_F32 && dtype != HG_BF16 && dtype != HG_F16)
+            return fail(HG_ERR_ARG, "unknown dtype");
+        if (block < 0) return fail(HG_ERR_ARG, "block must be >= 0");
+        if (info) std::memset(info, 0, sizeof *info);
+        if (nchan == 0) return HG_OK;
+        if (!host_out || (!host_values && P.n > 0))
+            return fail(HG_ERR_ARG, "values and out must not be NULL");
+        if (ld < nchan) return fail(HG_ERR_ARG, "ld must be >= nchan");
+        if (P.opts.precision == HG_PREC_MFMA_BF16 && dtype != HG_BF16)
+            return fail(HG_ERR_UNSUPPORTED, "a BF16-MFMA plan grids BF16 values");
+        if (P.opts.precision == HG_PREC_MFMA_F16 && dtype != HG_F16)
+            return fail(HG_ERR_UNSUPPORTED, "an FP16-MFMA plan grids FP16 values");
+        hipError_t e = hipSetDevice(P.device);
+        if (e != hipSuccess) return fail_hip(e, "grid_channels_host_noalloc");
+        std::string err;
+        int rc = grid_channels_host_noalloc(P, host_values, ld, nchan, dtype, host_out, block,
+                                            (hipStream_t)hip_stream, info, err);
+        if (rc) return fail(rc, err);
+        return HG_OK;
+    });
+}
+
 int hg_grid_finish(hg_plan* h) {
     return guarded([&]() -> int {
         g_err.clear();

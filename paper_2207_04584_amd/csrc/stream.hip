@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <thread>
 
 #include "hg_common.h"
@@ -293,6 +294,166 @@ int grid_channels_host(Plan& P, const void* host_values, int64_t ld, int32_t nch
         info->kernel_ms = tm.sum(t_ker);
         info->h2d_ms = tm.sum(t_h2d);
         info->d2h_ms = tm.sum(t_d2h);
+        info->wall_ms = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t0)
+                            .count();
+    }
+    return HG_OK;
+}
+
+}  // namespace hg
+
+// ---------------------------------------------------------------------------
+// The same streamed channel phase for callers that cannot allocate
+// (hg_grid_channels_host_noalloc): the two device slots live in one fixed
+// staging array of HG_NOALLOC_STAGING_BYTES per device instead of plan-owned
+// buffers, the copy streams and their events are made once per device, the
+// caller's buffers must be page-locked (no pinned staging of the library's
+// own), and the kernel takes its work items in plain order (no launch-order
+// buffer).  The kernels and the per-cell arithmetic are those of
+// hg_grid_channels_host, so the maps are identical.  Calls that overlap on
+// one device race on the array and the streams.
+namespace hg {
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[HG_NOALLOC_STAGING_BYTES];
+
+struct NoAllocDevice {
+    bool ready = false;
+    char* ptr = nullptr;  // this device's copy of `scratch` (never the host-side name)
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    hipEvent_t ev_h2d[RING_SLOTS] = {nullptr, nullptr};
+    hipEvent_t ev_ker[RING_SLOTS] = {nullptr, nullptr};
+    hipEvent_t ev_d2h[RING_SLOTS] = {nullptr, nullptr};
+};
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Once per device, with that device current: the staging array's device
+// address, two copy streams and the slot events.
+int noalloc_device(int dev, NoAllocDevice** out, std::string& err) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        err = "device index beyond the staging table";
+        return HG_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    NoAllocDevice& D = g_noalloc[dev];
+    if (!D.ready) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("staging array address: ") + hipGetErrorString(e);
+            return HG_ERR_DEVICE;
+        }
+        if (!D.h2d) e = hipStreamCreateWithFlags(&D.h2d, hipStreamNonBlocking);
+        if (e == hipSuccess && !D.d2h) e = hipStreamCreateWithFlags(&D.d2h, hipStreamNonBlocking);
+        for (int s = 0; s < RING_SLOTS && e == hipSuccess; s++)
+            for (hipEvent_t* ev : {&D.ev_h2d[s], &D.ev_ker[s], &D.ev_d2h[s]})
+                if (e == hipSuccess && !*ev) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            err = std::string("staging streams: ") + hipGetErrorString(e);
+            return HG_ERR_DEVICE;
+        }
+        D.ptr = (char*)p;
+        D.ready = true;
+    }
+    *out = &D;
+    return HG_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+int grid_channels_host_noalloc(Plan& P, const void* host_values, int64_t ld, int32_t nchan,
+                               int32_t dtype, float* host_out, int32_t block, hipStream_t cs,
+                               hg_stream_info* info, std::string& err) {
+    auto t0 = std::chrono::steady_clock::now();
+    if ((P.n > 0 && !is_pinned(host_values)) || !is_pinned(host_out)) {
+        err = "host_values and host_out must be page-locked (hipHostMalloc or pinned tensors)";
+        return HG_ERR_ARG;
+    }
+    const size_t es = dtype == HG_F32 ? 4 : 2;
+    const int64_t n = P.n, npix = P.npix;
+    // staging bytes of a block of b channels: two slots of values and of maps
+    auto need = [&](int64_t b, int64_t ldd) {
+        return 2 * round256((size_t)std::max<int64_t>(n, 1) * ldd * es) +
+               2 * round256((size_t)b * npix * 4);
+    };
+    int64_t blk = block;
+    if (blk == 0) {
+        // the widest block that fits the staging array
+        blk = std::min<int64_t>(nchan, 4096);
+        while (blk > 1 && need(blk, (blk + 7) / 8 * 8) > (size_t)HG_NOALLOC_STAGING_BYTES) blk--;
+    }
+    blk = std::min<int64_t>(blk, nchan);
+    const int nb = (int)((nchan + blk - 1) / blk);
+    const bool linear = nb == 1 && blk == ld;
+    const int64_t ldd = linear ? ld : (blk + 7) / 8 * 8;
+    if (need(blk, ldd) > (size_t)HG_NOALLOC_STAGING_BYTES) {
+        err = "a block of " + std::to_string(blk) + " channels needs " +
+              std::to_string(need(blk, ldd)) + " bytes of staging, over the fixed " +
+              std::to_string((size_t)HG_NOALLOC_STAGING_BYTES) + "; use a smaller block";
+        return HG_ERR_ARG;
+    }
+    NoAllocDevice* D = nullptr;
+    int rc = noalloc_device(P.device, &D, err);
+    if (rc) return rc;
+    char* vals[RING_SLOTS];
+    float* outs[RING_SLOTS];
+    const size_t val_al = round256((size_t)std::max<int64_t>(n, 1) * ldd * es);
+    const size_t out_al = round256((size_t)blk * npix * 4);
+    for (int s = 0; s < RING_SLOTS; s++) {
+        vals[s] = D->ptr + s * val_al;
+        outs[s] = (float*)(D->ptr + RING_SLOTS * val_al + s * out_al);
+    }
+    const char* vin = (const char*)host_values;
+    char* vout = (char*)host_out;
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < nb && e == hipSuccess; b++) {
+        const int s = b % RING_SLOTS;
+        const int64_t c0 = (int64_t)b * blk;
+        const int64_t w = std::min<int64_t>(blk, nchan - c0);
+        if (b >= RING_SLOTS) e = hipStreamWaitEvent(D->h2d, D->ev_ker[s], 0);
+        if (n > 0 && e == hipSuccess) {
+            if (linear)
+                e = hipMemcpyAsync(vals[s], vin, (size_t)n * ld * es, hipMemcpyHostToDevice, D->h2d);
+            else
+                e = hipMemcpy2DAsync(vals[s], (size_t)ldd * es, vin + (size_t)c0 * es,
+                                     (size_t)ld * es, (size_t)w * es, (size_t)n,
+                                     hipMemcpyHostToDevice, D->h2d);
+        }
+        if (e == hipSuccess) e = hipEventRecord(D->ev_h2d[s], D->h2d);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, D->ev_h2d[s], 0);
+        if (e == hipSuccess && b >= RING_SLOTS) e = hipStreamWaitEvent(cs, D->ev_d2h[s], 0);
+        if (e == hipSuccess)
+            e = launch_channels_plain_order(P, n > 0 ? vals[s] : nullptr, ldd, (int32_t)w, dtype,
+                                            outs[s], cs, P.shape);
+        if (e == hipSuccess) e = hipEventRecord(D->ev_ker[s], cs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(D->d2h, D->ev_ker[s], 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(vout + (size_t)c0 * npix * 4, outs[s], (size_t)w * npix * 4,
+                               hipMemcpyDeviceToHost, D->d2h);
+        if (e == hipSuccess) e = hipEventRecord(D->ev_d2h[s], D->d2h);
+    }
+    hipError_t e2 = hipStreamSynchronize(D->d2h);
+    if (e == hipSuccess) e = e2;
+    e2 = hipStreamSynchronize(D->h2d);
+    if (e == hipSuccess) e = e2;
+    e2 = hipStreamSynchronize(cs);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) {
+        err = std::string("grid_channels_host_noalloc: ") + hipGetErrorString(e);
+        return HG_ERR_DEVICE;
+    }
+    P.ch_calls += nb;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->blocks = nb;
+        info->pinned = 1;
+        info->h2d_bytes = (int64_t)n * nchan * (int64_t)es;
+        info->d2h_bytes = (int64_t)nchan * npix * 4;
         info->wall_ms = std::chrono::duration<double, std::milli>(
                             std::chrono::steady_clock::now() - t0)
                             .count();
