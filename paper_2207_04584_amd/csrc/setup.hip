@@ -627,6 +627,10 @@ __device__ inline double kernel_weight(const KernelArgs& ka, double d2, const Pa
 // order into the group's entry list with their four FP32 weights.  HPX: the
 // map is a HEALPix patch, whose two rows have their own pixel RAs.
 constexpr int GATHER_WAVES = 4;
+constexpr int BUCKET_WAVES = 4;
+// tiles with at most this many chunks are dealt (chunk = compacted slot mod
+// the chunk count); denser tiles keep consecutive slots per chunk
+constexpr int SCRAMBLE_MAX_NCH = 2048;
 
 template <bool SMALL, int KT, bool HPX>
 __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
@@ -901,19 +905,35 @@ __global__ __launch_bounds__(256) void k_mark_used(
 __global__ void k_tile_rebase(const int64_t* __restrict__ tile_base, int64_t ntiles,
                               const int64_t* __restrict__ newpos, int32_t chunk,
                               int64_t* __restrict__ tile_base2, int64_t* __restrict__ tile_ncp,
-                              int64_t* __restrict__ tile_nch) {
+                              int64_t* __restrict__ tile_nch, int64_t* __restrict__ tile_pad,
+                              int32_t* __restrict__ tile_scr) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > ntiles) return;
     tile_base2[t] = newpos[tile_base[t]];
     if (t == ntiles) return;
     int64_t ns = newpos[tile_base[t + 1]] - newpos[tile_base[t]];
-    tile_ncp[t] = (int64_t)TILE_PGS * ((ns + chunk - 1) / chunk + 1);
-    tile_nch[t] = (ns + chunk - 1) / chunk;
+    const int64_t nch = (ns + chunk - 1) / chunk;
+    tile_ncp[t] = (int64_t)TILE_PGS * (nch + 1);
+    tile_nch[t] = nch;
+    // Dealt tiles: slot p of the compacted list goes to chunk p mod nch, so
+    // that every chunk samples the whole tile (a run of consecutive slots
+    // lies in one or two sky cells, i.e. in a few pixel groups only); the
+    // chunks' unused tail slots are padding.
+    const bool scr = nch >= 2 && nch <= SCRAMBLE_MAX_NCH && nch * chunk <= (int64_t)SLOT_MASK;
+    tile_scr[t] = scr ? 1 : 0;
+    tile_pad[t] = scr ? nch * chunk : ns;
+}
+
+// Tile-local slot of compacted slot p in a dealt tile: chunk p mod nch,
+// position p / nch in it.
+__device__ inline uint32_t dealt_slot(int64_t p, int64_t nch, int32_t chunk) {
+    return (uint32_t)((p % nch) * chunk + p / nch);
 }
 
 __global__ __launch_bounds__(256) void k_remap_entries(
-    int32_t npgx, int64_t npg, int32_t ntx, const int64_t* __restrict__ tile_base,
-    const int64_t* __restrict__ tile_base2, const int64_t* __restrict__ pg_base,
+    int32_t npgx, int64_t npg, int32_t ntx, int32_t chunk, const int64_t* __restrict__ tile_base,
+    const int64_t* __restrict__ tile_base2, const int64_t* __restrict__ tile_nch,
+    const int32_t* __restrict__ tile_scr, const int64_t* __restrict__ pg_base,
     const uint32_t* __restrict__ pg_cnt, const int64_t* __restrict__ newpos,
     uint32_t* __restrict__ ent_slot) {
     int64_t pg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -921,6 +941,8 @@ __global__ __launch_bounds__(256) void k_remap_entries(
     const int lane = threadIdx.x & 63;
     const int64_t tile = pg_tile(pg, npgx, ntx);
     const int64_t tb = tile_base[tile], tb2 = tile_base2[tile];
+    const bool scr = tile_scr[tile] != 0;
+    const int64_t nch = tile_nch[tile];
     uint32_t* es = ent_slot + pg_base[pg];
     const uint32_t n = pg_cnt[pg];
     // four entries a lane per pass: their loads, then their position lookups,
@@ -939,7 +961,9 @@ __global__ __launch_bounds__(256) void k_remap_entries(
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const uint32_t t = t0 + lane + 64 * k;
-            if (t < n) es[t] = (uint32_t)(np[k] - tb2) | (w[k] & ~SLOT_MASK);
+            const int64_t p = np[k] - tb2;
+            const uint32_t loc = scr ? dealt_slot(p, nch, chunk) : (uint32_t)p;
+            if (t < n) es[t] = loc | (w[k] & ~SLOT_MASK);
         }
     }
 }
@@ -952,6 +976,133 @@ __global__ void k_compact_slots(const uint32_t* __restrict__ used,
 }
 
 
+
+// The tile slot lists in their final layout (base tile_base3): a dealt tile's
+// slot c * chunk + j holds compacted slot j * nch + c, or, past the chunk's
+// real slots, the tile's first sample (staged and never used); other tiles
+// are copied as they are.  One workgroup per tile.
+__global__ __launch_bounds__(256) void k_deal_slots(
+    const int64_t* __restrict__ tile_base2, const int64_t* __restrict__ tile_base3,
+    const int64_t* __restrict__ tile_nch, const int32_t* __restrict__ tile_scr, int32_t chunk,
+    const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+    const int64_t t = blockIdx.x;
+    const int64_t b2 = tile_base2[t], ns = tile_base2[t + 1] - b2;
+    const int64_t b3 = tile_base3[t], np = tile_base3[t + 1] - b3;
+    const bool scr = tile_scr[t] != 0;
+    const int64_t nch = tile_nch[t];
+    for (int64_t q = threadIdx.x; q < np; q += blockDim.x) {
+        int64_t p = q;
+        if (scr) {
+            p = (q % chunk) * nch + q / chunk;
+            if (p >= ns) p = 0;
+        }
+        dst[b3 + q] = src[b2 + p];
+    }
+}
+
+// Entries bucketed by chunk, one wave per pixel group.  A dealt tile's
+// entries leave the remap in ascending compacted slot, i.e. with chunks
+// interleaved; they are counted per chunk (LDS), the counts scanned into the
+// group's chunk pointers, and the entries moved to their chunk's bucket in
+// their order of arrival, which keeps every bucket in ascending slot order
+// (a chunk's slots are its compacted slots in ascending order).  Ranks
+// within a pass of 64 entries come from comparing chunk numbers lane by
+// lane, so the layout does not depend on the order of atomics.  Other tiles
+// keep their (already sorted) order and take their pointers by binary
+// search.
+__global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
+    int32_t npgx, int64_t npg, int32_t ntx, int32_t chunk, const int64_t* __restrict__ tile_blk,
+    const int32_t* __restrict__ tile_scr, const int64_t* __restrict__ cp_base,
+    const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ pg_cnt,
+    const uint32_t* __restrict__ ent_slot, const float4* __restrict__ ent_w,
+    uint32_t* __restrict__ chunk_ptr, uint32_t* __restrict__ ent_slot2,
+    float4* __restrict__ ent_w2) {
+    __shared__ uint32_t cur_all[BUCKET_WAVES][SCRAMBLE_MAX_NCH];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t pg = (int64_t)blockIdx.x * BUCKET_WAVES + wave;
+    if (pg >= npg) return;  // uniform per wave; no workgroup barrier below
+    uint32_t* cur = cur_all[wave];
+    const int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
+    const int64_t tile = (int64_t)(gy / TILE_PGY) * ntx + gx / TILE_PGX;
+    const int lp = (gy % TILE_PGY) * TILE_PGX + gx % TILE_PGX;
+    const int64_t nch = tile_blk[tile + 1] - tile_blk[tile];
+    uint32_t* cp = chunk_ptr + cp_base[tile] + (int64_t)lp * (nch + 1);
+    const int64_t base = pg_base[pg];
+    const uint32_t* es = ent_slot + base;
+    const float4* ew = ent_w + base;
+    const uint32_t ne = pg_cnt[pg];
+    if (!tile_scr[tile]) {
+        for (int64_t c = lane; c <= nch; c += 64) {
+            const uint32_t target = (uint32_t)(c * chunk);
+            uint32_t lo = 0, hi = ne;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if ((es[mid] & SLOT_MASK) < target)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            cp[c] = lo;
+        }
+        for (uint32_t t = lane; t < ne; t += 64) {
+            ent_slot2[base + t] = es[t];
+            ent_w2[base + t] = ew[t];
+        }
+        return;
+    }
+    for (int64_t c = lane; c < nch; c += 64) cur[c] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t t = lane; t < ne; t += 64) atomicAdd(&cur[(es[t] & SLOT_MASK) / chunk], 1u);
+    __builtin_amdgcn_wave_barrier();
+    // exclusive scan of the counts: the chunk pointers and the bucket cursors
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nch; c0 += 64) {
+        const int64_t c = c0 + lane;
+        const uint32_t v = c < nch ? cur[c] : 0u;
+        uint32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        const uint32_t excl = carry + x - v;
+        if (c < nch) {
+            cp[c] = excl;
+            cur[c] = excl;
+        }
+        carry += __shfl(x, 63, 64);
+    }
+    if (lane == 0) cp[nch] = carry;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t t0 = 0; t0 < ne; t0 += 64) {
+        const uint32_t t = t0 + lane;
+        const bool live = t < ne;
+        const uint32_t w = live ? es[t] : 0u;
+        const float4 wt = live ? ew[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int c = live ? (int)((w & SLOT_MASK) / chunk) : -1;
+        // compacted slot of the entry (ascending along the list): a pass that
+        // spans fewer than nch compacted slots meets every chunk at most once
+        const int64_t p = (int64_t)((w & SLOT_MASK) % chunk) * nch + c;
+        const uint32_t last = ne - 1 - t0 < 63u ? ne - 1 - t0 : 63u;
+        const int64_t p0 = __builtin_amdgcn_readfirstlane((uint32_t)p);
+        const int64_t p1 = __builtin_amdgcn_readlane((uint32_t)p, last);
+        int before = 0, after = 0;  // live lanes of this pass in the same chunk
+        if (p1 - p0 >= nch) {
+            for (int k = 0; k < 64; k++) {
+                const int ck = __builtin_amdgcn_readlane(c, k);
+                before += (k < lane && ck == c);
+                after += (k > lane && ck == c);
+            }
+        }
+        const uint32_t at = live ? cur[c] + before : 0u;
+        if (live) {
+            ent_slot2[base + at] = w;
+            ent_w2[base + at] = wt;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (live && after == 0) cur[c] = at + 1;  // the pass's last entry of its chunk
+        __builtin_amdgcn_wave_barrier();
+    }
+}
 
 // host-side ring band of a declination range [d0, d1] (radians) widened by r
 void ring_range(int64_t nside, double d0, double d1, double r, double eps, int32_t* lo,
@@ -1354,7 +1505,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
 
     DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, btile, wl;
-    DevBuf used, newpos, ctmp, tbase2, slot2;
+    DevBuf used, newpos, ctmp, tbase2, slot2, tpad, tscr, tbase3, slot3, es2, ew2;
     // Buffers go back to the allocation cache, where a setup on another
     // stream may take them at once: the stream's work is drained first.
     auto cleanup = [&]() {
@@ -1364,6 +1515,12 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         dev_free(ctmp);
         dev_free(tbase2);
         dev_free(slot2);
+        dev_free(tpad);
+        dev_free(tscr);
+        dev_free(tbase3);
+        dev_free(slot3);
+        dev_free(es2);
+        dev_free(ew2);
         dev_free(wl);
         dev_free(tnch);
         dev_free(bcnt);
@@ -1542,8 +1699,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         // the entry blocks take 20 B an entry in the FP32 form (12 B in the
         // 16-bit forms) and pad each (group, chunk) run to four entries
         const size_t blk_entry = P.opts.precision == HG_PREC_FP32 ? 20 : 12;
-        size_t need = (size_t)P.total_slots * (4 + 16) + (size_t)P.ent_cap * (20 + blk_entry) +
-                      (size_t)P.chunk_ptrs * (4 + 60);
+        // (the dealing's padded slot list and the bucketed copy of the entries
+        // add 4 B a slot plus 4 B per tile and chunk slot, and 20 B an entry)
+        size_t need = (size_t)P.total_slots * (4 + 16 + 4) + (size_t)P.ntiles * P.chunk * 4 +
+                      (size_t)P.ent_cap * (20 + 20 + blk_entry) + (size_t)P.chunk_ptrs * (4 + 60);
         size_t have = 0;
         for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                           &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.cp_base, &P.pix_count, &P.pix_W,
@@ -1589,14 +1748,23 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const int32_t*)P.pix_count.p, P.npix, nnz_total);
         HG_STEP(hipGetLastError());
     }
-    // 5b: drop the slots no pixel of their tile uses, then recount chunks
+    // 5b: drop the slots no pixel of their tile uses, recount chunks, deal the
+    // slots of each tile over its chunks, and bucket every group's entries by
+    // chunk (with the chunk pointers)
     if (P.total_slots > 0) {
         const int64_t ts = P.total_slots;
+        const int64_t ts_pad = ts + P.ntiles * (int64_t)P.chunk;  // padding: < chunk a tile
         HG_STEP(dev_alloc(used, (size_t)ts * 4));
         HG_STEP(dev_alloc(newpos, (size_t)(ts + 1) * 8));
         HG_STEP(dev_alloc(ctmp, (size_t)((ts + SCAN_B - 1) / SCAN_B + 1) * 8));
         HG_STEP(dev_alloc(tbase2, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
         HG_STEP(dev_alloc(slot2, (size_t)ts * 4));
+        HG_STEP(dev_alloc(tpad, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+        HG_STEP(dev_alloc(tscr, sizeof(int32_t) * (size_t)(P.ntiles + 1)));
+        HG_STEP(dev_alloc(tbase3, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
+        HG_STEP(dev_alloc(slot3, (size_t)ts_pad * 4));
+        HG_STEP(dev_alloc(es2, (size_t)(P.ent_cap ? P.ent_cap : 1) * 4));
+        HG_STEP(dev_alloc(ew2, (size_t)(P.ent_cap ? P.ent_cap : 1) * 16));
         HG_STEP(hipMemsetAsync(used.p, 0, (size_t)ts * 4, s));
         hipLaunchKernelGGL(k_mark_used, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
                            P.ntx, (const int64_t*)P.tile_nslots.p, (const int64_t*)P.pg_base.p,
@@ -1607,11 +1775,15 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                                    (int64_t*)newpos.p, (int64_t*)ctmp.p, s)));
         hipLaunchKernelGGL(k_tile_rebase, dim3(blocks_for(P.ntiles + 1, 256)), dim3(256), 0, s,
                            (const int64_t*)P.tile_nslots.p, P.ntiles, (const int64_t*)newpos.p,
-                           P.chunk, (int64_t*)tbase2.p, (int64_t*)tcp.p, (int64_t*)tnch.p);
+                           P.chunk, (int64_t*)tbase2.p, (int64_t*)tcp.p, (int64_t*)tnch.p,
+                           (int64_t*)tpad.p, (int32_t*)tscr.p);
         HG_STEP(hipGetLastError());
+        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tpad.p, P.ntiles,
+                                                  (int64_t*)tbase3.p, (int64_t*)scan_tmp, s)));
         hipLaunchKernelGGL(k_remap_entries, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx,
-                           P.npg, P.ntx, (const int64_t*)P.tile_nslots.p,
-                           (const int64_t*)tbase2.p, (const int64_t*)P.pg_base.p,
+                           P.npg, P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
+                           (const int64_t*)tbase2.p, (const int64_t*)tnch.p,
+                           (const int32_t*)tscr.p, (const int64_t*)P.pg_base.p,
                            (const uint32_t*)P.pg_cnt.p, (const int64_t*)newpos.p,
                            (uint32_t*)P.ent_slot.p);
         HG_STEP(hipGetLastError());
@@ -1619,15 +1791,30 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const uint32_t*)used.p, (const int64_t*)newpos.p, ts,
                            (const uint32_t*)P.slot_idx.p, (uint32_t*)slot2.p);
         HG_STEP(hipGetLastError());
-        std::swap(P.slot_idx, slot2);
-        HG_STEP(hipMemcpyAsync(P.tile_nslots.p, tbase2.p, sizeof(int64_t) * (size_t)(P.ntiles + 1),
+        hipLaunchKernelGGL(k_deal_slots, dim3((unsigned)P.ntiles), dim3(256), 0, s,
+                           (const int64_t*)tbase2.p, (const int64_t*)tbase3.p,
+                           (const int64_t*)tnch.p, (const int32_t*)tscr.p, P.chunk,
+                           (const uint32_t*)slot2.p, (uint32_t*)slot3.p);
+        HG_STEP(hipGetLastError());
+        std::swap(P.slot_idx, slot3);
+        HG_STEP(hipMemcpyAsync(P.tile_nslots.p, tbase3.p, sizeof(int64_t) * (size_t)(P.ntiles + 1),
                                hipMemcpyDeviceToDevice, s));
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tnch.p, P.ntiles,
                                                   (int64_t*)P.tile_blk.p, (int64_t*)scan_tmp, s)));
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tcp.p, P.ntiles,
                                                   (int64_t*)P.cp_base.p, (int64_t*)scan_tmp, s)));
+        hipLaunchKernelGGL(k_bucket_entries, dim3(blocks_for(P.npg, BUCKET_WAVES)),
+                           dim3(64 * BUCKET_WAVES), 0, s, P.npgx, P.npg, P.ntx, P.chunk,
+                           (const int64_t*)P.tile_blk.p, (const int32_t*)tscr.p,
+                           (const int64_t*)P.cp_base.p, (const int64_t*)P.pg_base.p,
+                           (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
+                           (const float4*)P.ent_w.p, (uint32_t*)P.chunk_ptr.p,
+                           (uint32_t*)es2.p, (float4*)ew2.p);
+        HG_STEP(hipGetLastError());
+        std::swap(P.ent_slot, es2);
+        std::swap(P.ent_w, ew2);
         int64_t t3[3];
-        HG_STEP(hipMemcpyAsync(&t3[0], (int64_t*)tbase2.p + P.ntiles, 8, hipMemcpyDeviceToHost, s));
+        HG_STEP(hipMemcpyAsync(&t3[0], (int64_t*)tbase3.p + P.ntiles, 8, hipMemcpyDeviceToHost, s));
         HG_STEP(hipMemcpyAsync(&t3[1], (int64_t*)P.tile_blk.p + P.ntiles, 8, hipMemcpyDeviceToHost,
                                s));
         HG_STEP(hipMemcpyAsync(&t3[2], (int64_t*)P.cp_base.p + P.ntiles, 8, hipMemcpyDeviceToHost,
@@ -1638,17 +1825,24 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         P.n_blocks = t3[1];
         P.chunk_ptrs = t3[2];
         dev_free(slot2);
+        dev_free(slot3);
+        dev_free(es2);
+        dev_free(ew2);
         dev_free(used);
         dev_free(newpos);
         dev_free(ctmp);
         dev_free(tbase2);
+        dev_free(tpad);
+        dev_free(tscr);
+        dev_free(tbase3);
+    } else {
+        hipLaunchKernelGGL(k_chunk_ptr, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx,
+                           P.npg, P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
+                           (const int64_t*)P.cp_base.p, (const int64_t*)P.pg_base.p,
+                           (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
+                           (uint32_t*)P.chunk_ptr.p);
+        HG_STEP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_chunk_ptr, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
-                       P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
-                       (const int64_t*)P.cp_base.p, (const int64_t*)P.pg_base.p,
-                       (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
-                       (uint32_t*)P.chunk_ptr.p);
-    HG_STEP(hipGetLastError());
     // chunk-major blocks for the channel kernels
     const bool grouped = P.opts.precision != HG_PREC_FP32;
     if (P.n_blocks > 0) {
