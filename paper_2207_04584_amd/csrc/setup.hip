@@ -630,7 +630,7 @@ constexpr int GATHER_WAVES = 4;
 constexpr int BUCKET_WAVES = 4;
 // tiles with at most this many chunks are dealt (chunk = compacted slot mod
 // the chunk count); denser tiles keep consecutive slots per chunk
-constexpr int SCRAMBLE_MAX_NCH = 2048;
+constexpr int SCRAMBLE_MAX_NCH = 1024;
 
 template <bool SMALL, int KT, bool HPX>
 __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
@@ -1002,26 +1002,30 @@ __global__ __launch_bounds__(256) void k_deal_slots(
 
 // Entries bucketed by chunk, one wave per pixel group.  A dealt tile's
 // entries leave the remap in ascending compacted slot, i.e. with chunks
-// interleaved; they are counted per chunk (LDS), the counts scanned into the
-// group's chunk pointers, and the entries moved to their chunk's bucket in
-// their order of arrival, which keeps every bucket in ascending slot order
-// (a chunk's slots are its compacted slots in ascending order).  Ranks
-// within a pass of 64 entries come from comparing chunk numbers lane by
-// lane, so the layout does not depend on the order of atomics.  Other tiles
-// keep their (already sorted) order and take their pointers by binary
-// search.
+// interleaved; each entry's tile-local slot is (chunk c, position j < chunk).
+// The group's entries are marked in one 64-bit word per chunk (LDS: bit j of
+// word c), the words' popcounts scanned into the group's chunk pointers, and
+// every entry's bucketed place is pointer c plus the number of its chunk's
+// entries at lower positions -- a function of the set alone, so every entry
+// is placed at once, each bucket is in ascending slot order, and the layout
+// does not depend on the order of the atomics.  The entries themselves stay
+// where they are: perm[place] is the entry's index in the group's list (the
+// block fills read through it).  Other tiles keep their (already sorted)
+// order, take their pointers by binary search and an identity perm.
 __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     int32_t npgx, int64_t npg, int32_t ntx, int32_t chunk, const int64_t* __restrict__ tile_blk,
     const int32_t* __restrict__ tile_scr, const int64_t* __restrict__ cp_base,
     const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ pg_cnt,
-    const uint32_t* __restrict__ ent_slot, const float4* __restrict__ ent_w,
-    uint32_t* __restrict__ chunk_ptr, uint32_t* __restrict__ ent_slot2,
-    float4* __restrict__ ent_w2) {
-    __shared__ uint32_t cur_all[BUCKET_WAVES][SCRAMBLE_MAX_NCH];
+    const uint32_t* __restrict__ ent_slot, uint32_t* __restrict__ chunk_ptr,
+    uint32_t* __restrict__ perm) {
+    static_assert(MAX_CHUNK <= 64, "a chunk's positions fit one 64-bit word");
+    __shared__ unsigned long long bits_all[BUCKET_WAVES][SCRAMBLE_MAX_NCH];
+    __shared__ uint32_t ptr_all[BUCKET_WAVES][SCRAMBLE_MAX_NCH];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t pg = (int64_t)blockIdx.x * BUCKET_WAVES + wave;
     if (pg >= npg) return;  // uniform per wave; no workgroup barrier below
-    uint32_t* cur = cur_all[wave];
+    unsigned long long* bits = bits_all[wave];
+    uint32_t* ptr = ptr_all[wave];
     const int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
     const int64_t tile = (int64_t)(gy / TILE_PGY) * ntx + gx / TILE_PGX;
     const int lp = (gy % TILE_PGY) * TILE_PGX + gx % TILE_PGX;
@@ -1029,7 +1033,7 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     uint32_t* cp = chunk_ptr + cp_base[tile] + (int64_t)lp * (nch + 1);
     const int64_t base = pg_base[pg];
     const uint32_t* es = ent_slot + base;
-    const float4* ew = ent_w + base;
+    uint32_t* pm = perm + base;
     const uint32_t ne = pg_cnt[pg];
     if (!tile_scr[tile]) {
         for (int64_t c = lane; c <= nch; c += 64) {
@@ -1044,21 +1048,21 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
             }
             cp[c] = lo;
         }
-        for (uint32_t t = lane; t < ne; t += 64) {
-            ent_slot2[base + t] = es[t];
-            ent_w2[base + t] = ew[t];
-        }
+        for (uint32_t t = lane; t < ne; t += 64) pm[t] = t;
         return;
     }
-    for (int64_t c = lane; c < nch; c += 64) cur[c] = 0;
+    for (int64_t c = lane; c < nch; c += 64) bits[c] = 0ull;
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t t = lane; t < ne; t += 64) atomicAdd(&cur[(es[t] & SLOT_MASK) / chunk], 1u);
+    for (uint32_t t = lane; t < ne; t += 64) {
+        const uint32_t loc = es[t] & SLOT_MASK;
+        atomicOr(&bits[loc / chunk], 1ull << (loc % chunk));
+    }
     __builtin_amdgcn_wave_barrier();
-    // exclusive scan of the counts: the chunk pointers and the bucket cursors
+    // exclusive scan of the chunks' entry counts: the chunk pointers
     uint32_t carry = 0;
     for (int64_t c0 = 0; c0 < nch; c0 += 64) {
         const int64_t c = c0 + lane;
-        const uint32_t v = c < nch ? cur[c] : 0u;
+        const uint32_t v = c < nch ? (uint32_t)__builtin_popcountll(bits[c]) : 0u;
         uint32_t x = v;
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, 64);
@@ -1067,40 +1071,16 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
         const uint32_t excl = carry + x - v;
         if (c < nch) {
             cp[c] = excl;
-            cur[c] = excl;
+            ptr[c] = excl;
         }
         carry += __shfl(x, 63, 64);
     }
     if (lane == 0) cp[nch] = carry;
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t t0 = 0; t0 < ne; t0 += 64) {
-        const uint32_t t = t0 + lane;
-        const bool live = t < ne;
-        const uint32_t w = live ? es[t] : 0u;
-        const float4 wt = live ? ew[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const int c = live ? (int)((w & SLOT_MASK) / chunk) : -1;
-        // compacted slot of the entry (ascending along the list): a pass that
-        // spans fewer than nch compacted slots meets every chunk at most once
-        const int64_t p = (int64_t)((w & SLOT_MASK) % chunk) * nch + c;
-        const uint32_t last = ne - 1 - t0 < 63u ? ne - 1 - t0 : 63u;
-        const int64_t p0 = __builtin_amdgcn_readfirstlane((uint32_t)p);
-        const int64_t p1 = __builtin_amdgcn_readlane((uint32_t)p, last);
-        int before = 0, after = 0;  // live lanes of this pass in the same chunk
-        if (p1 - p0 >= nch) {
-            for (int k = 0; k < 64; k++) {
-                const int ck = __builtin_amdgcn_readlane(c, k);
-                before += (k < lane && ck == c);
-                after += (k > lane && ck == c);
-            }
-        }
-        const uint32_t at = live ? cur[c] + before : 0u;
-        if (live) {
-            ent_slot2[base + at] = w;
-            ent_w2[base + at] = wt;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (live && after == 0) cur[c] = at + 1;  // the pass's last entry of its chunk
-        __builtin_amdgcn_wave_barrier();
+    for (uint32_t t = lane; t < ne; t += 64) {
+        const uint32_t loc = es[t] & SLOT_MASK, c = loc / chunk, j = loc % chunk;
+        const unsigned long long below = (1ull << j) - 1ull;
+        pm[ptr[c] + (uint32_t)__builtin_popcountll(bits[c] & below)] = t;
     }
 }
 
@@ -1196,7 +1176,7 @@ __device__ inline int64_t tile_of_block(const int64_t* tile_blk, int64_t ntiles,
 }
 
 struct BlockLane {
-    int64_t tile, c, src;
+    int64_t tile, c, src, pgb;  // src: run's first bucketed place; pgb: group's first entry
     int n;
 };
 
@@ -1214,7 +1194,8 @@ __device__ inline BlockLane block_lane_at(int64_t b, int64_t tile, int lane, int
     bool valid = gx < npgx && gy < npgy;
     const uint32_t* cp = chunk_ptr + cp_base[r.tile] + (int64_t)lane * (nch + 1);
     r.n = valid ? (int)(cp[r.c + 1] - cp[r.c]) : 0;
-    r.src = valid ? pg_base[(int64_t)gy * npgx + gx] + cp[r.c] : 0;
+    r.pgb = valid ? pg_base[(int64_t)gy * npgx + gx] : 0;
+    r.src = valid ? r.pgb + cp[r.c] : 0;
     return r;
 }
 
@@ -1232,32 +1213,41 @@ __device__ inline BlockLane block_lane(int64_t b, int lane, int32_t npgx, int32_
 // first unit with the next group), found by a binary search over the wave's
 // registers, with that group's run and the unit's place in it.
 struct UnitRef {
-    int64_t src;
+    int64_t src, pgb;
     int n, t;
 };
-__device__ inline UnitRef unit_ref(int i, int first, int64_t src, int n) {
+// src: the run's first place in the bucketed order (pg_base + chunk pointer);
+// pgb: the group's first entry
+__device__ inline int64_t shfl64(int64_t v, int lane) {
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)((uint64_t)v >> 32);
+    return (int64_t)(((uint64_t)(uint32_t)__shfl((int)hi, lane, 64) << 32) |
+                     (uint32_t)__shfl((int)lo, lane, 64));
+}
+__device__ inline UnitRef unit_ref(int i, int first, int64_t src, int64_t pgb, int n) {
     int lo = 0;
 #pragma unroll
     for (int step = 32; step > 0; step >>= 1)
         if (__shfl(first, lo + step, 64) <= i) lo += step;  // lo + step <= 63
-    const uint32_t slo = (uint32_t)src, shi = (uint32_t)((uint64_t)src >> 32);
     UnitRef u;
-    u.src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)shi, lo, 64) << 32) |
-                      (uint32_t)__shfl((int)slo, lo, 64));
+    u.src = shfl64(src, lo);
+    u.pgb = shfl64(pgb, lo);
     u.n = __shfl(n, lo, 64);
     u.t = i - __shfl(first, lo, 64);
     return u;
 }
 
 // The four entries of a unit (a run's last unit padded with zero weights and
-// its last real slot), slots relative to the chunk's first slot s0.
+// its last real slot), slots relative to the chunk's first slot s0.  The
+// bucketed place of an entry maps to its index in the group's list through
+// perm (pg_base is the group's first entry: a run never spans groups).
 __device__ inline void load_unit(const UnitRef& u, uint32_t s0, const uint32_t* ent_slot,
-                                 const float4* ent_w, uint32_t sl[4], float4 w[4]) {
+                                 const float4* ent_w, const uint32_t* perm, uint32_t sl[4],
+                                 float4 w[4]) {
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int e = 4 * u.t + k;
         const bool real = e < u.n;
-        const int64_t at = u.src + (real ? e : u.n - 1);
+        const int64_t at = u.pgb + perm[u.src + (real ? e : u.n - 1)];
         sl[k] = (ent_slot[at] & SLOT_MASK) - s0;
         const float4 v = ent_w[at];
         w[k] = real ? v : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1314,7 +1304,8 @@ __global__ __launch_bounds__(256) void k_block_fill(
     const int32_t* __restrict__ blk_tile, const int64_t* __restrict__ tile_blk,
     const int64_t* __restrict__ cp_base, const uint32_t* __restrict__ chunk_ptr,
     const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ ent_slot,
-    const float4* __restrict__ ent_w, const int64_t* __restrict__ blk_base,
+    const float4* __restrict__ ent_w, const uint32_t* __restrict__ perm,
+    const int64_t* __restrict__ blk_base,
     float4* __restrict__ e2_w, uint4* __restrict__ e2_s) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
@@ -1327,12 +1318,12 @@ __global__ __launch_bounds__(256) void k_block_fill(
     const uint32_t s0 = (uint32_t)(r.c * chunk);
     for (int i0 = 0; i0 < nu; i0 += 128) {  // same trip count on every lane
         const int ia = i0 + lane, ib = ia + 64;
-        const UnitRef ua = unit_ref(ia, first, r.src, r.n);
-        const UnitRef ub = unit_ref(ib, first, r.src, r.n);
+        const UnitRef ua = unit_ref(ia, first, r.src, r.pgb, r.n);
+        const UnitRef ub = unit_ref(ib, first, r.src, r.pgb, r.n);
         uint32_t sa[4], sb[4];
         float4 wa[4], wb[4];
-        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, sa, wa);
-        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, sb, wb);
+        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, perm, sa, wa);
+        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, perm, sb, wb);
         // [pixel q][entry k]: pixel q's weights for the unit's four entries
         if (ia < nu) {
             e2_s[base + ia] = make_uint4(sa[0], sa[1], sa[2], sa[3]);
@@ -1433,7 +1424,8 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
     const int32_t* __restrict__ blk_tile, const int64_t* __restrict__ tile_blk,
     const int64_t* __restrict__ cp_base, const uint32_t* __restrict__ chunk_ptr,
     const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ ent_slot,
-    const float4* __restrict__ ent_w, const int64_t* __restrict__ blk_base,
+    const float4* __restrict__ ent_w, const uint32_t* __restrict__ perm,
+    const int64_t* __restrict__ blk_base,
     uint16_t* __restrict__ e3_w, uint4* __restrict__ e3_s) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
@@ -1446,12 +1438,12 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
     const uint32_t s0 = (uint32_t)(r.c * chunk);
     for (int i0 = 0; i0 < nu; i0 += 128) {  // same trip count on every lane
         const int ia = i0 + lane, ib = ia + 64;
-        const UnitRef ua = unit_ref(ia, first, r.src, r.n);
-        const UnitRef ub = unit_ref(ib, first, r.src, r.n);
+        const UnitRef ua = unit_ref(ia, first, r.src, r.pgb, r.n);
+        const UnitRef ub = unit_ref(ib, first, r.src, r.pgb, r.n);
         uint32_t sa[4], sb[4];
         float4 wa[4], wb[4];
-        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, sa, wa);
-        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, sb, wb);
+        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, perm, sa, wa);
+        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, perm, sb, wb);
         if (ia < nu) store_unit_g(e3_w, e3_s, base + ia, sa, wa, prec);
         if (ib < nu) store_unit_g(e3_w, e3_s, base + ib, sb, wb, prec);
     }
@@ -1505,7 +1497,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
 
     DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, btile, wl;
-    DevBuf used, newpos, ctmp, tbase2, slot2, tpad, tscr, tbase3, slot3, es2, ew2;
+    DevBuf used, newpos, ctmp, tbase2, slot2, tpad, tscr, tbase3, slot3, perm;
     // Buffers go back to the allocation cache, where a setup on another
     // stream may take them at once: the stream's work is drained first.
     auto cleanup = [&]() {
@@ -1519,8 +1511,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         dev_free(tscr);
         dev_free(tbase3);
         dev_free(slot3);
-        dev_free(es2);
-        dev_free(ew2);
+        dev_free(perm);
         dev_free(wl);
         dev_free(tnch);
         dev_free(bcnt);
@@ -1699,10 +1690,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         // the entry blocks take 20 B an entry in the FP32 form (12 B in the
         // 16-bit forms) and pad each (group, chunk) run to four entries
         const size_t blk_entry = P.opts.precision == HG_PREC_FP32 ? 20 : 12;
-        // (the dealing's padded slot list and the bucketed copy of the entries
-        // add 4 B a slot plus 4 B per tile and chunk slot, and 20 B an entry)
+        // (the dealing's padded slot list and the entries' bucketed order add
+        // 4 B a slot plus 4 B per tile and chunk slot, and 4 B an entry)
         size_t need = (size_t)P.total_slots * (4 + 16 + 4) + (size_t)P.ntiles * P.chunk * 4 +
-                      (size_t)P.ent_cap * (20 + 20 + blk_entry) + (size_t)P.chunk_ptrs * (4 + 60);
+                      (size_t)P.ent_cap * (20 + 4 + blk_entry) + (size_t)P.chunk_ptrs * (4 + 60);
         size_t have = 0;
         for (DevBuf* b : {&P.srt_idx, &P.srt_coord, &P.cell_off, &P.tile_piece, &P.tile_nslots,
                           &P.pg_piece, &P.pg_base, &P.pg_cnt, &P.cp_base, &P.pix_count, &P.pix_W,
@@ -1763,8 +1754,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(tscr, sizeof(int32_t) * (size_t)(P.ntiles + 1)));
         HG_STEP(dev_alloc(tbase3, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
         HG_STEP(dev_alloc(slot3, (size_t)ts_pad * 4));
-        HG_STEP(dev_alloc(es2, (size_t)(P.ent_cap ? P.ent_cap : 1) * 4));
-        HG_STEP(dev_alloc(ew2, (size_t)(P.ent_cap ? P.ent_cap : 1) * 16));
+        HG_STEP(dev_alloc(perm, (size_t)(P.ent_cap ? P.ent_cap : 1) * 4));
         HG_STEP(hipMemsetAsync(used.p, 0, (size_t)ts * 4, s));
         hipLaunchKernelGGL(k_mark_used, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
                            P.ntx, (const int64_t*)P.tile_nslots.p, (const int64_t*)P.pg_base.p,
@@ -1808,11 +1798,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const int64_t*)P.tile_blk.p, (const int32_t*)tscr.p,
                            (const int64_t*)P.cp_base.p, (const int64_t*)P.pg_base.p,
                            (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
-                           (const float4*)P.ent_w.p, (uint32_t*)P.chunk_ptr.p,
-                           (uint32_t*)es2.p, (float4*)ew2.p);
+                           (uint32_t*)P.chunk_ptr.p, (uint32_t*)perm.p);
         HG_STEP(hipGetLastError());
-        std::swap(P.ent_slot, es2);
-        std::swap(P.ent_w, ew2);
         int64_t t3[3];
         HG_STEP(hipMemcpyAsync(&t3[0], (int64_t*)tbase3.p + P.ntiles, 8, hipMemcpyDeviceToHost, s));
         HG_STEP(hipMemcpyAsync(&t3[1], (int64_t*)P.tile_blk.p + P.ntiles, 8, hipMemcpyDeviceToHost,
@@ -1826,8 +1813,6 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         P.chunk_ptrs = t3[2];
         dev_free(slot2);
         dev_free(slot3);
-        dev_free(es2);
-        dev_free(ew2);
         dev_free(used);
         dev_free(newpos);
         dev_free(ctmp);
@@ -1842,6 +1827,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
                            (uint32_t*)P.chunk_ptr.p);
         HG_STEP(hipGetLastError());
+        // no slots, no entries: the block fills read no entry
+        HG_STEP(dev_alloc(perm, 4));
     }
     // chunk-major blocks for the channel kernels
     const bool grouped = P.opts.precision != HG_PREC_FP32;
@@ -1879,7 +1866,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
                                (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
                                (const int64_t*)P.pg_base.p, (const uint32_t*)P.ent_slot.p,
-                               (const float4*)P.ent_w.p, (const int64_t*)P.blk_base.p,
+                               (const float4*)P.ent_w.p, (const uint32_t*)perm.p,
+                               (const int64_t*)P.blk_base.p,
                                (uint16_t*)P.e3_w.p, (uint4*)P.e3_s.p);
             HG_STEP(hipGetLastError());
         }
@@ -1892,7 +1880,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
                                (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
                                (const int64_t*)P.pg_base.p, (const uint32_t*)P.ent_slot.p,
-                               (const float4*)P.ent_w.p, (const int64_t*)P.blk_base.p,
+                               (const float4*)P.ent_w.p, (const uint32_t*)perm.p,
+                               (const int64_t*)P.blk_base.p,
                                (float4*)P.e2_w.p, (uint4*)P.e2_s.p);
             HG_STEP(hipGetLastError());
         }

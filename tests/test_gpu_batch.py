@@ -239,7 +239,7 @@ def test_dense_fields_take_shorter_chunks(precision, first, tol):
     to the workloads with a few hundred neighbours per pixel); the 16-bit
     form keeps its 2e-3 gate."""
     rng = np.random.default_rng(77)
-    # 400,000 samples over the 1 x 1 deg field: a tile holds over 2048 chunks of
+    # 400,000 samples over the 1 x 1 deg field: a tile holds over 1024 chunks of
     # slots, so its slots stay in consecutive runs per chunk (dealing is for
     # lighter tiles), and a chunk near a tile's centre reaches all 64 groups
     n = 400_000
