@@ -140,11 +140,12 @@ def parity(V, Vr, cnt):
             "pixels": int(ok.sum())}
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, form=None):
     """HBM bytes per launch of the dominant kernel from the committed PMC
-    record in profiles/, or None when there is none or the sources it was
-    taken on (the kernel, and the setup that lays out its work) have changed
-    since the counters were taken."""
+    record in profiles/ (form: None for the record's own kernel, else a key
+    of the record such as "bf16_form"), or None when there is none or the
+    sources it was taken on (the kernel, and the setup that lays out its
+    work) have changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_channels_{workload}_traffic.json")
     if not os.path.exists(path):
@@ -152,6 +153,10 @@ def measured_traffic(workload):
     rec = json.load(open(path))
     for src, digest in rec["sources_sha256"].items():
         if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != digest:
+            return None
+    if form is not None:
+        rec = rec.get(form)
+        if rec is None:
             return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -346,6 +351,7 @@ def run_drift(args):
         rb["roofline"] = roofline(2.0 * sb["nnz"] * C, 2.0 * n * C + 4.0 * P * C,
                                   rb["channels_ms"], PEAK_F16_MFMA_TFLOPS,
                                   "k_channels (BF16 MFMA form)")
+        rb["roofline"]["traffic"] = measured_traffic("drift", "bf16_form")
         rb["speedup_vs_plain"] = {"step": ms_step / rb["ms_per_step"],
                                   "channels": ch_avg / rb["channels_ms"]}
         if not args.no_cpu_baseline:
