@@ -868,6 +868,20 @@ __global__ __launch_bounds__(256) void k_chunk_ptr(
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Several device buffers (whole dwords each) set to zero by one launch
+// instead of one runtime call apiece.
+struct ZeroList {
+    uint32_t* p[8];
+    int64_t dwords[8];
+    int32_t n;
+};
+__global__ __launch_bounds__(256) void k_zero(ZeroList z) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < z.n; k++)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.dwords[k]; i += stride)
+            z.p[k][i] = 0u;
+}
+
 // Slot compaction.  A tile's slots are every sample of its candidate cell runs;
 // those no pixel of the tile has in its support are dropped, so that the
 // channel kernel stages only samples it uses.  Slot order (ring, cell,
@@ -1262,6 +1276,12 @@ __global__ __launch_bounds__(256) void k_block_meta(
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
+    // launched over a bound on the block count: blocks past the real count
+    // (the last tile's end) hold nothing
+    if (b >= tile_blk[ntiles]) {
+        if (lane == 0) blk_cnt[b] = 0;
+        return;
+    }
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
     if (lane == 0) blk_tile[b] = (int32_t)r.tile;
@@ -1296,6 +1316,22 @@ __device__ inline int block_units(int n, int& first) {
     return __shfl(x, 63, 64);
 }
 
+// Entry-block fills read each group's entries through the bucket permutation,
+// so one tile's blocks (its chunks) read the same groups' lists scattered
+// over them.  The dispatcher deals workgroups round-robin over the 8 XCDs,
+// each with its own L2: the fills launch a multiple of 8 workgroups and
+// workgroup w takes run (w mod 8) x (grid / 8) + w / 8, so that runs of
+// consecutive blocks, one tile's chunks, read those lists through one L2.
+constexpr int FILL_XCDS = 8;
+__device__ inline int64_t fill_block(int lane_wave) {
+    const int64_t per = gridDim.x / FILL_XCDS;
+    const int64_t w = (int64_t)(blockIdx.x % FILL_XCDS) * per + blockIdx.x / FILL_XCDS;
+    return w * 4 + lane_wave;
+}
+inline unsigned fill_grid(int64_t n_blocks) {
+    return (unsigned)(((n_blocks + 4 * FILL_XCDS - 1) / (4 * FILL_XCDS)) * FILL_XCDS);
+}
+
 // One wave per block: lane l knows group l's run (first entry, count); the
 // block's units are then written flat, lane i taking units i and i + 64 of
 // each pass of 128 (coalesced writes; both units' loads in flight together).
@@ -1307,8 +1343,8 @@ __global__ __launch_bounds__(256) void k_block_fill(
     const float4* __restrict__ ent_w, const uint32_t* __restrict__ perm,
     const int64_t* __restrict__ blk_base,
     float4* __restrict__ e2_w, uint4* __restrict__ e2_s) {
-    int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
+    const int64_t b = fill_block(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
     const int64_t base = blk_base[b];
     BlockLane r = block_lane_at(b, blk_tile[b], lane, npgx, npgy, ntx, tile_blk, cp_base,
@@ -1370,7 +1406,13 @@ __global__ __launch_bounds__(256) void k_block_meta_g(
     int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff, int32_t* __restrict__ blk_tile) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
-    if (b >= n_blocks) return;
+    if (b >= n_blocks) return;  // uniform per wave
+    // launched over a bound on the block count: blocks past the real count
+    // (the last tile's end) hold nothing
+    if (b >= tile_blk[ntiles]) {
+        if (lane == 0) blk_cnt[b] = 0;
+        return;
+    }
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
     if (lane == 0) blk_tile[b] = (int32_t)r.tile;
@@ -1427,8 +1469,8 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
     const float4* __restrict__ ent_w, const uint32_t* __restrict__ perm,
     const int64_t* __restrict__ blk_base,
     uint16_t* __restrict__ e3_w, uint4* __restrict__ e3_s) {
-    int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
+    const int64_t b = fill_block(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
     const int64_t base = blk_base[b];
     BlockLane r = block_lane_at(b, blk_tile[b], lane, npgx, npgy, ntx, tile_blk, cp_base,
@@ -1496,7 +1538,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                     std::max<int64_t>(P.npg + 1, P.ntiles + 1));
     int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
 
-    DevBuf key, cnt, cursor, rows_t, rows_p, tslots, tcp, tnch, pcap, totals, bcnt, btile, wl;
+    DevBuf key, cnt, cursor, rows_t, tslots, tcp, tnch, pcap, totals, bcnt, btile, wl;
+    std::vector<RowInfo> rows_all;
     DevBuf used, newpos, ctmp, tbase2, slot2, tpad, tscr, tbase3, slot3, perm;
     // Buffers go back to the allocation cache, where a setup on another
     // stream may take them at once: the stream's work is drained first.
@@ -1520,7 +1563,6 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         dev_free(cnt);
         dev_free(cursor);
         dev_free(rows_t);
-        dev_free(rows_p);
         dev_free(tslots);
         dev_free(tcp);
         dev_free(pcap);
@@ -1557,8 +1599,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(P.cell_off, (size_t)(P.n_cells + 1) * 4));
     HG_STEP(dev_alloc(P.srt_idx, (size_t)n1 * 4));
     HG_STEP(dev_alloc(P.srt_coord, (size_t)n1 * sizeof(double4)));
-    HG_STEP(dev_alloc(rows_t, sizeof(RowInfo) * trows.size()));
-    HG_STEP(dev_alloc(rows_p, sizeof(RowInfo) * prows.size()));
+    HG_STEP(dev_alloc(rows_t, sizeof(RowInfo) * (trows.size() + prows.size())));
     HG_STEP(dev_alloc(P.tile_piece, sizeof(int4) * (size_t)(P.ntiles * npc_t)));
     HG_STEP(dev_alloc(tslots, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
     HG_STEP(dev_alloc(tcp, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
@@ -1577,18 +1618,36 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     int* flag = (int*)P.scratch.p;
     unsigned long long* nnz_total = (unsigned long long*)((char*)P.scratch.p + 8);
     int* blk_max = (int*)((char*)P.scratch.p + 16);  // most units in one block
+    int64_t* slot_total = (int64_t*)((char*)P.scratch.p + 24);  // after compaction
     void* scan_tmp = (char*)P.scratch.p + 64;
 
-    HG_STEP(hipMemsetAsync(P.scratch.p, 0, 64, s));
-    HG_STEP(hipMemsetAsync(cnt.p, 0, (size_t)(P.n_cells + 1) * 4, s));
-    HG_STEP(hipMemsetAsync(P.pix_count.p, 0, sizeof(int32_t) * (size_t)P.npix, s));
-    HG_STEP(hipMemsetAsync(P.pix_W.p, 0, sizeof(double) * (size_t)P.npix, s));
-    HG_STEP(hipMemsetAsync(P.pix_Wf.p, 0, sizeof(float) * (size_t)P.npix, s));
-    HG_STEP(hipMemsetAsync(P.pg_cnt.p, 0, sizeof(uint32_t) * (size_t)P.npg, s));
-    HG_STEP(hipMemcpyAsync(rows_t.p, trows.data(), sizeof(RowInfo) * trows.size(),
+    {
+        ZeroList z{};
+        const std::pair<void*, int64_t> bufs[] = {
+            {P.scratch.p, 16},
+            {cnt.p, P.n_cells + 1},
+            {P.pix_count.p, P.npix},
+            {P.pix_W.p, 2 * P.npix},
+            {P.pix_Wf.p, P.npix},
+            {P.pg_cnt.p, P.npg},
+            {wl.p, 1}};
+        int64_t most = 0;
+        for (const auto& b : bufs) {
+            z.p[z.n] = (uint32_t*)b.first;
+            z.dwords[z.n++] = b.second;
+            most = std::max(most, b.second);
+        }
+        hipLaunchKernelGGL(k_zero, dim3(std::max<unsigned>(1, std::min<unsigned>(2048, blocks_for(most, 256)))),
+                           dim3(256), 0, s, z);
+        HG_STEP(hipGetLastError());
+    }
+    // the planner's row tables, one copy for both (tile rows, then group
+    // rows); rows_all lives until setup has drained its stream
+    rows_all = trows;
+    rows_all.insert(rows_all.end(), prows.begin(), prows.end());
+    HG_STEP(hipMemcpyAsync(rows_t.p, rows_all.data(), sizeof(RowInfo) * rows_all.size(),
                            hipMemcpyHostToDevice, s));
-    HG_STEP(hipMemcpyAsync(rows_p.p, prows.data(), sizeof(RowInfo) * prows.size(),
-                           hipMemcpyHostToDevice, s));
+    const RowInfo* rows_p = (const RowInfo*)rows_t.p + trows.size();
 
     // 1-3: bin, count, look-up table, scatter, per-cell order, sorted coordinates
     if (n > 0) {
@@ -1605,7 +1664,6 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            (const uint32_t*)key.p, n, (uint32_t*)cursor.p, (uint32_t*)P.srt_idx.p);
         HG_STEP(hipGetLastError());
-        HG_STEP(hipMemsetAsync(wl.p, 0, 4, s));
         hipLaunchKernelGGL(k_cell_sort_small, dim3(blocks_for(P.n_cells, 256)), dim3(256), 0, s,
                            (const uint32_t*)P.cell_off.p, P.n_cells, (uint32_t*)P.srt_idx.p,
                            (uint32_t*)wl.p + 1, (uint32_t*)wl.p);
@@ -1642,7 +1700,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                                   (int64_t*)P.cp_base.p, (int64_t*)scan_tmp, s)));
         int64_t np = P.npg * P.pg_rings;
         hipLaunchKernelGGL(k_pg_plan, dim3(blocks_for(np, 256)), dim3(256), 0, s,
-                           (const RowInfo*)rows_p.p, (const RowInfo*)rows_t.p, P.npgx, P.npg,
+                           rows_p, (const RowInfo*)rows_t.p, P.npgx, P.npg,
                            P.ntx, P.pg_rings, P.tile_rings, P.nside, P.cell_base,
                            (const uint32_t*)P.cell_off.p, P.map, eps,
                            (const int4*)P.tile_piece.p, (int4*)P.pg_piece.p, flag);
@@ -1710,7 +1768,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(P.ent_slot, (size_t)(P.ent_cap ? P.ent_cap : 1) * 4));
     HG_STEP(dev_alloc(P.ent_w, (size_t)(P.ent_cap ? P.ent_cap : 1) * 16));
     HG_STEP(dev_alloc(P.chunk_ptr, (size_t)(P.chunk_ptrs ? P.chunk_ptrs : 1) * 4));
-    HG_STEP(dev_alloc(bcnt, sizeof(int64_t) * (size_t)(P.n_blocks + 1)));
+    // block sizes, then the partial sums of their scan (the block count is
+    // not bounded by the scans' shared partial-sum area)
+    const int64_t bscan_nb = (P.n_blocks + SCAN_B - 1) / SCAN_B + 1;
+    HG_STEP(dev_alloc(bcnt, sizeof(int64_t) * (size_t)(P.n_blocks + 1 + bscan_nb)));
     HG_STEP(dev_alloc(btile, sizeof(int32_t) * (size_t)(P.n_blocks + 1)));
     HG_STEP(dev_alloc(P.blk_base, sizeof(int64_t) * (size_t)(P.n_blocks + 1)));
     HG_STEP(dev_alloc(P.blk_pgoff, sizeof(uint16_t) * PGOFF_STRIDE * (size_t)(P.n_blocks + 1)));
@@ -1800,26 +1861,9 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
                            (uint32_t*)P.chunk_ptr.p, (uint32_t*)perm.p);
         HG_STEP(hipGetLastError());
-        int64_t t3[3];
-        HG_STEP(hipMemcpyAsync(&t3[0], (int64_t*)tbase3.p + P.ntiles, 8, hipMemcpyDeviceToHost, s));
-        HG_STEP(hipMemcpyAsync(&t3[1], (int64_t*)P.tile_blk.p + P.ntiles, 8, hipMemcpyDeviceToHost,
-                               s));
-        HG_STEP(hipMemcpyAsync(&t3[2], (int64_t*)P.cp_base.p + P.ntiles, 8, hipMemcpyDeviceToHost,
-                               s));
-        HG_STEP(hipStreamSynchronize(s));
-        // the later buffers were sized for the counts before compaction, which bound these
-        P.total_slots = t3[0];
-        P.n_blocks = t3[1];
-        P.chunk_ptrs = t3[2];
-        dev_free(slot2);
-        dev_free(slot3);
-        dev_free(used);
-        dev_free(newpos);
-        dev_free(ctmp);
-        dev_free(tbase2);
-        dev_free(tpad);
-        dev_free(tscr);
-        dev_free(tbase3);
+        // the slot total after padding: read back with the other sizes below
+        HG_STEP(hipMemcpyAsync(slot_total, (int64_t*)tbase3.p + P.ntiles, 8,
+                               hipMemcpyDeviceToDevice, s));
     } else {
         hipLaunchKernelGGL(k_chunk_ptr, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx,
                            P.npg, P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
@@ -1830,8 +1874,12 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         // no slots, no entries: the block fills read no entry
         HG_STEP(dev_alloc(perm, 4));
     }
-    // chunk-major blocks for the channel kernels
+    // chunk-major blocks for the channel kernels.  P.n_blocks still holds the
+    // count before compaction, a bound on the real one: the meta pass and
+    // the scan run over the bound (blocks past the real count hold nothing),
+    // so every size is read back with one synchronisation.
     const bool grouped = P.opts.precision != HG_PREC_FP32;
+    const bool compacted = P.total_slots > 0;
     if (P.n_blocks > 0) {
         hipLaunchKernelGGL(grouped ? k_block_meta_g : k_block_meta, dim3(blocks_for(P.n_blocks, 4)),
                            dim3(256), 0, s, P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks,
@@ -1845,15 +1893,36 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(hipGetLastError());
     }
     HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)bcnt.p, P.n_blocks,
-                                              (int64_t*)P.blk_base.p, (int64_t*)scan_tmp, s)));
+                                              (int64_t*)P.blk_base.p,
+                                              (int64_t*)bcnt.p + P.n_blocks + 1, s)));
     unsigned long long nz = 0;
-    int64_t n_ent = 0;
+    int64_t n_ent = 0, slots = 0, cps = 0;
+    int bmax = 0;
+    P.tile_blk_host.assign((size_t)P.ntiles + 1, 0);
     HG_STEP(hipMemcpyAsync(&nz, nnz_total, sizeof nz, hipMemcpyDeviceToHost, s));
     HG_STEP(hipMemcpyAsync(&n_ent, (int64_t*)P.blk_base.p + P.n_blocks, sizeof n_ent,
                            hipMemcpyDeviceToHost, s));
-    int bmax = 0;
     HG_STEP(hipMemcpyAsync(&bmax, blk_max, sizeof bmax, hipMemcpyDeviceToHost, s));
+    // per-tile chunk counts (the channel kernel's launch order) and sizes
+    HG_STEP(hipMemcpyAsync(P.tile_blk_host.data(), P.tile_blk.p, sizeof(int64_t) * (P.ntiles + 1),
+                           hipMemcpyDeviceToHost, s));
+    if (compacted) {
+        HG_STEP(hipMemcpyAsync(&slots, slot_total, 8, hipMemcpyDeviceToHost, s));
+        HG_STEP(hipMemcpyAsync(&cps, (int64_t*)P.cp_base.p + P.ntiles, 8, hipMemcpyDeviceToHost,
+                               s));
+    }
     HG_STEP(hipStreamSynchronize(s));
+    // The compaction's transient arrays go back to the allocation cache only
+    // now that the stream has drained: a setup on another stream (a batch
+    // sets fields up in parallel) may take them at once.
+    for (DevBuf* b : {&slot2, &slot3, &used, &newpos, &ctmp, &tbase2, &tpad, &tscr, &tbase3})
+        dev_free(*b);
+    if (compacted) {
+        // the buffers were sized for the counts before compaction, which bound these
+        P.total_slots = slots;
+        P.n_blocks = P.tile_blk_host[(size_t)P.ntiles];
+        P.chunk_ptrs = cps;
+    }
     P.nnz = (int64_t)nz;
     P.nnz_entries = n_ent;
     P.blk_max = bmax;
@@ -1861,7 +1930,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(P.e3_w, (size_t)(n_ent ? n_ent : 1) * 32));
         HG_STEP(dev_alloc(P.e3_s, (size_t)(n_ent ? n_ent : 1) * 16));
         if (P.n_blocks > 0) {
-            hipLaunchKernelGGL(k_block_fill_g, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_block_fill_g, dim3(fill_grid(P.n_blocks)), dim3(256), 0, s,
                                P.npgx, P.npgy, P.ntx, P.n_blocks, P.chunk, P.opts.precision,
                                (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
                                (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
@@ -1875,7 +1944,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(P.e2_w, (size_t)(n_ent ? n_ent : 1) * 64));
         HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 16));
         if (P.n_blocks > 0) {
-            hipLaunchKernelGGL(k_block_fill, dim3(blocks_for(P.n_blocks, 4)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_block_fill, dim3(fill_grid(P.n_blocks)), dim3(256), 0, s,
                                P.npgx, P.npgy, P.ntx, P.n_blocks, P.chunk,
                                (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
                                (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
@@ -1886,11 +1955,6 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
             HG_STEP(hipGetLastError());
         }
     }
-    // per-tile chunk counts for the channel kernel's launch order
-    P.tile_blk_host.assign((size_t)P.ntiles + 1, 0);
-    HG_STEP(hipMemcpyAsync(P.tile_blk_host.data(), P.tile_blk.p, sizeof(int64_t) * (P.ntiles + 1),
-                           hipMemcpyDeviceToHost, s));
-    HG_STEP(hipStreamSynchronize(s));
     cleanup();
     return hipSuccess;
 #undef HG_STEP
