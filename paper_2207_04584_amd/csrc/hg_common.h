@@ -151,6 +151,11 @@ struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
 };
+// page-locked host memory from the process-wide pool (runtime.hip)
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
 
 // The order in which the channel kernel's workgroups take a plan's (tile,
 // channel block) items, for one channel-block count: item b of the launch is
@@ -346,5 +351,7 @@ int grid_channels_host_noalloc(Plan& P, const void* host_values, int64_t ld, int
 // device memory (runtime.hip)
 hipError_t dev_alloc(DevBuf& b, size_t bytes);
 void dev_free(DevBuf& b);
+hipError_t host_alloc(HostBuf& b, size_t bytes);
+void host_free(HostBuf& b);
 
 }  // namespace hg

@@ -153,6 +153,45 @@ void dev_free(DevBuf& b) {
     b.bytes = 0;
 }
 
+// Page-locked host buffers for set-up's small transfers (row tables in,
+// sizes out), pooled by size for the life of the process: page-locking
+// costs more per call than the copies it speeds up, and copies to or from
+// pageable memory are staged by the runtime.  Portable: any device may copy
+// through them.
+namespace {
+std::multimap<size_t, void*> g_host_pool;
+}
+
+hipError_t host_alloc(HostBuf& b, size_t bytes) {
+    if (b.p) host_free(b);
+    const size_t g = 4096;
+    const size_t want = ((bytes ? bytes : 1) + g - 1) / g * g;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_host_pool.lower_bound(want);
+        if (it != g_host_pool.end() && it->first <= 4 * want) {
+            b.p = it->second;
+            b.bytes = it->first;
+            g_host_pool.erase(it);
+            return hipSuccess;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocPortable);
+    if (e != hipSuccess) return e;
+    b.p = p;
+    b.bytes = want;
+    return hipSuccess;
+}
+
+void host_free(HostBuf& b) {
+    if (!b.p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_host_pool.emplace(b.bytes, b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
 namespace {
 
 void plan_free(Plan& P) {

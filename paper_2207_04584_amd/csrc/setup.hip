@@ -168,26 +168,32 @@ struct RowInfo {
 };
 
 // 1. binning ------------------------------------------------------------------
-// counter[k] += 1 for every active lane with valid set, one atomic per
-// distinct key in the wave (consecutive samples of a scan share cells, and
-// per-lane atomics on one address serialise).  Returns each such lane the
-// counter's old value plus its rank among the wave's lanes with the same key:
-// distinct values, as separate atomics would give, in another order.
+// counter[k] += 1 for every lane with valid set: lanes in runs of equal keys
+// over consecutive lanes (a scan's consecutive samples share cells) take one
+// atomic per run, all runs in the same vector instruction, so a wave costs
+// one atomic round trip whatever its keys.  Returns each valid lane the
+// counter's old value plus its offset in its run: distinct values, as
+// separate atomics would give, in another order.
 __device__ inline uint32_t wave_atomic_inc(uint32_t* counter, uint32_t k, bool valid) {
     const int lane = threadIdx.x & 63;
-    uint64_t todo = __ballot(valid);
-    uint32_t result = 0;
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const uint32_t kl = (uint32_t)__shfl((int)k, leader, 64);
-        const uint64_t same = __ballot(valid && k == kl) & todo;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&counter[kl], (uint32_t)__popcll(same));
-        base = (uint32_t)__shfl((int)base, leader, 64);
-        if ((same >> lane) & 1ull) result = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
-        todo &= ~same;
+    const uint32_t kprev = (uint32_t)__shfl_up((int)k, 1, 64);
+    const uint64_t vmask = __ballot(valid);
+    const bool prev_valid = lane > 0 && ((vmask >> (lane - 1)) & 1ull);
+    const bool start = valid && (!prev_valid || kprev != k);
+    const uint64_t starts = __ballot(start);
+    // a run ends before the next start or the next invalid lane
+    const uint64_t stops = starts | ~vmask;
+    uint32_t base = 0;
+    if (start) {
+        const uint64_t after = lane == 63 ? 0ull : stops & ~((2ull << lane) - 1ull);
+        const int next = after ? __ffsll((long long)after) - 1 : 64;
+        base = atomicAdd(&counter[k], (uint32_t)(next - lane));
     }
-    return result;
+    // the run's first lane: the highest start at or below this lane
+    const uint64_t upto = lane == 63 ? starts : starts & ((2ull << lane) - 1ull);
+    const int first = upto ? 63 - __clzll((long long)upto) : lane;
+    const uint32_t b0 = (uint32_t)__shfl((int)base, first, 64);
+    return valid ? b0 + (uint32_t)(lane - first) : 0u;
 }
 
 __global__ void k_bin(const double* __restrict__ ra_deg, const double* __restrict__ dec_deg,
@@ -247,37 +253,100 @@ __device__ inline void sift_down(uint32_t* v, uint32_t root, uint32_t end) {
     }
 }
 
-// The atomic scatter leaves each cell's samples in arbitrary order; sorting
+// The atomic scatter leaves each cell's samples in arbitrary order; ordering
 // them by original index makes the key (cell, index) total and the layout
-// deterministic.  Cells of up to SMALL_CELL samples are sorted by one thread;
-// larger cells go to a worklist sorted one workgroup per cell.
-constexpr uint32_t SMALL_CELL = 16;
+// deterministic.  Single samples are copied; a cell of 2 .. RANK_CELL
+// samples is placed by rank, one wave per cell: the sample at position p of
+// cell c goes to off[c] + #{q in c : idx[q] < idx[p]} (sample indices are
+// distinct, so the ranks are a permutation of the cell), the cell held in
+// the wave's registers and each sample broadcast in turn.  Larger cells are
+// copied as they are and sorted by a workgroup each.
+constexpr int RANK_PER_LANE = 8;
+constexpr uint32_t RANK_CELL = 64 * RANK_PER_LANE;
+constexpr int RANK_WAVES = 4096;  // persistent waves over the cell list
 constexpr int BIG_SORT_T = 256;
 constexpr uint32_t BIG_SORT_MAX = 4096;
 
-__global__ void k_cell_sort_small(const uint32_t* __restrict__ off, int64_t n_cells,
-                                  uint32_t* __restrict__ idx, uint32_t* __restrict__ worklist,
-                                  uint32_t* __restrict__ wl_count) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    uint32_t a = off[c], b = off[c + 1];
-    uint32_t len = b - a;
-    if (len < 2) return;
-    if (len > SMALL_CELL) {
-        worklist[atomicAdd(wl_count, 1u)] = (uint32_t)c;
-        return;
+// one thread per cell: copy single samples, list the others (one atomic a wave)
+__global__ __launch_bounds__(256) void k_cell_list(const uint32_t* __restrict__ off,
+                                                   int64_t n_cells, const uint32_t* __restrict__ idx,
+                                                   uint32_t* __restrict__ idx2,
+                                                   uint32_t* __restrict__ list,
+                                                   uint32_t* __restrict__ list_count) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t len = 0, a = 0;
+    if (c < n_cells) {
+        a = off[c];
+        len = off[c + 1] - a;
     }
-    uint32_t* v = idx + a;
-    for (uint32_t t = 1; t < len; t++) {
-        uint32_t x = v[t];
-        uint32_t u = t;
-        while (u > 0 && v[u - 1] > x) {
-            v[u] = v[u - 1];
-            u--;
+    if (len == 1) idx2[a] = idx[a];
+    const bool many = len > 1;
+    const uint64_t m = __ballot(many);
+    if (!m) return;  // uniform
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(list_count, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    if (many) list[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)c;
+}
+
+// rank placement of one cell of m samples, 64 (NK - 1) < m <= 64 NK
+template <int NK>
+__device__ inline void rank_cell(const uint32_t* __restrict__ idx, uint32_t* __restrict__ idx2,
+                                 uint32_t a, uint32_t m, int lane) {
+    uint32_t v[NK], r[NK];
+#pragma unroll
+    for (int k = 0; k < NK; k++) {
+        const uint32_t q = (uint32_t)(k * 64 + lane);
+        v[k] = q < m ? idx[a + q] : 0xFFFFFFFFu;
+        r[k] = 0;
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < NK; k2++) {
+        const int lanes = k2 < NK - 1 ? 64 : (int)(m - (uint32_t)(64 * (NK - 1)));
+        for (int l2 = 0; l2 < lanes; l2++) {
+            const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v[k2], l2);
+#pragma unroll
+            for (int k = 0; k < NK; k++) r[k] += x < v[k] ? 1u : 0u;
         }
-        v[u] = x;
+    }
+#pragma unroll
+    for (int k = 0; k < NK; k++) {
+        const uint32_t q = (uint32_t)(k * 64 + lane);
+        if (q < m) idx2[a + r[k]] = v[k];
     }
 }
+
+__global__ __launch_bounds__(256) void k_cell_rank(
+    const uint32_t* __restrict__ off, const uint32_t* __restrict__ idx,
+    uint32_t* __restrict__ idx2, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ list_count, uint32_t* __restrict__ big,
+    uint32_t* __restrict__ big_count) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nlist = *list_count;
+    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < nlist;
+         w += gridDim.x * (blockDim.x >> 6)) {
+        // w is the wave's: every value below is uniform over it
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)list[w]);
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readfirstlane((int)off[c]);
+        const uint32_t m = (uint32_t)__builtin_amdgcn_readfirstlane((int)off[c + 1]) - a;
+        switch ((m + 63) / 64) {
+            case 1: rank_cell<1>(idx, idx2, a, m, lane); break;
+            case 2: rank_cell<2>(idx, idx2, a, m, lane); break;
+            case 3: rank_cell<3>(idx, idx2, a, m, lane); break;
+            case 4: rank_cell<4>(idx, idx2, a, m, lane); break;
+            case 5: rank_cell<5>(idx, idx2, a, m, lane); break;
+            case 6: rank_cell<6>(idx, idx2, a, m, lane); break;
+            case 7: rank_cell<7>(idx, idx2, a, m, lane); break;
+            case 8: rank_cell<8>(idx, idx2, a, m, lane); break;
+            default:
+                for (uint32_t q = lane; q < m; q += 64) idx2[a + q] = idx[a + q];
+                if (lane == 0) big[atomicAdd(big_count, 1u)] = c;
+        }
+    }
+}
+static_assert(RANK_CELL == 8 * 64, "k_cell_rank's cases cover cells up to RANK_CELL samples");
 
 // One workgroup per listed cell: bitonic sort in LDS (padded to a power of
 // two with UINT32_MAX); cells beyond BIG_SORT_MAX fall back to a heap sort.
@@ -1491,6 +1560,27 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
     }
 }
 
+// The sizes the host reads once the entry blocks are laid out, gathered for
+// one copy: [0] neighbour pairs, [1] entry units, [2] units in the largest
+// block, [3] slots after compaction, [4] chunk pointers, then the per-tile
+// block offsets tile_blk[0 .. ntiles].
+constexpr int64_t PACK_HEAD = 5;
+__global__ __launch_bounds__(256) void k_pack_sizes(
+    const unsigned long long* __restrict__ nnz, const int64_t* __restrict__ units,
+    const int* __restrict__ blk_max, const int64_t* __restrict__ slots,
+    const int64_t* __restrict__ cps, const int64_t* __restrict__ tile_blk, int64_t ntiles,
+    int64_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= ntiles) out[PACK_HEAD + i] = tile_blk[i];
+    if (i == 0) {
+        out[0] = (int64_t)*nnz;
+        out[1] = *units;
+        out[2] = *blk_max;
+        out[3] = *slots;
+        out[4] = *cps;
+    }
+}
+
 // small kernel: gather the totals the host needs to size the second stage
 __global__ void k_totals(const uint32_t* cell_off, int64_t n_cells, const int64_t* tile_base,
                          int64_t ntiles, const int64_t* pg_base, int64_t npg,
@@ -1538,8 +1628,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                     std::max<int64_t>(P.npg + 1, P.ntiles + 1));
     int64_t scan_nb = (big + SCAN_B - 1) / SCAN_B + 1;
 
-    DevBuf key, cnt, cursor, rows_t, tslots, tcp, tnch, pcap, totals, bcnt, btile, wl;
-    std::vector<RowInfo> rows_all;
+    DevBuf key, srt2, cnt, cursor, rows_t, sizes, tslots, tcp, tnch, pcap, totals, bcnt, btile, wl;
+    HostBuf hbuf;  // page-locked: row tables in, sizes out
     DevBuf used, newpos, ctmp, tbase2, slot2, tpad, tscr, tbase3, slot3, perm;
     // Buffers go back to the allocation cache, where a setup on another
     // stream may take them at once: the stream's work is drained first.
@@ -1560,6 +1650,9 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         dev_free(bcnt);
         dev_free(btile);
         dev_free(key);
+        dev_free(srt2);
+        dev_free(sizes);
+        host_free(hbuf);
         dev_free(cnt);
         dev_free(cursor);
         dev_free(rows_t);
@@ -1579,8 +1672,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     const int64_t n1 = n ? n : 1;
     if (P.opts.device_mem_cap > 0) {
         // first-stage footprint, checked before anything is allocated
-        size_t need = 64 + (size_t)scan_nb * 8 + 64 + (size_t)n1 * (4 + 4 + sizeof(double4)) +
-                      (size_t)(P.n_cells + 1) * 12 + sizeof(RowInfo) * (trows.size() + prows.size()) +
+        size_t need = 64 + (size_t)scan_nb * 8 + 64 + (size_t)n1 * (4 + 4 + 4 + sizeof(double4)) +
+                      (size_t)(P.n_cells + 1) * 20 + sizeof(RowInfo) * (trows.size() + prows.size()) +
                       sizeof(int4) * (size_t)(P.ntiles * npc_t + P.npg * npc_p) +
                       sizeof(int64_t) * (size_t)(4 * (P.ntiles + 1) + 2 * (P.npg + 1)) +
                       4 * (size_t)P.npg + 16 * (size_t)P.npix;
@@ -1593,9 +1686,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(P.scratch, 64 + (size_t)scan_nb * 8));
     HG_STEP(dev_alloc(totals, 64));
     HG_STEP(dev_alloc(key, (size_t)n1 * 4));
+    HG_STEP(dev_alloc(srt2, (size_t)n1 * 4));
     HG_STEP(dev_alloc(cnt, (size_t)(P.n_cells + 1) * 4));
     HG_STEP(dev_alloc(cursor, (size_t)(P.n_cells + 1) * 4));
-    HG_STEP(dev_alloc(wl, (size_t)(P.n_cells + 2) * 4));  // [0] count, then cell ids
+    HG_STEP(dev_alloc(wl, (size_t)(2 * P.n_cells + 2) * 4));  // two counts, two cell lists
     HG_STEP(dev_alloc(P.cell_off, (size_t)(P.n_cells + 1) * 4));
     HG_STEP(dev_alloc(P.srt_idx, (size_t)n1 * 4));
     HG_STEP(dev_alloc(P.srt_coord, (size_t)n1 * sizeof(double4)));
@@ -1630,7 +1724,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
             {P.pix_W.p, 2 * P.npix},
             {P.pix_Wf.p, P.npix},
             {P.pg_cnt.p, P.npg},
-            {wl.p, 1}};
+            {wl.p, 2}};
         int64_t most = 0;
         for (const auto& b : bufs) {
             z.p[z.n] = (uint32_t*)b.first;
@@ -1642,11 +1736,15 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(hipGetLastError());
     }
     // the planner's row tables, one copy for both (tile rows, then group
-    // rows); rows_all lives until setup has drained its stream
-    rows_all = trows;
-    rows_all.insert(rows_all.end(), prows.begin(), prows.end());
-    HG_STEP(hipMemcpyAsync(rows_t.p, rows_all.data(), sizeof(RowInfo) * rows_all.size(),
-                           hipMemcpyHostToDevice, s));
+    // rows) from page-locked memory, which also receives the sizes read
+    // back below (stream order puts those copies after this one)
+    const size_t rows_bytes = sizeof(RowInfo) * (trows.size() + prows.size());
+    const size_t back_off = (rows_bytes + 63) / 64 * 64;
+    HG_STEP(host_alloc(hbuf, back_off + sizeof(int64_t) * (size_t)(PACK_HEAD + P.ntiles + 1)));
+    int64_t* back = (int64_t*)((char*)hbuf.p + back_off);
+    std::copy(trows.begin(), trows.end(), (RowInfo*)hbuf.p);
+    std::copy(prows.begin(), prows.end(), (RowInfo*)hbuf.p + trows.size());
+    HG_STEP(hipMemcpyAsync(rows_t.p, hbuf.p, rows_bytes, hipMemcpyHostToDevice, s));
     const RowInfo* rows_p = (const RowInfo*)rows_t.p + trows.size();
 
     // 1-3: bin, count, look-up table, scatter, per-cell order, sorted coordinates
@@ -1664,13 +1762,22 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            (const uint32_t*)key.p, n, (uint32_t*)cursor.p, (uint32_t*)P.srt_idx.p);
         HG_STEP(hipGetLastError());
-        hipLaunchKernelGGL(k_cell_sort_small, dim3(blocks_for(P.n_cells, 256)), dim3(256), 0, s,
-                           (const uint32_t*)P.cell_off.p, P.n_cells, (uint32_t*)P.srt_idx.p,
-                           (uint32_t*)wl.p + 1, (uint32_t*)wl.p);
+        // wl: [0] listed cells, [1] big cells, then the two lists
+        uint32_t* list = (uint32_t*)wl.p + 2;
+        uint32_t* big = list + P.n_cells;
+        hipLaunchKernelGGL(k_cell_list, dim3(blocks_for(P.n_cells, 256)), dim3(256), 0, s,
+                           (const uint32_t*)P.cell_off.p, P.n_cells, (const uint32_t*)P.srt_idx.p,
+                           (uint32_t*)srt2.p, list, (uint32_t*)wl.p);
         HG_STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_cell_rank, dim3(RANK_WAVES / 4), dim3(256), 0, s,
+                           (const uint32_t*)P.cell_off.p, (const uint32_t*)P.srt_idx.p,
+                           (uint32_t*)srt2.p, (const uint32_t*)list, (const uint32_t*)wl.p, big,
+                           (uint32_t*)wl.p + 1);
+        HG_STEP(hipGetLastError());
+        std::swap(P.srt_idx, srt2);
         hipLaunchKernelGGL(k_cell_sort_big, dim3(1024), dim3(BIG_SORT_T), 0, s,
                            (const uint32_t*)P.cell_off.p, (uint32_t*)P.srt_idx.p,
-                           (const uint32_t*)wl.p + 1, (const uint32_t*)wl.p);
+                           (const uint32_t*)big, (const uint32_t*)wl.p + 1);
         HG_STEP(hipGetLastError());
         hipLaunchKernelGGL(k_sorted_coords_dev, dim3(blocks_for(n, 256)), dim3(256), 0, s, ra_deg,
                            dec_deg, (const uint32_t*)P.srt_idx.p,
@@ -1716,9 +1823,10 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                        P.npg, (const int64_t*)P.cp_base.p, (const int64_t*)P.tile_blk.p,
                        (const int*)flag, (int64_t*)totals.p);
     HG_STEP(hipGetLastError());
-    int64_t tot[6];
-    HG_STEP(hipMemcpyAsync(tot, totals.p, sizeof tot, hipMemcpyDeviceToHost, s));
+    HG_STEP(hipMemcpyAsync(back, totals.p, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HG_STEP(hipStreamSynchronize(s));
+    int64_t tot[6];
+    std::copy(back, back + 6, tot);
     P.n_used = tot[0];
     P.total_slots = tot[1];
     P.ent_cap = tot[2];
@@ -1895,37 +2003,33 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)bcnt.p, P.n_blocks,
                                               (int64_t*)P.blk_base.p,
                                               (int64_t*)bcnt.p + P.n_blocks + 1, s)));
-    unsigned long long nz = 0;
-    int64_t n_ent = 0, slots = 0, cps = 0;
-    int bmax = 0;
-    P.tile_blk_host.assign((size_t)P.ntiles + 1, 0);
-    HG_STEP(hipMemcpyAsync(&nz, nnz_total, sizeof nz, hipMemcpyDeviceToHost, s));
-    HG_STEP(hipMemcpyAsync(&n_ent, (int64_t*)P.blk_base.p + P.n_blocks, sizeof n_ent,
+    HG_STEP(dev_alloc(sizes, sizeof(int64_t) * (size_t)(PACK_HEAD + P.ntiles + 1)));
+    hipLaunchKernelGGL(k_pack_sizes, dim3(blocks_for(P.ntiles + 1, 256)), dim3(256), 0, s,
+                       (const unsigned long long*)nnz_total, (const int64_t*)P.blk_base.p + P.n_blocks,
+                       (const int*)blk_max, (const int64_t*)slot_total,
+                       (const int64_t*)P.cp_base.p + P.ntiles, (const int64_t*)P.tile_blk.p,
+                       P.ntiles, (int64_t*)sizes.p);
+    HG_STEP(hipGetLastError());
+    HG_STEP(hipMemcpyAsync(back, sizes.p, sizeof(int64_t) * (size_t)(PACK_HEAD + P.ntiles + 1),
                            hipMemcpyDeviceToHost, s));
-    HG_STEP(hipMemcpyAsync(&bmax, blk_max, sizeof bmax, hipMemcpyDeviceToHost, s));
-    // per-tile chunk counts (the channel kernel's launch order) and sizes
-    HG_STEP(hipMemcpyAsync(P.tile_blk_host.data(), P.tile_blk.p, sizeof(int64_t) * (P.ntiles + 1),
-                           hipMemcpyDeviceToHost, s));
-    if (compacted) {
-        HG_STEP(hipMemcpyAsync(&slots, slot_total, 8, hipMemcpyDeviceToHost, s));
-        HG_STEP(hipMemcpyAsync(&cps, (int64_t*)P.cp_base.p + P.ntiles, 8, hipMemcpyDeviceToHost,
-                               s));
-    }
     HG_STEP(hipStreamSynchronize(s));
     // The compaction's transient arrays go back to the allocation cache only
     // now that the stream has drained: a setup on another stream (a batch
     // sets fields up in parallel) may take them at once.
     for (DevBuf* b : {&slot2, &slot3, &used, &newpos, &ctmp, &tbase2, &tpad, &tscr, &tbase3})
         dev_free(*b);
+    // per-tile block offsets: the channel kernel's launch order
+    P.tile_blk_host.assign(back + PACK_HEAD, back + PACK_HEAD + P.ntiles + 1);
     if (compacted) {
         // the buffers were sized for the counts before compaction, which bound these
-        P.total_slots = slots;
+        P.total_slots = back[3];
         P.n_blocks = P.tile_blk_host[(size_t)P.ntiles];
-        P.chunk_ptrs = cps;
+        P.chunk_ptrs = back[4];
     }
-    P.nnz = (int64_t)nz;
-    P.nnz_entries = n_ent;
-    P.blk_max = bmax;
+    P.nnz = back[0];
+    P.nnz_entries = back[1];
+    P.blk_max = (int)back[2];
+    const int64_t n_ent = P.nnz_entries;
     if (grouped) {
         HG_STEP(dev_alloc(P.e3_w, (size_t)(n_ent ? n_ent : 1) * 32));
         HG_STEP(dev_alloc(P.e3_s, (size_t)(n_ent ? n_ent : 1) * 16));
