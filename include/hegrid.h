@@ -123,11 +123,14 @@ typedef struct {
     int32_t precision;      /* HG_PREC_*; 0 = HG_PREC_FP32.  A BF16 / FP16 plan
                                grids values of that type only                   */
     int32_t nside;          /* HEALPix resolution of the sky cells; 0 = auto    */
-    int32_t chunk;          /* tile slots staged per step, a multiple of 8 up to 64;
-                               0 = the longest that fits (48 for the FP32 form, 64 for
-                               the 16-bit forms, shorter for very dense fields).  An
-                               explicit chunk whose densest entry block would not fit
-                               two staged chunks in LDS fails (HG_ERR_UNSUPPORTED)  */
+    int32_t chunk;          /* tile slots staged per step, a multiple of 8 up to 64
+                               (FP32 form, 1 KB rows) or 112 (16-bit forms, 512 B
+                               rows), else HG_ERR_ARG; 0 = the longest that fits (56
+                               for the FP32 form, 112 for the 16-bit forms -- 64 for
+                               a batch's fields --, shorter for dense fields).  An explicit chunk whose densest
+                               entry block would not fit two staged chunks in LDS,
+                               or (past 64 slots) where one pixel group takes more
+                               than 64 entries of a chunk, fails (HG_ERR_UNSUPPORTED) */
     int32_t waves;          /* channel kernel: waves per workgroup, 8 or 16; 0 = 16.
                                The waves share the tile's 64 pixel groups       */
     int64_t device_mem_cap; /* bytes; 0 = none.  Setup fails with HG_ERR_NOMEM

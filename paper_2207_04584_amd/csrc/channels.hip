@@ -46,6 +46,13 @@ constexpr int TILE_PX = TILE_PGX * PG;  // 16 pixels per tile side
 constexpr int FORM_F32 = 0;  // FP32 values in LDS, one entry per MFMA
 constexpr int FORM_M16 = 1;  // 16-bit values in LDS, groups of four entries per MFMA
 
+// Longest chunk a form stages: the FP32 form's 1 KB rows fill LDS with two
+// chunks of 64; the 16-bit forms' rows are half as long.
+template <int FORM>
+constexpr int max_chunk() {
+    return FORM == FORM_F32 ? 64 : MAX_CHUNK;
+}
+
 template <int FORM, int G>
 struct Form {
     static constexpr int VB = FORM == FORM_F32 ? 4 : 2;   // bytes per staged value
@@ -65,7 +72,7 @@ struct Form {
 template <int FORM, int G, int WAVES>
 struct Rows {
     static constexpr int RPI = Form<FORM, G>::RPI;
-    static constexpr int GPW = (MAX_CHUNK / RPI + WAVES - 1) / WAVES;  // row groups per wave
+    static constexpr int GPW = (max_chunk<FORM>() / RPI + WAVES - 1) / WAVES;  // row groups per wave
     static constexpr int NRW = GPW * RPI;                              // rows per wave
 };
 
@@ -76,10 +83,18 @@ struct Rows {
 constexpr int LDS_BYTES = 160 * 1024;
 constexpr int MAX_NBUF = 4;
 // Chunk metadata ring: two halves of 16 chunks, each chunk's staged-row sample
-// indices (MAX_CHUNK x uint32) and the 17 entry-block offsets of a half.
+// indices (up to the form's longest chunk, uint32) and the 17 entry-block
+// offsets of a half.
 constexpr int META_RUN = 16;
-constexpr int META_ROWS = 2 * META_RUN * MAX_CHUNK * 4;
-constexpr int META_LDS = META_ROWS + 2 * (META_RUN + 1) * 8 + TILE_PGS;  // + the group map
+template <int FORM>
+constexpr int meta_rows() {
+    return 2 * META_RUN * max_chunk<FORM>() * 4;
+}
+template <int FORM>
+constexpr int meta_lds() {
+    return meta_rows<FORM>() + 2 * (META_RUN + 1) * 8 + TILE_PGS;  // + the group map
+}
+inline int meta_lds(bool m16) { return m16 ? meta_lds<FORM_M16>() : meta_lds<FORM_F32>(); }
 
 struct LdsLayout {
     int vals, ew, es, po, stride;
@@ -372,7 +387,8 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     const uint32_t* sidx = slot_idx + s_base;
 
     char* ring_rows = smem + nbuf * L.stride;
-    char* ring_blk = ring_rows + META_ROWS;
+    constexpr int MAXC = max_chunk<FORM>();
+    char* ring_blk = ring_rows + meta_rows<FORM>();
     uint8_t* gmap = (uint8_t*)(ring_blk + 2 * (META_RUN + 1) * 8);
     // Which pixel groups each wave owns.  Balanced: within each quadrant of
     // 4 x 4 groups, the groups are ranked by their entry count (all chunks)
@@ -437,7 +453,7 @@ __device__ __attribute__((always_inline)) inline void grid_item(
     auto meta_of = [&](int64_t ch) {
         Meta m;
         const int h = (int)((ch / META_RUN) & 1), j = (int)(ch % META_RUN);
-        const uint32_t* rr = (const uint32_t*)(ring_rows) + (h * META_RUN + j) * MAX_CHUNK;
+        const uint32_t* rr = (const uint32_t*)(ring_rows) + (h * META_RUN + j) * MAXC;
         const char* bb = ring_blk + (h * (META_RUN + 1) + j) * 8;
         int64_t s0 = ch * chunk;
         int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
@@ -451,9 +467,9 @@ __device__ __attribute__((always_inline)) inline void grid_item(
         return m;
     };
     // Copy the metadata of chunks [c0, c0 + 16) into ring half h: wave w the
-    // row indices of chunks c0 + w, c0 + w + WAVES, ..., wave 0 also the 17
-    // block offsets.  Returns the copies this wave issued (each has at least
-    // one active lane).
+    // row indices of chunks c0 + w, c0 + w + WAVES, ... (64 a copy), wave 0
+    // also the 17 block offsets.  Returns the copies this wave issued (each
+    // has at least one active lane).
     auto refill = [&](int64_t c0, int h) {
         int k = 0;
 #pragma unroll
@@ -463,9 +479,15 @@ __device__ __attribute__((always_inline)) inline void grid_item(
             if (c < nch) {
                 const int64_t s0 = c * chunk;
                 const int ns = (int)((nslots - s0) < chunk ? (nslots - s0) : chunk);
-                if (lane < ns)
-                    dma4s(sidx + s0, 4u * lane, ring_rows + (h * META_RUN + j) * MAX_CHUNK * 4);
-                k++;
+#pragma unroll
+                for (int part = 0; part < MAXC; part += 64) {
+                    if (part < ns) {
+                        if (lane < ns - part)
+                            dma4s(sidx + s0 + part, 4u * lane,
+                                  ring_rows + ((h * META_RUN + j) * MAXC + part) * 4);
+                        k++;
+                    }
+                }
             }
         }
         if (wave == 0) {
@@ -627,6 +649,7 @@ __device__ __attribute__((always_inline)) inline void grid_item(
             const int q = lane & 3;
             const uint32_t slot_lane = slK[k];
             if constexpr (FORM == FORM_F32) {
+                static_assert(max_chunk<FORM_F32>() <= 64, "a run's slots fit the wave's lanes");
                 // Each entry's slot comes from v_readlane into a scalar
                 // register, so the value read needs no second LDS round trip.
                 // Entries go a unit (four) at a time: one 16-byte read brings
@@ -686,7 +709,10 @@ __device__ __attribute__((always_inline)) inline void grid_item(
                 }
             } else {
                 // groups of four entries, slots picked by v_readlane, the
-                // next group's reads issued ahead of this group's MFMAs
+                // next group's reads issued ahead of this group's MFMAs.  A
+                // lane holds one entry's slot: setup builds chunks past 64
+                // slots only where no group's run in a chunk exceeds 64
+                // entries.
                 typedef typename VH<G>::T VT;
                 const char* vl = vals + lane * (G * 2);
                 auto ldv = [&](int j) {
@@ -818,7 +844,7 @@ size_t lds_stride(bool m16, int chunk, int ucap, int g) {
 
 void lds_plan(bool m16, int chunk, int blk_max, int g, int32_t& ucap, int32_t& nbuf) {
     ucap = (blk_max < 4 ? 4 : (blk_max + 3) / 4 * 4);
-    nbuf = (int32_t)((LDS_BYTES - META_LDS) / lds_stride(m16, chunk, ucap, g));
+    nbuf = (int32_t)((LDS_BYTES - meta_lds(m16)) / lds_stride(m16, chunk, ucap, g));
     if (nbuf > MAX_NBUF) nbuf = MAX_NBUF;
     if (nbuf < 2) nbuf = 2;  // not reached: setup checks the fit for the widest block
 }
@@ -829,7 +855,7 @@ size_t out_lds(int g) {
 }
 
 size_t lds_shm(bool m16, int chunk, int ucap, int nbuf, int g) {
-    size_t shm = (size_t)nbuf * lds_stride(m16, chunk, ucap, g) + META_LDS;
+    size_t shm = (size_t)nbuf * lds_stride(m16, chunk, ucap, g) + meta_lds(m16);
     return shm < out_lds(g) ? out_lds(g) : shm;
 }
 
@@ -984,7 +1010,8 @@ hipError_t launch_channels_plain_order(Plan& P, const void* values, int64_t ld, 
 bool channel_lds_fits(bool m16, int chunk, int blk_max) {
     int32_t ucap, nbuf;
     lds_plan(m16, chunk, blk_max, 4, ucap, nbuf);
-    return (size_t)2 * lds_stride(m16, chunk, ucap, 4) + META_LDS <= (size_t)LDS_BYTES;
+    if (!m16 && chunk > max_chunk<FORM_F32>()) return false;
+    return (size_t)2 * lds_stride(m16, chunk, ucap, 4) + meta_lds(m16) <= (size_t)LDS_BYTES;
 }
 
 size_t field_lds_bytes(const FieldDesc& d, bool m16, Shape shape) {

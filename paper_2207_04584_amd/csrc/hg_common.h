@@ -28,7 +28,7 @@ constexpr int TILE_PGS = TILE_PGX * TILE_PGY;
 constexpr uint32_t SLOT_MASK = 0x0FFFFFFFu;  // low 28 bits: tile-local slot
 constexpr int SLOT_SHIFT = 28;               // high 4 bits: in-support mask
 constexpr int PGOFF_STRIDE = 68;             // uint16 per block: 65 offsets, padded to 136 B
-constexpr int MAX_CHUNK = 64;                // tile slots per staged chunk, upper bound
+constexpr int MAX_CHUNK = 112;               // tile slots per staged chunk, upper bound
 
 // ---------------------------------------------------------------------------
 // HEALPix RING scheme (Gorski et al. 2005; the partition used by the paper's
@@ -218,6 +218,7 @@ struct Plan {
     // chunk-major entry blocks: block b = (tile t, chunk c), b = tile_blk[t] + c
     int64_t n_blocks = 0;
     int32_t blk_max = 0;  // most units (entries, or groups of four) in one block
+    int32_t run_max = 0;  // longest (group, chunk) run of entries if over 64, else 0
     DevBuf tile_blk;     // int64 [ntiles+1] first block of each tile
     std::vector<int64_t> tile_blk_host;       // the same, on the host (launch order costs)
     std::map<int32_t, LaunchOrder> orders;    // launch orders by channel-block count
@@ -333,6 +334,8 @@ Shape effective_shape(bool m16, int32_t dtype, bool vec, Shape s);
 BatchKernelInfo batch_kernel(bool m16, int32_t dtype, bool vec, size_t shm, Shape shape);
 size_t field_lds_bytes(const FieldDesc& d, bool m16, Shape shape);
 bool channel_lds_fits(bool m16, int chunk, int blk_max);
+// the channel kernel holds a run's slots one a lane: runs of at most 64 entries
+inline bool channel_runs_fit(int chunk, int run_max) { return chunk <= 64 || run_max <= 64; }
 hipError_t launch_ang2pix(int64_t nside, const double* ra_deg, const double* dec_deg, int64_t n,
                           int64_t* pix, hipStream_t s);
 

@@ -336,7 +336,9 @@ int validate_setup(const double* ra, const double* dec, int64_t n, const hg_kern
         if (o->nside < 0 || o->nside > 16384 || (o->nside & (o->nside - 1)))
             return fail(HG_ERR_ARG, "nside must be 0 or a power of two <= 16384");
         if (o->chunk != 0 && (o->chunk < 8 || o->chunk > MAX_CHUNK || o->chunk % 8))
-            return fail(HG_ERR_ARG, "chunk must be 0 or a multiple of 8 in [8, 64]");
+            return fail(HG_ERR_ARG, "chunk must be 0 or a multiple of 8 in [8, 112]");
+        if (o->chunk > 64 && o->precision == HG_PREC_FP32)
+            return fail(HG_ERR_ARG, "the FP32 form stages at most 64 slots a chunk");
         if (o->device_mem_cap < 0) return fail(HG_ERR_ARG, "device_mem_cap must be >= 0");
         if (o->waves != 0 && o->waves != 8 && o->waves != 16)
             return fail(HG_ERR_ARG, "waves must be 0, 8 or 16");
@@ -352,7 +354,8 @@ std::vector<BatchItem> plan_batch_items(const std::vector<std::vector<int64_t>>&
 
 // Setup proper, after validation (shared by hg_grid_setup and hg_batch_create).
 int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_kernel* k,
-              const hg_map* m, const hg_opts* o, hipStream_t s, hg_plan** out) {
+              const hg_map* m, const hg_opts* o, hipStream_t s, hg_plan** out,
+              bool batch_field = false) {
     auto t0 = std::chrono::steady_clock::now();
     hg_plan* h = new hg_plan();
     Plan& P = h->P;
@@ -382,13 +385,17 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     // Chunk length: the caller's, or the longest of a list that still fits two
     // staged chunks of the plan's densest entry block in LDS (longer chunks
     // mean fewer synchronisations per tile; the fit is known only once the
-    // blocks are built, so a plan that does not fit is rebuilt shorter).
+    // blocks are built, so a plan that does not fit is rebuilt shorter).  A
+    // batch's fields start at 64 slots: their set-ups run side by side and
+    // dense fields, which 112 slots do not fit, would each be set up again.
     const bool m16 = P.opts.precision != HG_PREC_FP32;
     std::vector<int32_t> chunks;
     if (o && o->chunk)
         chunks = {o->chunk};
-    else if (m16)
+    else if (m16 && batch_field)
         chunks = {64, 48, 32, 16, 8};
+    else if (m16)
+        chunks = {112, 88, 64, 48, 32, 16, 8};
     else
         chunks = {56, 48, 32, 16, 8};
     for (size_t ci = 0; ci < chunks.size(); ci++) {
@@ -406,13 +413,17 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
             delete h;
             return fail(status, err);
         }
-        if (channel_lds_fits(m16, P.chunk, P.blk_max)) break;
+        const bool lds_ok = channel_lds_fits(m16, P.chunk, P.blk_max);
+        const bool runs_ok = channel_runs_fit(P.chunk, P.run_max);
+        if (lds_ok && runs_ok) break;
         plan_free(P);
         if (ci + 1 == chunks.size()) {
             delete h;
             return fail(HG_ERR_UNSUPPORTED,
-                        "the densest entry block does not fit two staged chunks in LDS; use a "
-                        "smaller chunk");
+                        !lds_ok ? "the densest entry block does not fit two staged chunks in "
+                                  "LDS; use a smaller chunk"
+                                : "a pixel group takes more than 64 entries of one chunk; use a "
+                                  "chunk of at most 64 slots");
         }
     }
     P.setup_ms =
@@ -503,7 +514,8 @@ int setup_fields(hg_batch* b, const hg_field* fields, int32_t nfields, const hg_
             const hg_field& f = fields[i];
             const int r = guarded([&]() -> int {
                 hg_plan* h = nullptr;
-                int r2 = make_plan(f.ra_deg, f.dec_deg, f.n, &f.kernel, &f.map, &po, ws, &h);
+                int r2 = make_plan(f.ra_deg, f.dec_deg, f.n, &f.kernel, &f.map, &po, ws, &h,
+                                   true);
                 if (r2) return r2;
                 plans[i] = h;
                 h->owned_by_batch = true;

@@ -697,9 +697,11 @@ __device__ inline double kernel_weight(const KernelArgs& ka, double d2, const Pa
 // map is a HEALPix patch, whose two rows have their own pixel RAs.
 constexpr int GATHER_WAVES = 4;
 constexpr int BUCKET_WAVES = 4;
-// tiles with at most this many chunks are dealt (chunk = compacted slot mod
-// the chunk count); denser tiles keep consecutive slots per chunk
-constexpr int SCRAMBLE_MAX_NCH = 1024;
+// tiles whose chunks' presence words (one 64-bit word per 64 positions of a
+// chunk) number at most this many are dealt (chunk = compacted slot mod the
+// chunk count); denser tiles keep consecutive slots per chunk
+constexpr int SCRAMBLE_MAX_WORDS = 1024;
+__host__ __device__ inline int chunk_words(int32_t chunk) { return (chunk + 63) / 64; }
 
 template <bool SMALL, int KT, bool HPX>
 __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
@@ -1002,7 +1004,8 @@ __global__ void k_tile_rebase(const int64_t* __restrict__ tile_base, int64_t nti
     // that every chunk samples the whole tile (a run of consecutive slots
     // lies in one or two sky cells, i.e. in a few pixel groups only); the
     // chunks' unused tail slots are padding.
-    const bool scr = nch >= 2 && nch <= SCRAMBLE_MAX_NCH && nch * chunk <= (int64_t)SLOT_MASK;
+    const bool scr = nch >= 2 && nch * chunk_words(chunk) <= SCRAMBLE_MAX_WORDS &&
+                     nch * chunk <= (int64_t)SLOT_MASK;
     tile_scr[t] = scr ? 1 : 0;
     tile_pad[t] = scr ? nch * chunk : ns;
 }
@@ -1086,10 +1089,11 @@ __global__ __launch_bounds__(256) void k_deal_slots(
 // Entries bucketed by chunk, one wave per pixel group.  A dealt tile's
 // entries leave the remap in ascending compacted slot, i.e. with chunks
 // interleaved; each entry's tile-local slot is (chunk c, position j < chunk).
-// The group's entries are marked in one 64-bit word per chunk (LDS: bit j of
-// word c), the words' popcounts scanned into the group's chunk pointers, and
-// every entry's bucketed place is pointer c plus the number of its chunk's
-// entries at lower positions -- a function of the set alone, so every entry
+// The group's entries are marked in one 64-bit word per 64 positions of a
+// chunk (LDS: bit j mod 64 of word j / 64 of chunk c), the chunks' popcounts
+// scanned into the group's chunk pointers, and every entry's bucketed place
+// is pointer c plus the number of its chunk's entries at lower positions --
+// a function of the set alone, so every entry
 // is placed at once, each bucket is in ascending slot order, and the layout
 // does not depend on the order of the atomics.  The entries themselves stay
 // where they are: perm[place] is the entry's index in the group's list (the
@@ -1101,9 +1105,9 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ pg_cnt,
     const uint32_t* __restrict__ ent_slot, uint32_t* __restrict__ chunk_ptr,
     uint32_t* __restrict__ perm) {
-    static_assert(MAX_CHUNK <= 64, "a chunk's positions fit one 64-bit word");
-    __shared__ unsigned long long bits_all[BUCKET_WAVES][SCRAMBLE_MAX_NCH];
-    __shared__ uint32_t ptr_all[BUCKET_WAVES][SCRAMBLE_MAX_NCH];
+    static_assert(MAX_CHUNK <= 128, "a chunk's positions fit two 64-bit words");
+    __shared__ unsigned long long bits_all[BUCKET_WAVES][SCRAMBLE_MAX_WORDS];
+    __shared__ uint32_t ptr_all[BUCKET_WAVES][SCRAMBLE_MAX_WORDS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t pg = (int64_t)blockIdx.x * BUCKET_WAVES + wave;
     if (pg >= npg) return;  // uniform per wave; no workgroup barrier below
@@ -1134,18 +1138,22 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
         for (uint32_t t = lane; t < ne; t += 64) pm[t] = t;
         return;
     }
-    for (int64_t c = lane; c < nch; c += 64) bits[c] = 0ull;
+    // dealt tiles: nch * nw <= SCRAMBLE_MAX_WORDS
+    const int nw = chunk_words(chunk);
+    for (int64_t i = lane; i < nch * nw; i += 64) bits[i] = 0ull;
     __builtin_amdgcn_wave_barrier();
     for (uint32_t t = lane; t < ne; t += 64) {
-        const uint32_t loc = es[t] & SLOT_MASK;
-        atomicOr(&bits[loc / chunk], 1ull << (loc % chunk));
+        const uint32_t loc = es[t] & SLOT_MASK, c = loc / chunk, j = loc % chunk;
+        atomicOr(&bits[c * nw + j / 64], 1ull << (j % 64));
     }
     __builtin_amdgcn_wave_barrier();
     // exclusive scan of the chunks' entry counts: the chunk pointers
     uint32_t carry = 0;
     for (int64_t c0 = 0; c0 < nch; c0 += 64) {
         const int64_t c = c0 + lane;
-        const uint32_t v = c < nch ? (uint32_t)__builtin_popcountll(bits[c]) : 0u;
+        uint32_t v = 0;
+        if (c < nch)
+            for (int w = 0; w < nw; w++) v += (uint32_t)__builtin_popcountll(bits[c * nw + w]);
         uint32_t x = v;
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, 64);
@@ -1162,8 +1170,11 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     __builtin_amdgcn_wave_barrier();
     for (uint32_t t = lane; t < ne; t += 64) {
         const uint32_t loc = es[t] & SLOT_MASK, c = loc / chunk, j = loc % chunk;
-        const unsigned long long below = (1ull << j) - 1ull;
-        pm[ptr[c] + (uint32_t)__builtin_popcountll(bits[c] & below)] = t;
+        const unsigned long long* cw = bits + c * nw;
+        uint32_t at = ptr[c];
+        for (uint32_t w = 0; w < j / 64; w++) at += (uint32_t)__builtin_popcountll(cw[w]);
+        const unsigned long long below = (1ull << (j % 64)) - 1ull;
+        pm[at + (uint32_t)__builtin_popcountll(cw[j / 64] & below)] = t;
     }
 }
 
@@ -1341,7 +1352,8 @@ __global__ __launch_bounds__(256) void k_block_meta(
     int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
     const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
-    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff, int32_t* __restrict__ blk_tile) {
+    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff, int32_t* __restrict__ blk_tile,
+    int* __restrict__ run_max) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
@@ -1354,6 +1366,11 @@ __global__ __launch_bounds__(256) void k_block_meta(
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
     if (lane == 0) blk_tile[b] = (int32_t)r.tile;
+    // the longest (group, chunk) run: the channel kernel holds a run's slots
+    // one a lane, so chunks past 64 slots need every run within 64 entries
+    int rm = r.n;
+    for (int o = 32; o > 0; o >>= 1) rm = max(rm, __shfl_xor(rm, o, 64));
+    if (lane == 0 && rm > 64) atomicMax(run_max, rm);
     // units are groups of four entries; a group's run starts on a unit and
     // its last unit is padded: po[l] = 4 x (first unit) + (padding entries)
     const int ng = (r.n + 3) >> 2;
@@ -1472,7 +1489,8 @@ __global__ __launch_bounds__(256) void k_block_meta_g(
     int32_t npgx, int32_t npgy, int32_t ntx, int64_t ntiles, int64_t n_blocks,
     const int64_t* __restrict__ tile_blk, const int64_t* __restrict__ cp_base,
     const uint32_t* __restrict__ chunk_ptr, const int64_t* __restrict__ pg_base,
-    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff, int32_t* __restrict__ blk_tile) {
+    int64_t* __restrict__ blk_cnt, uint16_t* __restrict__ blk_pgoff, int32_t* __restrict__ blk_tile,
+    int* __restrict__ run_max) {
     int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
     if (b >= n_blocks) return;  // uniform per wave
@@ -1485,6 +1503,11 @@ __global__ __launch_bounds__(256) void k_block_meta_g(
     BlockLane r = block_lane(b, lane, npgx, npgy, ntx, ntiles, tile_blk, cp_base, chunk_ptr,
                              pg_base);
     if (lane == 0) blk_tile[b] = (int32_t)r.tile;
+    // the longest (group, chunk) run: the channel kernel holds a run's slots
+    // one a lane, so chunks past 64 slots need every run within 64 entries
+    int rm = r.n;
+    for (int o = 32; o > 0; o >>= 1) rm = max(rm, __shfl_xor(rm, o, 64));
+    if (lane == 0 && rm > 64) atomicMax(run_max, rm);
     int ng = (r.n + 3) >> 2;
     int x = ng;
     for (int o = 1; o < 64; o <<= 1) {
@@ -1562,14 +1585,15 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
 
 // The sizes the host reads once the entry blocks are laid out, gathered for
 // one copy: [0] neighbour pairs, [1] entry units, [2] units in the largest
-// block, [3] slots after compaction, [4] chunk pointers, then the per-tile
-// block offsets tile_blk[0 .. ntiles].
-constexpr int64_t PACK_HEAD = 5;
+// block, [3] slots after compaction, [4] chunk pointers, [5] the longest
+// (group, chunk) run if over 64 entries (else 0), then the per-tile block
+// offsets tile_blk[0 .. ntiles].
+constexpr int64_t PACK_HEAD = 6;
 __global__ __launch_bounds__(256) void k_pack_sizes(
     const unsigned long long* __restrict__ nnz, const int64_t* __restrict__ units,
     const int* __restrict__ blk_max, const int64_t* __restrict__ slots,
-    const int64_t* __restrict__ cps, const int64_t* __restrict__ tile_blk, int64_t ntiles,
-    int64_t* __restrict__ out) {
+    const int64_t* __restrict__ cps, const int* __restrict__ run_max,
+    const int64_t* __restrict__ tile_blk, int64_t ntiles, int64_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i <= ntiles) out[PACK_HEAD + i] = tile_blk[i];
     if (i == 0) {
@@ -1578,6 +1602,7 @@ __global__ __launch_bounds__(256) void k_pack_sizes(
         out[2] = *blk_max;
         out[3] = *slots;
         out[4] = *cps;
+        out[5] = *run_max;
     }
 }
 
@@ -1713,6 +1738,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     unsigned long long* nnz_total = (unsigned long long*)((char*)P.scratch.p + 8);
     int* blk_max = (int*)((char*)P.scratch.p + 16);  // most units in one block
     int64_t* slot_total = (int64_t*)((char*)P.scratch.p + 24);  // after compaction
+    int* run_max = (int*)((char*)P.scratch.p + 32);  // longest run past 64 entries, else 0
     void* scan_tmp = (char*)P.scratch.p + 64;
 
     {
@@ -1993,7 +2019,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            dim3(256), 0, s, P.npgx, P.npgy, P.ntx, P.ntiles, P.n_blocks,
                            (const int64_t*)P.tile_blk.p, (const int64_t*)P.cp_base.p,
                            (const uint32_t*)P.chunk_ptr.p, (const int64_t*)P.pg_base.p,
-                           (int64_t*)bcnt.p, (uint16_t*)P.blk_pgoff.p, (int32_t*)btile.p);
+                           (int64_t*)bcnt.p, (uint16_t*)P.blk_pgoff.p, (int32_t*)btile.p,
+                           run_max);
         HG_STEP(hipGetLastError());
         // the largest block sizes the channel kernel's LDS entry area
         hipLaunchKernelGGL(k_max_count, dim3(256), dim3(256), 0, s, (const int64_t*)bcnt.p,
@@ -2007,8 +2034,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     hipLaunchKernelGGL(k_pack_sizes, dim3(blocks_for(P.ntiles + 1, 256)), dim3(256), 0, s,
                        (const unsigned long long*)nnz_total, (const int64_t*)P.blk_base.p + P.n_blocks,
                        (const int*)blk_max, (const int64_t*)slot_total,
-                       (const int64_t*)P.cp_base.p + P.ntiles, (const int64_t*)P.tile_blk.p,
-                       P.ntiles, (int64_t*)sizes.p);
+                       (const int64_t*)P.cp_base.p + P.ntiles, (const int*)run_max,
+                       (const int64_t*)P.tile_blk.p, P.ntiles, (int64_t*)sizes.p);
     HG_STEP(hipGetLastError());
     HG_STEP(hipMemcpyAsync(back, sizes.p, sizeof(int64_t) * (size_t)(PACK_HEAD + P.ntiles + 1),
                            hipMemcpyDeviceToHost, s));
@@ -2029,7 +2056,14 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     P.nnz = back[0];
     P.nnz_entries = back[1];
     P.blk_max = (int)back[2];
+    P.run_max = (int)back[5];
     const int64_t n_ent = P.nnz_entries;
+    // a chunk length the channel kernel cannot stage is rebuilt shorter by
+    // the caller: the entry blocks are not filled
+    if (!channel_lds_fits(grouped, P.chunk, P.blk_max) || !channel_runs_fit(P.chunk, P.run_max)) {
+        cleanup();
+        return hipSuccess;
+    }
     if (grouped) {
         HG_STEP(dev_alloc(P.e3_w, (size_t)(n_ent ? n_ent : 1) * 32));
         HG_STEP(dev_alloc(P.e3_s, (size_t)(n_ent ? n_ent : 1) * 16));

@@ -34,8 +34,11 @@ import numpy as np
 from . import api
 
 SHAPES = ((16, 256), (16, 128), (16, 64), (8, 256), (8, 128), (8, 64))
-CHUNKS = {api.HG_PREC_FP32: (56, 48, 32), api.HG_PREC_MFMA_BF16: (64, 48, 32),
-          api.HG_PREC_MFMA_F16: (64, 48, 32)}
+# chunk lengths to try: the FP32 form stages at most 64 slots (1 KB rows),
+# the 16-bit forms up to 112 (512 B rows); a length whose densest entry
+# block does not fit LDS is skipped
+CHUNKS = {api.HG_PREC_FP32: (56, 48, 32), api.HG_PREC_MFMA_BF16: (112, 96, 80, 64, 48, 32),
+          api.HG_PREC_MFMA_F16: (112, 96, 80, 64, 48, 32)}
 
 
 def cache_path():

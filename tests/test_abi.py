@@ -89,7 +89,8 @@ def good():
 
 @pytest.mark.parametrize("case", ["null_out", "null_kernel", "neg_n", "null_coords", "fwhm",
                                   "support", "nx", "spacing", "pole", "nside", "chunk",
-                                  "waves", "chan_block", "memcap"])
+                                  "chunk_long", "chunk_long_f32", "waves", "chan_block",
+                                  "memcap"])
 def test_setup_rejects_bad_arguments_without_a_device(case):
     k, m = good()
     o = api.hg_opts()
@@ -116,6 +117,11 @@ def test_setup_rejects_bad_arguments_without_a_device(case):
         o.nside = 3
     elif case == "chunk":
         o.chunk = 7
+    elif case == "chunk_long":  # past the 16-bit forms' 112 slots
+        o.precision = api.HG_PREC_MFMA_BF16
+        o.chunk = 120
+    elif case == "chunk_long_f32":  # the FP32 form's 1 KB rows: 64 slots at most
+        o.chunk = 72
     elif case == "waves":
         o.waves = 12
     elif case == "chan_block":

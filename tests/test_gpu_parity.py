@@ -291,6 +291,41 @@ def test_precision_form_parity(form, name):
     print(f"  {form} {name}: e_max={e_max:.3g} e_rms={e_rms:.3g}")
 
 
+@pytest.mark.parametrize("form", sorted(MFMA))
+@pytest.mark.parametrize("chunk", [72, 96, 112])
+def test_long_chunks_in_16bit_forms(form, chunk):
+    """The 16-bit forms stage up to 112 slots a chunk (512 B rows): past 64
+    the bucketing marks two presence words per chunk and the metadata ring
+    takes two index copies per chunk.  About 2,000 slots a tile, so tens of
+    dealt chunks per tile with ragged last chunks, against the reference (a
+    2 arcmin beam keeps the densest entry block within LDS at 112)."""
+    prec, dt, u = MFMA[form]
+    ra, dec, vals, m, k = rand_field(41, 2500, 26, 23, 95.0, -20.0, fwhm=2.0, C=300, dtype=dt)
+    check_field(ra, dec, vals, m, k, tol=MFMA_TOL, w_rtol=u, precision=prec, chunk=chunk)
+
+
+def _dense_tile_field():
+    # 200,000 samples under one 12 x 12-pixel tile with a 1 arcmin beam: past
+    # the dealing limit at chunks over 64 slots (two presence words a chunk,
+    # 1024 words a wave)
+    return rand_field(42, 200_000, 12, 12, 40.0, 10.0, fwhm=1.0, C=9, dtype=torch.bfloat16)
+
+
+def test_long_chunk_refused_where_a_group_takes_most_of_it():
+    """A tile too dense to deal at chunks past 64 slots keeps consecutive
+    slots per chunk; those lie in one sky cell (or the sliver of a cell that
+    reaches the map), so single pixel groups take runs of up to 72 entries,
+    past what the channel kernel holds (one slot a lane).  An explicit chunk
+    of 72 is refused with a message; the default chunk builds."""
+    ra, dec, vals, m, k = _dense_tile_field()
+    with pytest.raises(api.HegridError) as e:
+        api.Plan(ra, dec, m, k, precision=1, chunk=72)
+    assert e.value.status == api.HG_ERR_UNSUPPORTED
+    assert "64 entries" in str(e.value)
+    with api.Plan(ra, dec, m, k, precision=1) as p:
+        assert p.stats()["chunk"] <= 64
+
+
 def test_cfg3_bf16_mfma_form():
     """8192 BF16 channels on the cfg1 geometry; reference on sampled channels."""
     f = synth.config("cfg3")

@@ -30,4 +30,5 @@ def test_candidates_are_valid_options():
         assert waves in (8, 16) and cb in (64, 128, 256)
     for prec, chunks in tune.CHUNKS.items():
         assert prec in (api.HG_PREC_FP32, api.HG_PREC_MFMA_BF16, api.HG_PREC_MFMA_F16)
-        assert all(8 <= c <= 64 and c % 8 == 0 for c in chunks)
+        top = 64 if prec == api.HG_PREC_FP32 else 112
+        assert all(8 <= c <= top and c % 8 == 0 for c in chunks)
