@@ -640,6 +640,9 @@ def run_paper(args):
     host memory and the cube ends there.  One step = coordinates to the GPU +
     setup, with the values' copy to the GPU on a second stream behind it
     (api.grid_from_host) + channels + the cube back + finish; with
+    --paper-bands B (default 8) the channels run in B bands of tile rows, each
+    started once the values of its samples have arrived and its rows copied
+    back while later bands run (0: one launch after the whole copy); with
     --paper-streamed, setup and then the channels streamed in blocks
     (hg_grid_channels_host), the copies overlapped with the kernel only."""
     import numpy as np
@@ -671,7 +674,7 @@ def run_paper(args):
         t0 = time.perf_counter()
         if overlap:
             _, info = api.grid_from_host(ra_h, dec_h, m, k, vals, out=out, dev_values=dev_vals,
-                                         dev_out=dev_out)
+                                         dev_out=dev_out, bands=args.paper_bands, pieces=16)
             st = {"nnz": info["nnz"], "setup_ms": info["setup_ms"]}
             info["wall_ms"] = (time.perf_counter() - t0) * 1e3
         else:
@@ -716,12 +719,17 @@ def run_paper(args):
         "config": {"workload": f"paper-scale stand-in: {n} samples from 19-beam drift scans over "
                                "60x20 deg at (30, 41) deg, 3600x1200 map at 1 arcmin, FWHM 3 "
                                "arcmin, 50 FP32 channels in page-locked host memory; step = "
-                               + ("coordinates H2D + setup (values H2D on a second stream) + "
+                               + (("coordinates H2D + setup (values H2D on a second stream, in 16 "
+                                   f"index pieces) + channels in {args.paper_bands} bands of tile "
+                                   "rows, each started once its samples' piece has arrived, its "
+                                   "rows D2H while later bands run") if overlap and args.paper_bands
+                                  else "coordinates H2D + setup (values H2D on a second stream) + "
                                   "channels + cube D2H" if overlap else
                                   "coordinates H2D + setup + streamed channels + cube D2H"),
                    "n_samples": n, "channels": C, "map": [m["ny"], m["nx"]], "nnz": nnz},
         "setup_ms": mean["setup"], "phases_wall_ms": mean["wall"], "h2d_ms": mean["h2d"],
         "channels_ms": mean["kernel"], "d2h_ms": mean["d2h"],
+        "bands": args.paper_bands if overlap else 0,
         "roofline": roof,
         "paper_context": {"hegrid_s": 40.94, "hardware": "V100 + Xeon Gold 6151",
                           "samples": 1.9e7, "channels": 50,
@@ -835,6 +843,8 @@ def main():
     ap.add_argument("--kernel", choices=["gauss", "sinc", "elliptical"], default="gauss",
                     help="drift workload: kernel shape")
     ap.add_argument("--paper-samples", type=int, default=19_000_000)
+    ap.add_argument("--paper-bands", type=int, default=8,
+                    help="paper workload: bands of tile rows (0: the whole map at once)")
     ap.add_argument("--paper-streamed", action="store_true",
                     help="paper workload: stream the channels after setup (hg_grid_channels_host) "
                          "instead of copying the values during setup")

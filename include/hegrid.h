@@ -210,6 +210,38 @@ int hg_grid_channels(hg_plan* p, const void* values, int64_t ld, int32_t nchan, 
                      float* out, void* hip_stream);
 
 /*
+ * hg_grid_channels for the tiles of tile rows [tile_row0, tile_row1): map rows
+ * [16 tile_row0, min(16 tile_row1, ny)) of every channel (tiles are 16 x 16
+ * pixels; the map has ceil(ny / 16) tile rows).  The same per-tile work as
+ * hg_grid_channels, so calls over rows that cover the map give its result bit
+ * for bit; only those rows of out ([nchan][ny][nx], the whole cube's buffer)
+ * are written.  This lets a caller copy finished rows back, or start rows
+ * whose samples have arrived, while later rows are computed (the channels of
+ * Eq. 1 split by output region: each pixel's sum still runs over all of its
+ * neighbours, Sec. 4.2).  0 <= tile_row0 <= tile_row1 <= tile rows, else
+ * HG_ERR_ARG; tile_row0 == tile_row1 does nothing.  Other arguments, errors
+ * and asynchrony as for hg_grid_channels; each distinct row range keeps its
+ * own launch order on the plan (a few KB).
+ */
+int hg_grid_channels_rows(hg_plan* p, const void* values, int64_t ld, int32_t nchan,
+                          int32_t dtype, float* out, int32_t tile_row0, int32_t tile_row1,
+                          void* hip_stream);
+
+/*
+ * For bands of rows_per_band tile rows (band b: tile rows [b rows_per_band,
+ * min((b + 1) rows_per_band, tile rows))): host_need[b] = 1 + the largest
+ * sample index that any tile of the band stages, 0 if it stages none, so
+ * hg_grid_channels_rows over band b reads only the values of samples
+ * [0, host_need[b]).  A caller streaming the values to the device in index
+ * order can start a band once that prefix has arrived (for scans recorded in
+ * order, a band's samples lie in a narrow index range).  host_need: HOST
+ * int64 [nbands], nbands = ceil(tile rows / rows_per_band), else HG_ERR_ARG;
+ * rows_per_band >= 1.  Runs a small kernel on hip_stream and synchronises it.
+ */
+int hg_plan_row_needs(const hg_plan* p, int32_t rows_per_band, int64_t* host_need,
+                      int32_t nbands, void* hip_stream);
+
+/*
  * Grid a cube held in HOST memory, block by block of channels, with the copy
  * of the next block in, the kernel of the current block and the copy of the
  * previous block out overlapped on three streams (channels are independent,

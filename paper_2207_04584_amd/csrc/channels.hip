@@ -959,16 +959,49 @@ FieldDesc field_desc(const Plan& P, const void* values, int64_t ld, int32_t ncha
 }
 
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
-                           float* out, hipStream_t s, Shape shape) {
+                           float* out, hipStream_t s, Shape shape, int32_t row0, int32_t row1) {
     const bool vec = values_vec(P, values, ld, dtype);
     const bool m16 = P.opts.precision != HG_PREC_FP32;
     shape = effective_shape(m16, dtype, vec, shape);
     const int32_t ncb = (nchan + 64 * shape.g - 1) / (64 * shape.g);
     const int64_t* order = nullptr;
     int64_t nwg = 0;
-    hipError_t e = launch_order(P, ncb, s, &order, &nwg);
+    hipError_t e = launch_order(P, ncb, s, &order, &nwg, row0, row1);
     if (e != hipSuccess) return e;
     return launch_channels_on(P, values, ld, nchan, dtype, out, s, shape, order, nwg);
+}
+
+// 1 + the largest sample index tile t stages (its slots' sample indices), 0
+// when it stages none: one workgroup per tile.
+__global__ __launch_bounds__(256) void k_tile_max_index(const int64_t* __restrict__ tile_base,
+                                                        const uint32_t* __restrict__ slot_idx,
+                                                        int64_t* __restrict__ tile_need) {
+    __shared__ int64_t red[4];
+    const int64_t t = blockIdx.x;
+    const int64_t a = tile_base[t], b = tile_base[t + 1];
+    int64_t m = 0;
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+        const int64_t v = (int64_t)slot_idx[i] + 1;
+        m = v > m ? v : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t y = __shfl_xor(m, o, 64);
+        m = y > m ? y : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t r = red[0];
+        for (int k = 1; k < 4; k++) r = red[k] > r ? red[k] : r;
+        tile_need[t] = r;
+    }
+}
+
+hipError_t launch_tile_max_index(const Plan& P, int64_t* tile_need, hipStream_t s) {
+    if (P.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_max_index, dim3((unsigned)P.ntiles), dim3(256), 0, s,
+                       (const int64_t*)P.tile_nslots.p, (const uint32_t*)P.slot_idx.p, tile_need);
+    return hipGetLastError();
 }
 
 hipError_t launch_channels_on(Plan& P, const void* values, int64_t ld, int32_t nchan,

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
@@ -221,7 +222,8 @@ struct Plan {
     int32_t run_max = 0;  // longest (group, chunk) run of entries if over 64, else 0
     DevBuf tile_blk;     // int64 [ntiles+1] first block of each tile
     std::vector<int64_t> tile_blk_host;       // the same, on the host (launch order costs)
-    std::map<int32_t, LaunchOrder> orders;    // launch orders by channel-block count
+    // launch orders by (channel-block count, first tile row, end tile row)
+    std::map<std::tuple<int32_t, int32_t, int32_t>, LaunchOrder> orders;
     DevBuf blk_base;     // int64 [n_blocks+1] first entry of each block
     DevBuf blk_pgoff;    // uint16 [n_blocks][PGOFF_STRIDE] per-group offsets in the block
     DevBuf e2_w;         // float [units][4 pixels][4 entries] weights, block order
@@ -309,13 +311,20 @@ __host__ __device__ inline double col_ra_hi(const hg_map& m, int64_t i) {
 
 // The launch order of a plan's channel kernel for ncb channel blocks, built
 // and uploaded on stream s at its first use (runtime.hip).
-hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** items, int64_t* n);
+// The (tile, channel block) items of tile rows [row0, row1) (row1 < 0: every
+// row) in launch order: XCD-aware, cached per plan.
+hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** items, int64_t* n,
+                        int32_t row0 = 0, int32_t row1 = -1);
+// per tile: 1 + the largest sample index it stages (0 for an empty tile), on s
+hipError_t launch_tile_max_index(const Plan& P, int64_t* tile_need, hipStream_t s);
 
 // kernel launchers (setup.hip, channels.hip, literal.hip)
 hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hipStream_t s,
                         std::string& err, int& status);
+// the channel phase over tile rows [row0, row1) (row1 < 0: the whole map)
 hipError_t launch_channels(Plan& P, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
-                           float* out, hipStream_t s, Shape shape);
+                           float* out, hipStream_t s, Shape shape, int32_t row0 = 0,
+                           int32_t row1 = -1);
 // the same launch on a caller-provided item order of nwg positions (device)
 hipError_t launch_channels_on(Plan& P, const void* values, int64_t ld, int32_t nchan,
                               int32_t dtype, float* out, hipStream_t s, Shape shape,

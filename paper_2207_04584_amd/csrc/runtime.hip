@@ -622,16 +622,26 @@ std::vector<BatchItem> plan_batch_items(const std::vector<std::vector<int64_t>>&
 // order is built and uploaded on the first launch with a given channel-block
 // count and kept with the plan; a later launch on another stream waits for
 // the upload's event.
-hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** items, int64_t* n) {
+hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** items, int64_t* n,
+                        int32_t row0, int32_t row1) {
     if (P.tile_blk_host.size() != (size_t)P.ntiles + 1) return hipErrorNotInitialized;
-    auto it = P.orders.find(ncb);
+    if (row1 < 0) {
+        row0 = 0;
+        row1 = P.nty;
+    }
+    const auto key = std::make_tuple(ncb, row0, row1);
+    auto it = P.orders.find(key);
     if (it == P.orders.end()) {
         LaunchOrder o;
         int64_t n_items = 0;
-        const std::vector<BatchItem> pos = plan_batch_items({P.tile_blk_host}, {ncb}, n_items);
+        // the rows' tiles are contiguous: their chunk offsets, rebased
+        const int64_t t0 = (int64_t)row0 * P.ntx, t1 = (int64_t)row1 * P.ntx;
+        std::vector<int64_t> tb(P.tile_blk_host.begin() + t0, P.tile_blk_host.begin() + t1 + 1);
+        for (auto& v : tb) v -= P.tile_blk_host[(size_t)t0];
+        const std::vector<BatchItem> pos = plan_batch_items({tb}, {ncb}, n_items);
         o.host.resize(pos.size());
         for (size_t i = 0; i < pos.size(); i++)
-            o.host[i] = pos[i].field < 0 ? -1 : pos[i].tile * ncb + pos[i].cb;
+            o.host[i] = pos[i].field < 0 ? -1 : (t0 + pos[i].tile) * ncb + pos[i].cb;
         o.n = (int64_t)pos.size();
         hipError_t e = dev_alloc(o.items, sizeof(int64_t) * (o.host.empty() ? 1 : o.host.size()));
         if (e == hipSuccess) e = hipEventCreateWithFlags(&o.ready, hipEventDisableTiming);
@@ -644,7 +654,7 @@ hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** ite
             if (o.ready) (void)hipEventDestroy(o.ready);
             return e;
         }
-        it = P.orders.emplace(ncb, std::move(o)).first;
+        it = P.orders.emplace(key, std::move(o)).first;
     } else {
         hipError_t e = hipStreamWaitEvent(s, it->second.ready, 0);
         if (e != hipSuccess) return e;
@@ -680,8 +690,12 @@ int hg_grid_setup(const double* ra_deg, const double* dec_deg, int64_t n, const 
     });
 }
 
-int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
-                     float* out, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+// hg_grid_channels over tile rows [row0, row1) (row1 < 0: every row)
+int grid_channels_rows(hg_plan* h, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
+                       float* out, void* hip_stream, int32_t row0, int32_t row1) {
     return guarded([&]() -> int {
         g_err.clear();
         if (!h) return fail(HG_ERR_ARG, "plan must not be NULL");
@@ -690,7 +704,9 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
         if (nchan < 0) return fail(HG_ERR_ARG, "nchan must be >= 0");
         if (dtype != HG_F32 && dtype != HG_BF16 && dtype != HG_F16)
             return fail(HG_ERR_ARG, "unknown dtype");
-        if (nchan == 0) return HG_OK;
+        if (row1 >= 0 && (row0 < 0 || row1 > P.nty || row0 > row1))
+            return fail(HG_ERR_ARG, "tile rows must satisfy 0 <= row0 <= row1 <= the map's tile rows");
+        if (nchan == 0 || row0 == row1) return HG_OK;
         if (!out || (!values && P.n > 0)) return fail(HG_ERR_ARG, "values and out must not be NULL");
         if (ld < nchan) return fail(HG_ERR_ARG, "ld must be >= nchan");
         if (P.opts.precision == HG_PREC_MFMA_BF16 && dtype != HG_BF16)
@@ -717,7 +733,7 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
             e = hipEventRecord(ev.first, s);
             if (e != hipSuccess) return fail_hip(e, "grid_channels (events)");
         }
-        e = launch_channels(P, values, ld, nchan, dtype, out, s, P.shape);
+        e = launch_channels(P, values, ld, nchan, dtype, out, s, P.shape, row0, row1);
         if (e != hipSuccess) return fail_hip(e, "grid_channels");
         if (timed) {
             e = hipEventRecord(ev.second, s);
@@ -725,6 +741,59 @@ int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, 
             P.ev_pending.push_back(ev);
         }
         P.ch_calls++;
+        return HG_OK;
+    });
+}
+}  // namespace
+
+extern "C" {
+
+int hg_grid_channels(hg_plan* h, const void* values, int64_t ld, int32_t nchan, int32_t dtype,
+                     float* out, void* hip_stream) {
+    return grid_channels_rows(h, values, ld, nchan, dtype, out, hip_stream, 0, -1);
+}
+
+int hg_grid_channels_rows(hg_plan* h, const void* values, int64_t ld, int32_t nchan,
+                          int32_t dtype, float* out, int32_t tile_row0, int32_t tile_row1,
+                          void* hip_stream) {
+    if (tile_row1 < 0) {
+        g_err = "tile_row1 must be >= 0";
+        return HG_ERR_ARG;
+    }
+    return grid_channels_rows(h, values, ld, nchan, dtype, out, hip_stream, tile_row0, tile_row1);
+}
+
+int hg_plan_row_needs(const hg_plan* h, int32_t rows_per_band, int64_t* host_need,
+                      int32_t nbands, void* hip_stream) {
+    return guarded([&]() -> int {
+        g_err.clear();
+        if (!h) return fail(HG_ERR_ARG, "plan must not be NULL");
+        const Plan& P = h->P;
+        if (P.finished) return fail(HG_ERR_STATE, "plan already finished");
+        if (rows_per_band < 1) return fail(HG_ERR_ARG, "rows_per_band must be >= 1");
+        const int64_t want = ((int64_t)P.nty + rows_per_band - 1) / rows_per_band;
+        if (nbands != want || !host_need)
+            return fail(HG_ERR_ARG, "host_need must hold ceil(tile rows / rows_per_band) values");
+        hipError_t e = hipSetDevice(P.device);
+        if (e != hipSuccess) return fail_hip(e, "plan_row_needs");
+        hipStream_t s = (hipStream_t)hip_stream;
+        std::vector<int64_t> tn((size_t)P.ntiles);
+        DevBuf d;
+        e = dev_alloc(d, sizeof(int64_t) * (size_t)(P.ntiles ? P.ntiles : 1));
+        if (e == hipSuccess) e = launch_tile_max_index(P, (int64_t*)d.p, s);
+        if (e == hipSuccess && P.ntiles)
+            e = hipMemcpyAsync(tn.data(), d.p, sizeof(int64_t) * tn.size(), hipMemcpyDeviceToHost,
+                               s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dev_free(d);
+        if (e != hipSuccess) return fail_hip(e, "plan_row_needs");
+        for (int32_t b = 0; b < nbands; b++) {
+            int64_t m = 0;
+            const int64_t r0 = (int64_t)b * rows_per_band;
+            const int64_t r1 = std::min<int64_t>(r0 + rows_per_band, P.nty);
+            for (int64_t t = r0 * P.ntx; t < r1 * P.ntx; t++) m = std::max(m, tn[(size_t)t]);
+            host_need[b] = m;
+        }
         return HG_OK;
     });
 }
