@@ -507,14 +507,22 @@ __global__ void k_pg_plan(const RowInfo* __restrict__ pg_rows, const RowInfo* __
     }
 }
 
+// A group's entries are numbered below 2^PERM_INDEX_BITS (the bucket
+// permutation packs the number with the entry's position in its chunk).
+constexpr int PERM_POS_BITS = 7;
+constexpr uint32_t PERM_POS_MASK = (1u << PERM_POS_BITS) - 1u;
+constexpr int PERM_INDEX_BITS = 32 - PERM_POS_BITS;
+static_assert(MAX_CHUNK <= (1 << PERM_POS_BITS), "a chunk position fits the permutation's low bits");
+
 __global__ void k_pg_capacity(const int4* __restrict__ pg_piece, int64_t npg, int32_t pg_rings,
-                              int64_t* __restrict__ cap) {
+                              int64_t* __restrict__ cap, int* __restrict__ flag) {
     int64_t pg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pg >= npg) return;
     const int4* p = pg_piece + pg * pg_rings * 2;
     int64_t s = 0;
     for (int k = 0; k < 2 * pg_rings; k++) s += p[k].y;
     cap[pg] = s;
+    if (s >= ((int64_t)1 << PERM_INDEX_BITS)) atomicOr(flag, 32);
 }
 
 __global__ __launch_bounds__(256) void k_slot_fill(const int4* __restrict__ tile_piece,
@@ -1096,8 +1104,10 @@ __global__ __launch_bounds__(256) void k_deal_slots(
 // a function of the set alone, so every entry
 // is placed at once, each bucket is in ascending slot order, and the layout
 // does not depend on the order of the atomics.  The entries themselves stay
-// where they are: perm[place] is the entry's index in the group's list (the
-// block fills read through it).  Other tiles keep their (already sorted)
+// where they are: perm[place] holds the entry's index in the group's list
+// (the block fills read its weights through it) above PERM_POS_BITS bits of
+// its position in its chunk (the slot the fills store, so that they need not
+// read the entry's slot word).  Other tiles keep their (already sorted)
 // order, take their pointers by binary search and an identity perm.
 __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     int32_t npgx, int64_t npg, int32_t ntx, int32_t chunk, const int64_t* __restrict__ tile_blk,
@@ -1135,7 +1145,8 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
             }
             cp[c] = lo;
         }
-        for (uint32_t t = lane; t < ne; t += 64) pm[t] = t;
+        for (uint32_t t = lane; t < ne; t += 64)
+            pm[t] = (t << PERM_POS_BITS) | ((es[t] & SLOT_MASK) % (uint32_t)chunk);
         return;
     }
     // dealt tiles: nch * nw <= SCRAMBLE_MAX_WORDS
@@ -1174,7 +1185,7 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
         uint32_t at = ptr[c];
         for (uint32_t w = 0; w < j / 64; w++) at += (uint32_t)__builtin_popcountll(cw[w]);
         const unsigned long long below = (1ull << (j % 64)) - 1ull;
-        pm[at + (uint32_t)__builtin_popcountll(cw[j / 64] & below)] = t;
+        pm[at + (uint32_t)__builtin_popcountll(cw[j / 64] & below)] = (t << PERM_POS_BITS) | j;
     }
 }
 
@@ -1331,19 +1342,19 @@ __device__ inline UnitRef unit_ref(int i, int first, int64_t src, int64_t pgb, i
 }
 
 // The four entries of a unit (a run's last unit padded with zero weights and
-// its last real slot), slots relative to the chunk's first slot s0.  The
-// bucketed place of an entry maps to its index in the group's list through
-// perm (pg_base is the group's first entry: a run never spans groups).
-__device__ inline void load_unit(const UnitRef& u, uint32_t s0, const uint32_t* ent_slot,
-                                 const float4* ent_w, const uint32_t* perm, uint32_t sl[4],
-                                 float4 w[4]) {
+// its last real slot): slots relative to the chunk's first slot and the
+// weights, both through the bucket permutation (its value carries the
+// entry's index in the group's list and its position in the chunk; pg_base
+// is the group's first entry: a run never spans groups).
+__device__ inline void load_unit(const UnitRef& u, const float4* ent_w, const uint32_t* perm,
+                                 uint32_t sl[4], float4 w[4]) {
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int e = 4 * u.t + k;
         const bool real = e < u.n;
-        const int64_t at = u.pgb + perm[u.src + (real ? e : u.n - 1)];
-        sl[k] = (ent_slot[at] & SLOT_MASK) - s0;
-        const float4 v = ent_w[at];
+        const uint32_t pv = perm[u.src + (real ? e : u.n - 1)];
+        sl[k] = pv & PERM_POS_MASK;
+        const float4 v = ent_w[u.pgb + (pv >> PERM_POS_BITS)];
         w[k] = real ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
@@ -1422,11 +1433,11 @@ inline unsigned fill_grid(int64_t n_blocks) {
 // block's units are then written flat, lane i taking units i and i + 64 of
 // each pass of 128 (coalesced writes; both units' loads in flight together).
 __global__ __launch_bounds__(256) void k_block_fill(
-    int32_t npgx, int32_t npgy, int32_t ntx, int64_t n_blocks, int32_t chunk,
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t n_blocks,
     const int32_t* __restrict__ blk_tile, const int64_t* __restrict__ tile_blk,
     const int64_t* __restrict__ cp_base, const uint32_t* __restrict__ chunk_ptr,
-    const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ ent_slot,
-    const float4* __restrict__ ent_w, const uint32_t* __restrict__ perm,
+    const int64_t* __restrict__ pg_base, const float4* __restrict__ ent_w,
+    const uint32_t* __restrict__ perm,
     const int64_t* __restrict__ blk_base,
     float4* __restrict__ e2_w, uint4* __restrict__ e2_s) {
     const int64_t b = fill_block(threadIdx.x >> 6);
@@ -1437,15 +1448,14 @@ __global__ __launch_bounds__(256) void k_block_fill(
                                 chunk_ptr, pg_base);
     int first;
     const int nu = block_units(r.n, first);
-    const uint32_t s0 = (uint32_t)(r.c * chunk);
     for (int i0 = 0; i0 < nu; i0 += 128) {  // same trip count on every lane
         const int ia = i0 + lane, ib = ia + 64;
         const UnitRef ua = unit_ref(ia, first, r.src, r.pgb, r.n);
         const UnitRef ub = unit_ref(ib, first, r.src, r.pgb, r.n);
         uint32_t sa[4], sb[4];
         float4 wa[4], wb[4];
-        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, perm, sa, wa);
-        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, perm, sb, wb);
+        if (ia < nu) load_unit(ua, ent_w, perm, sa, wa);
+        if (ib < nu) load_unit(ub, ent_w, perm, sb, wb);
         // [pixel q][entry k]: pixel q's weights for the unit's four entries
         if (ia < nu) {
             e2_s[base + ia] = make_uint4(sa[0], sa[1], sa[2], sa[3]);
@@ -1554,11 +1564,11 @@ __device__ inline void store_unit_g(uint16_t* e3_w, uint4* e3_s, int64_t at, con
 // k_block_fill for the 16-bit forms: the same walk over a block's units (groups
 // of four entries), weights stored in the MFMA input type.
 __global__ __launch_bounds__(256) void k_block_fill_g(
-    int32_t npgx, int32_t npgy, int32_t ntx, int64_t n_blocks, int32_t chunk, int32_t prec,
+    int32_t npgx, int32_t npgy, int32_t ntx, int64_t n_blocks, int32_t prec,
     const int32_t* __restrict__ blk_tile, const int64_t* __restrict__ tile_blk,
     const int64_t* __restrict__ cp_base, const uint32_t* __restrict__ chunk_ptr,
-    const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ ent_slot,
-    const float4* __restrict__ ent_w, const uint32_t* __restrict__ perm,
+    const int64_t* __restrict__ pg_base, const float4* __restrict__ ent_w,
+    const uint32_t* __restrict__ perm,
     const int64_t* __restrict__ blk_base,
     uint16_t* __restrict__ e3_w, uint4* __restrict__ e3_s) {
     const int64_t b = fill_block(threadIdx.x >> 6);
@@ -1569,15 +1579,14 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
                                 chunk_ptr, pg_base);
     int first;
     const int nu = block_units(r.n, first);
-    const uint32_t s0 = (uint32_t)(r.c * chunk);
     for (int i0 = 0; i0 < nu; i0 += 128) {  // same trip count on every lane
         const int ia = i0 + lane, ib = ia + 64;
         const UnitRef ua = unit_ref(ia, first, r.src, r.pgb, r.n);
         const UnitRef ub = unit_ref(ib, first, r.src, r.pgb, r.n);
         uint32_t sa[4], sb[4];
         float4 wa[4], wb[4];
-        if (ia < nu) load_unit(ua, s0, ent_slot, ent_w, perm, sa, wa);
-        if (ib < nu) load_unit(ub, s0, ent_slot, ent_w, perm, sb, wb);
+        if (ia < nu) load_unit(ua, ent_w, perm, sa, wa);
+        if (ib < nu) load_unit(ub, ent_w, perm, sb, wb);
         if (ia < nu) store_unit_g(e3_w, e3_s, base + ia, sa, wa, prec);
         if (ib < nu) store_unit_g(e3_w, e3_s, base + ib, sb, wb, prec);
     }
@@ -1839,7 +1848,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const int4*)P.tile_piece.p, (int4*)P.pg_piece.p, flag);
         HG_STEP(hipGetLastError());
         hipLaunchKernelGGL(k_pg_capacity, dim3(blocks_for(P.npg, 256)), dim3(256), 0, s,
-                           (const int4*)P.pg_piece.p, P.npg, P.pg_rings, (int64_t*)pcap.p);
+                           (const int4*)P.pg_piece.p, P.npg, P.pg_rings, (int64_t*)pcap.p, flag);
         HG_STEP(hipGetLastError());
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)pcap.p, P.npg,
                                                   (int64_t*)P.pg_base.p, (int64_t*)scan_tmp, s)));
@@ -1870,7 +1879,13 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         cleanup();
         return hipSuccess;
     }
-    if (tot[4] & ~3) {
+    if (tot[4] & 32) {
+        status = HG_ERR_UNSUPPORTED;
+        err = "a pixel group has 2^25 or more candidate samples";
+        cleanup();
+        return hipSuccess;
+    }
+    if (tot[4] & ~(3 | 32)) {
         status = HG_ERR_INTERNAL;
         err = "planner consistency check failed (flag " + std::to_string(tot[4]) + ")";
         cleanup();
@@ -2069,11 +2084,11 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(P.e3_s, (size_t)(n_ent ? n_ent : 1) * 16));
         if (P.n_blocks > 0) {
             hipLaunchKernelGGL(k_block_fill_g, dim3(fill_grid(P.n_blocks)), dim3(256), 0, s,
-                               P.npgx, P.npgy, P.ntx, P.n_blocks, P.chunk, P.opts.precision,
+                               P.npgx, P.npgy, P.ntx, P.n_blocks, P.opts.precision,
                                (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
                                (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
-                               (const int64_t*)P.pg_base.p, (const uint32_t*)P.ent_slot.p,
-                               (const float4*)P.ent_w.p, (const uint32_t*)perm.p,
+                               (const int64_t*)P.pg_base.p, (const float4*)P.ent_w.p,
+                               (const uint32_t*)perm.p,
                                (const int64_t*)P.blk_base.p,
                                (uint16_t*)P.e3_w.p, (uint4*)P.e3_s.p);
             HG_STEP(hipGetLastError());
@@ -2083,11 +2098,11 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(P.e2_s, (size_t)(n_ent ? n_ent : 1) * 16));
         if (P.n_blocks > 0) {
             hipLaunchKernelGGL(k_block_fill, dim3(fill_grid(P.n_blocks)), dim3(256), 0, s,
-                               P.npgx, P.npgy, P.ntx, P.n_blocks, P.chunk,
+                               P.npgx, P.npgy, P.ntx, P.n_blocks,
                                (const int32_t*)btile.p, (const int64_t*)P.tile_blk.p,
                                (const int64_t*)P.cp_base.p, (const uint32_t*)P.chunk_ptr.p,
-                               (const int64_t*)P.pg_base.p, (const uint32_t*)P.ent_slot.p,
-                               (const float4*)P.ent_w.p, (const uint32_t*)perm.p,
+                               (const int64_t*)P.pg_base.p, (const float4*)P.ent_w.p,
+                               (const uint32_t*)perm.p,
                                (const int64_t*)P.blk_base.p,
                                (float4*)P.e2_w.p, (uint4*)P.e2_s.p);
             HG_STEP(hipGetLastError());
