@@ -15,7 +15,8 @@ are the same operations in the same order), so they are set on one plan
 (hg_plan_set_shape) and timed there; chunk changes the two-level summation
 and is checked against the reference like any other plan.  Each candidate is
 timed with HIP events recorded around the channel launch by the library
-(HG_FLAG_TIME_CHANNELS), median of a few launches.
+(HG_FLAG_TIME_CHANNELS), the fastest of a few launches (interference only
+ever adds time, and medians of three let it pick a shape 4 % off the best).
 
 Results go to a JSON cache (``$HEGRID_TUNE_CACHE``, else
 ``~/.cache/hegrid/tune.json``) keyed by the device name, the form, the value
@@ -28,8 +29,6 @@ runs in the library's kernels.
 import json
 import math
 import os
-
-import numpy as np
 
 from . import api
 
@@ -88,8 +87,9 @@ def _dtype_name(values):
     return str(values.dtype).replace("torch.", "")
 
 
-def time_shapes(plan, values, out, shapes=SHAPES, reps=3):
-    """Median device time (ms) of the plan's channel launch in each shape.
+def time_shapes(plan, values, out, shapes=SHAPES, reps=5):
+    """Fastest device time (ms) of reps launches of the plan's channel kernel
+    in each shape, after one untimed launch.
     The plan must have been made with time_channels=True."""
     res = {}
     for waves, cb in shapes:
@@ -99,13 +99,13 @@ def time_shapes(plan, values, out, shapes=SHAPES, reps=3):
         for _ in range(reps):
             plan.grid(values, out)
             ms.append(plan.stats()["last_channels_ms"])
-        res[(waves, cb)] = float(np.median(ms))
+        res[(waves, cb)] = float(min(ms))
     plan.set_shape(0, 0)
     return res
 
 
 def tune_plan(ra_deg, dec_deg, map, kernel, values, precision=api.HG_PREC_FP32, chunks=None,
-              shapes=SHAPES, reps=3, use_cache=True):
+              shapes=SHAPES, reps=5, use_cache=True):
     """Sweep chunk x shape on this workload; returns the best
     {"chunk", "waves", "chan_block", "ms", "table", "key", "cached"}.
     With use_cache a stored choice for the same kind of workload is returned
@@ -152,7 +152,7 @@ def tuned_plan(ra_deg, dec_deg, map, kernel, values, precision=api.HG_PREC_FP32,
                     waves=best["waves"], chan_block=best["chan_block"], **plan_kw), best
 
 
-def tune_batch(fields, precision=api.HG_PREC_MFMA_F16, shapes=SHAPES, reps=2, use_cache=True):
+def tune_batch(fields, precision=api.HG_PREC_MFMA_F16, shapes=SHAPES, reps=3, use_cache=True):
     """Shape of the batched launch (one kernel for every field, so one
     waves x chan_block for all; each field keeps the longest chunk that fits
     it).  fields as for api.Batch.  Returns {"waves", "chan_block", "ms",
@@ -175,7 +175,7 @@ def tune_batch(fields, precision=api.HG_PREC_MFMA_F16, shapes=SHAPES, reps=2, us
             for _ in range(reps):
                 b.run()
                 ms.append(b.stats()["last_run_ms"])
-        t = float(np.median(ms))
+        t = float(min(ms))
         table[f"w{waves}_c{cb}"] = t
         if best is None or t < best["ms"]:
             best = {"waves": waves, "chan_block": cb, "ms": t}
