@@ -80,7 +80,6 @@ struct Rows {
 // slots) for up to `ucap` units, then the 65 per-group offsets.  ucap is the
 // plan's largest block (a multiple of 4), so a chunk takes what the plan needs
 // rather than the 64 x chunk worst case, and more chunks fit in flight.
-constexpr int LDS_BYTES = 160 * 1024;
 constexpr int MAX_NBUF = 4;
 // Chunk metadata ring: two halves of 16 chunks, each chunk's staged-row sample
 // indices (up to the form's longest chunk, uint32) and the 17 entry-block

@@ -18,6 +18,8 @@ namespace hg {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kDeg = 3.14159265358979323846 / 180.0;
+// LDS a workgroup can hold on gfx950 (160 KB per compute unit)
+constexpr int LDS_BYTES = 160 * 1024;
 
 // Pixel groups (PG): 2 x 2 map pixels that share one neighbour walk and one
 // entry list; slot r = 2*(j&1) + (i&1).  Tiles: TILE_PGX x TILE_PGY groups

@@ -704,6 +704,23 @@ __device__ inline double kernel_weight(const KernelArgs& ka, double d2, const Pa
 // order into the group's entry list with their four FP32 weights.  HPX: the
 // map is a HEALPix patch, whose two rows have their own pixel RAs.
 constexpr int GATHER_WAVES = 4;
+// Candidates that pass the support test wait in a per-wave LDS queue (their
+// entry word and four haversines) until a whole wave of them is there, so
+// that the weights, most of the gather's arithmetic, are computed on full
+// waves of real pairs instead of on every candidate lane; GATHER_QCAP holds
+// one wave's worth left over plus one pass.  The elliptical kernel, whose
+// weight needs more of each pair's geometry, computes in place.
+constexpr int GATHER_QCAP = 128;
+constexpr size_t GATHER_QUEUE_BYTES = GATHER_QCAP * (4 * sizeof(double) + sizeof(uint32_t));
+inline size_t gather_lds_bytes(int64_t npc) {
+    const size_t lists = (size_t)GATHER_WAVES * 3 * (npc + 1) * sizeof(int);
+    return (lists + 15) / 16 * 16 + (size_t)GATHER_WAVES * GATHER_QUEUE_BYTES;
+}
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 constexpr int BUCKET_WAVES = 4;
 // tiles whose chunks' presence words (one 64-bit word per 64 positions of a
 // chunk) number at most this many are dealt (chunk = compacted slot mod the
@@ -730,6 +747,11 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
     int* ppos = pref + (npc + 1);
     int* pslot = ppos + (npc + 1);
     const int4* pp = pg_piece + pg * npc;
+    constexpr bool QUEUE = KT != HG_KERNEL_ELLIPTICAL;
+    const size_t lists = ((size_t)GATHER_WAVES * 3 * (npc + 1) * sizeof(int) + 15) / 16 * 16;
+    double* qh = (double*)((char*)sh_gather + lists + (size_t)wave * GATHER_QUEUE_BYTES);
+    uint32_t* qkey = (uint32_t*)(qh + 4 * GATHER_QCAP);
+    int qn = 0;  // queued candidates (wave-uniform)
     if (lane == 0) {
         int s = 0;
         for (int k = 0; k < npc; k++) {
@@ -775,6 +797,29 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
         cn = srt_coord[ppos[lo] + off];
         sn = (uint32_t)(pslot[lo] + off);
     }
+    // Weights of the first n queued candidates, one a lane, written to the
+    // entry list after those written before (QUEUE only).
+    auto drain = [&](int n) {
+        if (lane < n) {
+            const uint32_t key = qkey[lane];
+            const uint32_t mk = key >> SLOT_SHIFT;
+            const PairGeom g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            float wq[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const double h = qh[k * GATHER_QCAP + lane];
+                float wf = 0.f;
+                if ((mk >> k) & 1u)
+                    wf = round_weight((float)kernel_weight<KT>(ka, dist2<SMALL>(h), g), prec);
+                wq[k] = wf;
+                cnt[k] += (mk >> k) & 1u;
+                wsum[k] += (double)wf;
+            }
+            ent_slot[base_out + written + lane] = key;
+            ent_w[base_out + written + lane] = make_float4(wq[0], wq[1], wq[2], wq[3]);
+        }
+        written += n;
+    };
     for (int v0 = 0; v0 < total; v0 += 64) {
         int v = v0 + lane;
         bool active = v < total;
@@ -788,6 +833,7 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
             cn = srt_coord[ppos[lo] + off];
             sn = (uint32_t)(pslot[lo] + off);
         }
+        double hk[4] = {0.0, 0.0, 0.0, 0.0};
         if (active) {
             double sd0, sd1, sa[4];
             half_sines(0.5 * (c.y - pdec0), 0.5 * (c.y - pdec1), 0.5 * (c.x - pra[0]),
@@ -800,7 +846,6 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 sa[2] = sa[0];
                 sa[3] = sa[1];
             }
-            double hk[4];
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 bool ok = ((k & 1) == 0 || vx1) && ((k >> 1) == 0 || vy1);
@@ -810,53 +855,86 @@ __global__ __launch_bounds__(64 * GATHER_WAVES) void k_gather(
                 hk[k] = sd * sd + pc * c.z * sa_k * sa_k;
                 if (ok && hk[k] <= h_r) mask |= 1u << k;
             }
-            // The four pixels' weights in turn, each pixel rotated through the
-            // first place; the loop is unrolled, so the rotations are only
-            // renamings (four inlined copies of each shape's weight hold fewer
-            // live registers than one copy in a loop did).  The elliptical
-            // kernel's pair geometry rotates with the pixels (unused by the
-            // other shapes, so it costs them nothing).
-            double h0 = hk[0], h1 = hk[1], h2 = hk[2], h3 = hk[3];
-            double s0 = sa[0], s1 = sa[1], s2 = sa[2], s3 = sa[3];
-            double r0 = c.x - pra[0], r1 = c.x - pra[1], r2 = c.x - pra[2], r3 = c.x - pra[3];
-            uint32_t mk = mask;
+            if constexpr (!QUEUE) {
+                // The four pixels' weights in turn, each pixel and its pair
+                // geometry rotated through the first place; the loop is
+                // unrolled, so the rotations are only renamings (four inlined
+                // copies of the weight hold fewer live registers than one copy
+                // in a loop did).
+                double h0 = hk[0], h1 = hk[1], h2 = hk[2], h3 = hk[3];
+                double s0 = sa[0], s1 = sa[1], s2 = sa[2], s3 = sa[3];
+                double r0 = c.x - pra[0], r1 = c.x - pra[1], r2 = c.x - pra[2], r3 = c.x - pra[3];
+                uint32_t mk = mask;
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                float wf = 0.f;
-                if (mk & 1u) {
-                    const PairGeom g{s0, r0, c.z, c.w, (k >> 1) ? pcos1 : pcos0,
-                                     (k >> 1) ? psin1 : psin0};
-                    wf = round_weight((float)kernel_weight<KT>(ka, dist2<SMALL>(h0), g), prec);
+                for (int k = 0; k < 4; k++) {
+                    float wf = 0.f;
+                    if (mk & 1u) {
+                        const PairGeom g{s0, r0, c.z, c.w, (k >> 1) ? pcos1 : pcos0,
+                                         (k >> 1) ? psin1 : psin0};
+                        wf = round_weight((float)kernel_weight<KT>(ka, dist2<SMALL>(h0), g), prec);
+                    }
+                    h0 = h1;
+                    h1 = h2;
+                    h2 = h3;
+                    s0 = s1;
+                    s1 = s2;
+                    s2 = s3;
+                    r0 = r1;
+                    r1 = r2;
+                    r2 = r3;
+                    w[0] = w[1];
+                    w[1] = w[2];
+                    w[2] = w[3];
+                    w[3] = wf;
+                    mk >>= 1;
                 }
-                h0 = h1;
-                h1 = h2;
-                h2 = h3;
-                s0 = s1;
-                s1 = s2;
-                s2 = s3;
-                r0 = r1;
-                r1 = r2;
-                r2 = r3;
-                w[0] = w[1];
-                w[1] = w[2];
-                w[2] = w[3];
-                w[3] = wf;
-                mk >>= 1;
-            }
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                cnt[k] += (mask >> k) & 1u;
-                wsum[k] += (double)w[k];
+                for (int k = 0; k < 4; k++) {
+                    cnt[k] += (mask >> k) & 1u;
+                    wsum[k] += (double)w[k];
+                }
             }
         }
         bool keep = active && mask != 0;
         uint64_t bal = __ballot(keep);
-        if (keep) {
-            int o = written + __popcll(bal & ((1ull << lane) - 1ull));
-            ent_slot[base_out + o] = slot | (mask << SLOT_SHIFT);
-            ent_w[base_out + o] = make_float4(w[0], w[1], w[2], w[3]);
+        if constexpr (QUEUE) {
+            // append in candidate order (the entry list stays in slot order)
+            if (keep) {
+                int o = qn + __popcll(bal & ((1ull << lane) - 1ull));
+                qkey[o] = slot | (mask << SLOT_SHIFT);
+#pragma unroll
+                for (int k = 0; k < 4; k++) qh[k * GATHER_QCAP + o] = hk[k];
+            }
+            qn += __popcll(bal);
+            if (qn >= 64) {
+                wave_lds_sync();
+                drain(64);
+                // move the rest (fewer than 64) to the front; each lane moves
+                // its own entry, reading and writing one place apart by 64
+                const int rest = qn - 64;
+                if (lane < rest) {
+                    qkey[lane] = qkey[64 + lane];
+#pragma unroll
+                    for (int k = 0; k < 4; k++)
+                        qh[k * GATHER_QCAP + lane] = qh[k * GATHER_QCAP + 64 + lane];
+                }
+                wave_lds_sync();
+                qn = rest;
+            }
+        } else {
+            if (keep) {
+                int o = written + __popcll(bal & ((1ull << lane) - 1ull));
+                ent_slot[base_out + o] = slot | (mask << SLOT_SHIFT);
+                ent_w[base_out + o] = make_float4(w[0], w[1], w[2], w[3]);
+            }
+            written += __popcll(bal);
         }
-        written += __popcll(bal);
+    }
+    if constexpr (QUEUE) {
+        if (qn > 0) {
+            wave_lds_sync();
+            drain(qn);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
@@ -1651,7 +1729,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     status = HG_OK;
     std::vector<RowInfo> trows, prows;
     plan_rows(P, trows, prows, eps);
-    if (P.pg_rings > 2000) {
+    if (gather_lds_bytes(2 * (int64_t)P.pg_rings) > (size_t)LDS_BYTES) {
         status = HG_ERR_UNSUPPORTED;
         err = "support spans too many HEALPix rings; use a coarser nside";
         return hipSuccess;
@@ -1931,7 +2009,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                        (const uint32_t*)P.srt_idx.p, (uint32_t*)P.slot_idx.p);
     HG_STEP(hipGetLastError());
     {
-        size_t shm = (size_t)GATHER_WAVES * 3 * (npc_p + 1) * sizeof(int);
+        const size_t shm = gather_lds_bytes(npc_p);
         const KernelArgs ka = kernel_args(P);
         // every in-support h is at most h_r; below 1e-4 no asin is needed
         const bool small = P.h_r < 1e-4;
