@@ -1507,6 +1507,25 @@ inline unsigned fill_grid(int64_t n_blocks) {
     return (unsigned)(((n_blocks + 4 * FILL_XCDS - 1) / (4 * FILL_XCDS)) * FILL_XCDS);
 }
 
+// A unit's weight record is NV 16-byte rows, one unit a lane.  Stored from
+// registers, each store instruction would write one row a lane, 16 NV bytes
+// apart, touching every cache line of the wave's records NV times; through
+// LDS (this wave's own NV KB), each store instruction writes 1 KB contiguous.
+// Records of units at or past nvalid (relative to the first) are not stored.
+template <int NV>
+__device__ inline void store_records(uint4* __restrict__ dst, const uint4 (&rec)[NV], int nvalid,
+                                     uint4* tw, int lane) {
+#pragma unroll
+    for (int v = 0; v < NV; v++) tw[lane * NV + v] = rec[v];
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < NV; j++) {
+        const int idx = j * 64 + lane;
+        if (idx < nvalid * NV) dst[idx] = tw[idx];
+    }
+    wave_lds_sync();
+}
+
 // One wave per block: lane l knows group l's run (first entry, count); the
 // block's units are then written flat, lane i taking units i and i + 64 of
 // each pass of 128 (coalesced writes; both units' loads in flight together).
@@ -1518,9 +1537,11 @@ __global__ __launch_bounds__(256) void k_block_fill(
     const uint32_t* __restrict__ perm,
     const int64_t* __restrict__ blk_base,
     float4* __restrict__ e2_w, uint4* __restrict__ e2_s) {
+    __shared__ uint4 sh_rec[4][64 * 4];
+    uint4* tw = sh_rec[threadIdx.x >> 6];
     const int64_t b = fill_block(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (b >= n_blocks) return;  // uniform per wave
+    if (b >= n_blocks) return;  // uniform per wave; only wave-level syncs below
     const int64_t base = blk_base[b];
     BlockLane r = block_lane_at(b, blk_tile[b], lane, npgx, npgy, ntx, tile_blk, cp_base,
                                 chunk_ptr, pg_base);
@@ -1531,26 +1552,27 @@ __global__ __launch_bounds__(256) void k_block_fill(
         const UnitRef ua = unit_ref(ia, first, r.src, r.pgb, r.n);
         const UnitRef ub = unit_ref(ib, first, r.src, r.pgb, r.n);
         uint32_t sa[4], sb[4];
-        float4 wa[4], wb[4];
+        float4 wa[4] = {}, wb[4] = {};
         if (ia < nu) load_unit(ua, ent_w, perm, sa, wa);
         if (ib < nu) load_unit(ub, ent_w, perm, sb, wb);
+        if (ia < nu) e2_s[base + ia] = make_uint4(sa[0], sa[1], sa[2], sa[3]);
+        if (ib < nu) e2_s[base + ib] = make_uint4(sb[0], sb[1], sb[2], sb[3]);
         // [pixel q][entry k]: pixel q's weights for the unit's four entries
-        if (ia < nu) {
-            e2_s[base + ia] = make_uint4(sa[0], sa[1], sa[2], sa[3]);
-            float4* wd = e2_w + (base + ia) * 4;
-            wd[0] = make_float4(wa[0].x, wa[1].x, wa[2].x, wa[3].x);
-            wd[1] = make_float4(wa[0].y, wa[1].y, wa[2].y, wa[3].y);
-            wd[2] = make_float4(wa[0].z, wa[1].z, wa[2].z, wa[3].z);
-            wd[3] = make_float4(wa[0].w, wa[1].w, wa[2].w, wa[3].w);
-        }
-        if (ib < nu) {
-            e2_s[base + ib] = make_uint4(sb[0], sb[1], sb[2], sb[3]);
-            float4* wd = e2_w + (base + ib) * 4;
-            wd[0] = make_float4(wb[0].x, wb[1].x, wb[2].x, wb[3].x);
-            wd[1] = make_float4(wb[0].y, wb[1].y, wb[2].y, wb[3].y);
-            wd[2] = make_float4(wb[0].z, wb[1].z, wb[2].z, wb[3].z);
-            wd[3] = make_float4(wb[0].w, wb[1].w, wb[2].w, wb[3].w);
-        }
+        auto rows = [](const float4 w[4], uint4 (&r)[4]) {
+            r[0] = make_uint4(__float_as_uint(w[0].x), __float_as_uint(w[1].x),
+                              __float_as_uint(w[2].x), __float_as_uint(w[3].x));
+            r[1] = make_uint4(__float_as_uint(w[0].y), __float_as_uint(w[1].y),
+                              __float_as_uint(w[2].y), __float_as_uint(w[3].y));
+            r[2] = make_uint4(__float_as_uint(w[0].z), __float_as_uint(w[1].z),
+                              __float_as_uint(w[2].z), __float_as_uint(w[3].z));
+            r[3] = make_uint4(__float_as_uint(w[0].w), __float_as_uint(w[1].w),
+                              __float_as_uint(w[2].w), __float_as_uint(w[3].w));
+        };
+        uint4 r[4];
+        rows(wa, r);
+        store_records<4>((uint4*)e2_w + (base + i0) * 4, r, nu - i0, tw, lane);
+        rows(wb, r);
+        store_records<4>((uint4*)e2_w + (base + i0 + 64) * 4, r, nu - i0 - 64, tw, lane);
     }
 }
 
@@ -1619,10 +1641,9 @@ __device__ inline uint16_t weight_bits(float w, int32_t prec) {
     return u;
 }
 
-__device__ inline void store_unit_g(uint16_t* e3_w, uint4* e3_s, int64_t at, const uint32_t sl[4],
-                                    const float4 w[4], int32_t prec) {
-    e3_s[at] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
-    // [pixel q][entry k] halves, packed in pairs: two 16-byte stores
+// A unit's weights in the MFMA input type, [pixel q][entry k] halves packed
+// in pairs: two 16-byte rows.
+__device__ inline void unit_rows_g(const float4 w[4], int32_t prec, uint4 (&r)[2]) {
     const float wk[4][4] = {{w[0].x, w[0].y, w[0].z, w[0].w},
                             {w[1].x, w[1].y, w[1].z, w[1].w},
                             {w[2].x, w[2].y, w[2].z, w[2].w},
@@ -1634,9 +1655,8 @@ __device__ inline void store_unit_g(uint16_t* e3_w, uint4* e3_s, int64_t at, con
         wb[j] = (uint32_t)weight_bits(wk[k][q], prec) |
                 ((uint32_t)weight_bits(wk[k + 1][q], prec) << 16);
     }
-    uint4* wd = (uint4*)(e3_w + at * 16);
-    wd[0] = make_uint4(wb[0], wb[1], wb[2], wb[3]);
-    wd[1] = make_uint4(wb[4], wb[5], wb[6], wb[7]);
+    r[0] = make_uint4(wb[0], wb[1], wb[2], wb[3]);
+    r[1] = make_uint4(wb[4], wb[5], wb[6], wb[7]);
 }
 
 // k_block_fill for the 16-bit forms: the same walk over a block's units (groups
@@ -1649,9 +1669,11 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
     const uint32_t* __restrict__ perm,
     const int64_t* __restrict__ blk_base,
     uint16_t* __restrict__ e3_w, uint4* __restrict__ e3_s) {
+    __shared__ uint4 sh_rec[4][64 * 2];
+    uint4* tw = sh_rec[threadIdx.x >> 6];
     const int64_t b = fill_block(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (b >= n_blocks) return;  // uniform per wave
+    if (b >= n_blocks) return;  // uniform per wave; only wave-level syncs below
     const int64_t base = blk_base[b];
     BlockLane r = block_lane_at(b, blk_tile[b], lane, npgx, npgy, ntx, tile_blk, cp_base,
                                 chunk_ptr, pg_base);
@@ -1662,11 +1684,16 @@ __global__ __launch_bounds__(256) void k_block_fill_g(
         const UnitRef ua = unit_ref(ia, first, r.src, r.pgb, r.n);
         const UnitRef ub = unit_ref(ib, first, r.src, r.pgb, r.n);
         uint32_t sa[4], sb[4];
-        float4 wa[4], wb[4];
+        float4 wa[4] = {}, wb[4] = {};
         if (ia < nu) load_unit(ua, ent_w, perm, sa, wa);
         if (ib < nu) load_unit(ub, ent_w, perm, sb, wb);
-        if (ia < nu) store_unit_g(e3_w, e3_s, base + ia, sa, wa, prec);
-        if (ib < nu) store_unit_g(e3_w, e3_s, base + ib, sb, wb, prec);
+        if (ia < nu) e3_s[base + ia] = make_uint4(sa[0], sa[1], sa[2], sa[3]);
+        if (ib < nu) e3_s[base + ib] = make_uint4(sb[0], sb[1], sb[2], sb[3]);
+        uint4 r[2];
+        unit_rows_g(wa, prec, r);
+        store_records<2>((uint4*)e3_w + (base + i0) * 2, r, nu - i0, tw, lane);
+        unit_rows_g(wb, prec, r);
+        store_records<2>((uint4*)e3_w + (base + i0 + 64) * 2, r, nu - i0 - 64, tw, lane);
     }
 }
 
