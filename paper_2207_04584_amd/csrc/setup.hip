@@ -722,6 +722,7 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 constexpr int BUCKET_WAVES = 4;
+constexpr int BUCKET_REGS = 16;  // slot words a lane holds per round of the bucketing
 // tiles whose chunks' presence words (one 64-bit word per 64 positions of a
 // chunk) number at most this many are dealt (chunk = compacted slot mod the
 // chunk count); denser tiles keep consecutive slots per chunk
@@ -1048,6 +1049,11 @@ __device__ inline int64_t pg_tile(int64_t pg, int32_t npgx, int32_t ntx) {
     return (int64_t)(gy / TILE_PGY) * ntx + gx / TILE_PGX;
 }
 
+// entries a lane keeps in flight in the slot marking and remapping (16 kept
+// the marking as it was and slowed the remapping, 0.039 -> 0.050 ms on a
+// million samples, at six waves a SIMD instead of eight)
+constexpr int ENTRY_REGS = 4;
+
 __global__ __launch_bounds__(256) void k_mark_used(
     int32_t npgx, int64_t npg, int32_t ntx, const int64_t* __restrict__ tile_base,
     const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ pg_cnt,
@@ -1058,17 +1064,17 @@ __global__ __launch_bounds__(256) void k_mark_used(
     const int64_t tb = tile_base[pg_tile(pg, npgx, ntx)];
     const uint32_t* es = ent_slot + pg_base[pg];
     const uint32_t n = pg_cnt[pg];
-    // four entries a lane per pass, their loads in flight together (a group
-    // of a wide support holds thousands of entries)
-    for (uint32_t t0 = 0; t0 < n; t0 += 256) {
-        uint32_t w[4];
+    // ENTRY_REGS entries a lane per pass, their loads in flight together (a
+    // group of a wide support holds thousands of entries)
+    for (uint32_t t0 = 0; t0 < n; t0 += 64 * ENTRY_REGS) {
+        uint32_t w[ENTRY_REGS];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < ENTRY_REGS; k++) {
             const uint32_t t = t0 + lane + 64 * k;
             w[k] = t < n ? es[t] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < 4; k++)
+        for (int k = 0; k < ENTRY_REGS; k++)
             if (t0 + lane + 64 * k < n) used[tb + (w[k] & SLOT_MASK)] = 1u;
     }
 }
@@ -1117,21 +1123,21 @@ __global__ __launch_bounds__(256) void k_remap_entries(
     const int64_t nch = tile_nch[tile];
     uint32_t* es = ent_slot + pg_base[pg];
     const uint32_t n = pg_cnt[pg];
-    // four entries a lane per pass: their loads, then their position lookups,
-    // each in flight together
-    for (uint32_t t0 = 0; t0 < n; t0 += 256) {
-        uint32_t w[4];
-        int64_t np[4];
+    // ENTRY_REGS entries a lane per pass: their loads, then their position
+    // lookups, each in flight together
+    for (uint32_t t0 = 0; t0 < n; t0 += 64 * ENTRY_REGS) {
+        uint32_t w[ENTRY_REGS];
+        int64_t np[ENTRY_REGS];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < ENTRY_REGS; k++) {
             const uint32_t t = t0 + lane + 64 * k;
             w[k] = t < n ? es[t] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < 4; k++)
+        for (int k = 0; k < ENTRY_REGS; k++)
             np[k] = t0 + lane + 64 * k < n ? newpos[tb + (w[k] & SLOT_MASK)] : tb2;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < ENTRY_REGS; k++) {
             const uint32_t t = t0 + lane + 64 * k;
             const int64_t p = np[k] - tb2;
             const uint32_t loc = scr ? dealt_slot(p, nch, chunk) : (uint32_t)p;
@@ -1192,15 +1198,17 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     const int32_t* __restrict__ tile_scr, const int64_t* __restrict__ cp_base,
     const int64_t* __restrict__ pg_base, const uint32_t* __restrict__ pg_cnt,
     const uint32_t* __restrict__ ent_slot, uint32_t* __restrict__ chunk_ptr,
-    uint32_t* __restrict__ perm) {
+    uint32_t* __restrict__ perm, int32_t words) {
     static_assert(MAX_CHUNK <= 128, "a chunk's positions fit two 64-bit words");
-    __shared__ unsigned long long bits_all[BUCKET_WAVES][SCRAMBLE_MAX_WORDS];
-    __shared__ uint32_t ptr_all[BUCKET_WAVES][SCRAMBLE_MAX_WORDS];
+    // per wave: `words` presence words and as many chunk pointers; words
+    // bounds nch * chunk_words(chunk) of every dealt tile (the host sizes it
+    // from the largest chunk count before compaction, which only drops slots)
+    extern __shared__ unsigned long long sh_bucket[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t pg = (int64_t)blockIdx.x * BUCKET_WAVES + wave;
     if (pg >= npg) return;  // uniform per wave; no workgroup barrier below
-    unsigned long long* bits = bits_all[wave];
-    uint32_t* ptr = ptr_all[wave];
+    unsigned long long* bits = sh_bucket + (int64_t)wave * words;
+    uint32_t* ptr = (uint32_t*)(sh_bucket + (int64_t)BUCKET_WAVES * words) + (int64_t)wave * words;
     const int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
     const int64_t tile = (int64_t)(gy / TILE_PGY) * ntx + gx / TILE_PGX;
     const int lp = (gy % TILE_PGY) * TILE_PGX + gx % TILE_PGX;
@@ -1231,9 +1239,23 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     const int nw = chunk_words(chunk);
     for (int64_t i = lane; i < nch * nw; i += 64) bits[i] = 0ull;
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t t = lane; t < ne; t += 64) {
-        const uint32_t loc = es[t] & SLOT_MASK, c = loc / chunk, j = loc % chunk;
-        atomicOr(&bits[c * nw + j / 64], 1ull << (j % 64));
+    // the group's slot words come BUCKET_REGS a lane at a time, all loads of
+    // a round issued before any is used, so that a wave waits for memory once
+    // a round rather than once an entry
+    for (uint32_t t0 = 0; t0 < ne; t0 += 64 * BUCKET_REGS) {
+        uint32_t loc[BUCKET_REGS];
+#pragma unroll
+        for (int k = 0; k < BUCKET_REGS; k++) {
+            const uint32_t t = t0 + lane + 64 * k;
+            loc[k] = t < ne ? es[t] & SLOT_MASK : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < BUCKET_REGS; k++) {
+            if (t0 + lane + 64 * k < ne) {
+                const uint32_t c = loc[k] / chunk, j = loc[k] % chunk;
+                atomicOr(&bits[c * nw + j / 64], 1ull << (j % 64));
+            }
+        }
     }
     __builtin_amdgcn_wave_barrier();
     // exclusive scan of the chunks' entry counts: the chunk pointers
@@ -1257,13 +1279,26 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     }
     if (lane == 0) cp[nch] = carry;
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t t = lane; t < ne; t += 64) {
-        const uint32_t loc = es[t] & SLOT_MASK, c = loc / chunk, j = loc % chunk;
-        const unsigned long long* cw = bits + c * nw;
-        uint32_t at = ptr[c];
-        for (uint32_t w = 0; w < j / 64; w++) at += (uint32_t)__builtin_popcountll(cw[w]);
-        const unsigned long long below = (1ull << (j % 64)) - 1ull;
-        pm[at + (uint32_t)__builtin_popcountll(cw[j / 64] & below)] = (t << PERM_POS_BITS) | j;
+    for (uint32_t t0 = 0; t0 < ne; t0 += 64 * BUCKET_REGS) {
+        uint32_t loc[BUCKET_REGS];
+#pragma unroll
+        for (int k = 0; k < BUCKET_REGS; k++) {
+            const uint32_t t = t0 + lane + 64 * k;
+            loc[k] = t < ne ? es[t] & SLOT_MASK : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < BUCKET_REGS; k++) {
+            const uint32_t t = t0 + lane + 64 * k;
+            if (t < ne) {
+                const uint32_t c = loc[k] / chunk, j = loc[k] % chunk;
+                const unsigned long long* cw = bits + c * nw;
+                uint32_t at = ptr[c];
+                for (uint32_t w = 0; w < j / 64; w++) at += (uint32_t)__builtin_popcountll(cw[w]);
+                const unsigned long long below = (1ull << (j % 64)) - 1ull;
+                pm[at + (uint32_t)__builtin_popcountll(cw[j / 64] & below)] =
+                    (t << PERM_POS_BITS) | j;
+            }
+        }
     }
 }
 
@@ -1864,7 +1899,8 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
             {P.pix_W.p, 2 * P.npix},
             {P.pix_Wf.p, P.npix},
             {P.pg_cnt.p, P.npg},
-            {wl.p, 2}};
+            {wl.p, 2},
+            {totals.p, 16}};
         int64_t most = 0;
         for (const auto& b : bufs) {
             z.p[z.n] = (uint32_t*)b.first;
@@ -1938,6 +1974,12 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (int4*)P.tile_piece.p, P.ntiles, P.tile_rings, P.chunk,
                            (int64_t*)tslots.p, (int64_t*)tcp.p, (int64_t*)tnch.p, flag);
         HG_STEP(hipGetLastError());
+        // the most chunks a tile has before compaction (totals[6]): sizes the
+        // bucketing's LDS
+        hipLaunchKernelGGL(k_max_count, dim3(std::max<unsigned>(1, std::min<unsigned>(256, blocks_for(P.ntiles, 256)))),
+                           dim3(256), 0, s, (const int64_t*)tnch.p, P.ntiles,
+                           (int*)((int64_t*)totals.p + 6));
+        HG_STEP(hipGetLastError());
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tnch.p, P.ntiles,
                                                   (int64_t*)P.tile_blk.p, (int64_t*)scan_tmp, s)));
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tslots.p, P.ntiles,
@@ -1963,10 +2005,11 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                        P.npg, (const int64_t*)P.cp_base.p, (const int64_t*)P.tile_blk.p,
                        (const int*)flag, (int64_t*)totals.p);
     HG_STEP(hipGetLastError());
-    HG_STEP(hipMemcpyAsync(back, totals.p, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HG_STEP(hipMemcpyAsync(back, totals.p, 7 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HG_STEP(hipStreamSynchronize(s));
-    int64_t tot[6];
-    std::copy(back, back + 6, tot);
+    int64_t tot[7];
+    std::copy(back, back + 7, tot);
+    const int64_t nch_pre_max = tot[6];
     P.n_used = tot[0];
     P.total_slots = tot[1];
     P.ent_cap = tot[2];
@@ -2108,12 +2151,17 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                                   (int64_t*)P.tile_blk.p, (int64_t*)scan_tmp, s)));
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tcp.p, P.ntiles,
                                                   (int64_t*)P.cp_base.p, (int64_t*)scan_tmp, s)));
+        // LDS for the largest dealt tile only (not the dealt limit), so that
+        // more groups' waves are resident on the usual workloads
+        const int32_t words = (int32_t)std::max<int64_t>(
+            1, std::min<int64_t>(SCRAMBLE_MAX_WORDS, nch_pre_max * chunk_words(P.chunk)));
+        const size_t bshm = (size_t)BUCKET_WAVES * words * (sizeof(unsigned long long) + 4);
         hipLaunchKernelGGL(k_bucket_entries, dim3(blocks_for(P.npg, BUCKET_WAVES)),
-                           dim3(64 * BUCKET_WAVES), 0, s, P.npgx, P.npg, P.ntx, P.chunk,
+                           dim3(64 * BUCKET_WAVES), bshm, s, P.npgx, P.npg, P.ntx, P.chunk,
                            (const int64_t*)P.tile_blk.p, (const int32_t*)tscr.p,
                            (const int64_t*)P.cp_base.p, (const int64_t*)P.pg_base.p,
                            (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
-                           (uint32_t*)P.chunk_ptr.p, (uint32_t*)perm.p);
+                           (uint32_t*)P.chunk_ptr.p, (uint32_t*)perm.p, words);
         HG_STEP(hipGetLastError());
         // the slot total after padding: read back with the other sizes below
         HG_STEP(hipMemcpyAsync(slot_total, (int64_t*)tbase3.p + P.ntiles, 8,
