@@ -79,9 +79,10 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_bsums(Tout* bsum, int64_t nb) {
     }
 }
 
+// out2 (may be NULL): a second copy of out[0 .. n)
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(SCAN_T) void k_scan_final(const Tin* in, int64_t n, const Tout* bsum,
-                                                       Tout* out) {
+                                                       Tout* out, Tout* out2) {
     __shared__ Tout vals[SCAN_B];
     __shared__ Tout sh[SCAN_T / 64 + 1];
     int64_t base = (int64_t)blockIdx.x * SCAN_B;
@@ -102,7 +103,10 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_final(const Tin* in, int64_t n,
     __syncthreads();
     for (int k = 0; k < SCAN_I; k++) {
         int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
-        if (i < n) out[i] = vals[k * SCAN_T + threadIdx.x];
+        if (i < n) {
+            out[i] = vals[k * SCAN_T + threadIdx.x];
+            if (out2) out2[i] = vals[k * SCAN_T + threadIdx.x];
+        }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = run;
 }
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_final(const Tin* in, int64_t n,
 constexpr int64_t SCAN_ONE_MAX = 2 * SCAN_B;
 
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(SCAN_T) void k_scan_one(const Tin* in, int64_t n, Tout* out) {
+__device__ inline void scan_one(const Tin* in, int64_t n, Tout* out, Tout* out2) {
     __shared__ Tout vals[SCAN_B];
     __shared__ Tout sh[SCAN_T / 64 + 1];
     Tout carry = 0;
@@ -135,7 +139,10 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_one(const Tin* in, int64_t n, T
         __syncthreads();
         for (int k = 0; k < SCAN_I; k++) {
             int64_t i = base + (int64_t)k * SCAN_T + threadIdx.x;
-            if (i < n) out[i] = vals[k * SCAN_T + threadIdx.x];
+            if (i < n) {
+                out[i] = vals[k * SCAN_T + threadIdx.x];
+                if (out2) out2[i] = vals[k * SCAN_T + threadIdx.x];
+            }
         }
         carry += tot;
         __syncthreads();  // vals is refilled by the next tile
@@ -143,11 +150,30 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_one(const Tin* in, int64_t n, T
     if (threadIdx.x == 0) out[n] = carry;
 }
 
-// scratch must hold ceil(n / SCAN_B) Tout
 template <typename Tin, typename Tout>
-hipError_t scan_exclusive(const Tin* in, int64_t n, Tout* out, Tout* scratch, hipStream_t s) {
+__global__ __launch_bounds__(SCAN_T) void k_scan_one(const Tin* in, int64_t n, Tout* out,
+                                                     Tout* out2) {
+    scan_one<Tin, Tout>(in, n, out, out2);
+}
+
+// Up to SCAN_MANY short int64 arrays of one length, one workgroup each, in one
+// launch (the planner's per-tile counts are scanned three at a time).
+constexpr int SCAN_MANY = 3;
+struct ScanJobs {
+    const int64_t* in[SCAN_MANY];
+    int64_t* out[SCAN_MANY];
+};
+__global__ __launch_bounds__(SCAN_T) void k_scan_many(ScanJobs j, int64_t n) {
+    scan_one<int64_t, int64_t>(j.in[blockIdx.x], n, j.out[blockIdx.x], nullptr);
+}
+
+// scratch must hold ceil(n / SCAN_B) Tout
+// out2 (may be NULL): a second copy of the n exclusive sums (not the total)
+template <typename Tin, typename Tout>
+hipError_t scan_exclusive(const Tin* in, int64_t n, Tout* out, Tout* scratch, hipStream_t s,
+                          Tout* out2 = nullptr) {
     if (n <= SCAN_ONE_MAX) {
-        hipLaunchKernelGGL((k_scan_one<Tin, Tout>), dim3(1), dim3(SCAN_T), 0, s, in, n, out);
+        hipLaunchKernelGGL((k_scan_one<Tin, Tout>), dim3(1), dim3(SCAN_T), 0, s, in, n, out, out2);
         return hipGetLastError();
     }
     int64_t nb = (n + SCAN_B - 1) / SCAN_B;
@@ -156,8 +182,28 @@ hipError_t scan_exclusive(const Tin* in, int64_t n, Tout* out, Tout* scratch, hi
                        scratch);
     hipLaunchKernelGGL((k_scan_bsums<Tout>), dim3(1), dim3(SCAN_T), 0, s, scratch, nb);
     hipLaunchKernelGGL((k_scan_final<Tin, Tout>), dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n,
-                       scratch, out);
+                       scratch, out, out2);
     return hipGetLastError();
+}
+
+// scan_exclusive of k <= SCAN_MANY int64 arrays of length n: one launch when
+// they are short, else one scan after another (sharing the scratch)
+hipError_t scan_exclusive_many(const int64_t* const* in, int64_t* const* out, int k, int64_t n,
+                               int64_t* scratch, hipStream_t s) {
+    if (n <= SCAN_ONE_MAX) {
+        ScanJobs j{};
+        for (int i = 0; i < k; i++) {
+            j.in[i] = in[i];
+            j.out[i] = out[i];
+        }
+        hipLaunchKernelGGL(k_scan_many, dim3((unsigned)k), dim3(SCAN_T), 0, s, j, n);
+        return hipGetLastError();
+    }
+    for (int i = 0; i < k; i++) {
+        hipError_t e = scan_exclusive<int64_t, int64_t>(in[i], n, out[i], scratch, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -436,7 +482,7 @@ __global__ void k_tile_plan(const RowInfo* __restrict__ rows, int32_t ntx, int64
 __global__ void k_tile_prefix(int4* __restrict__ tile_piece, int64_t ntiles, int32_t tile_rings,
                               int32_t chunk, int64_t* __restrict__ tile_nslots,
                               int64_t* __restrict__ tile_ncp, int64_t* __restrict__ tile_nch,
-                              int* flag) {
+                              int* flag, int* __restrict__ nch_max) {
     int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
     int4* tp = tile_piece + tile * tile_rings * 2;
@@ -449,8 +495,13 @@ __global__ void k_tile_prefix(int4* __restrict__ tile_piece, int64_t ntiles, int
     }
     if (s > (int64_t)SLOT_MASK) atomicOr(flag, 2);
     tile_nslots[tile] = s;
-    tile_ncp[tile] = (int64_t)TILE_PGS * ((s + chunk - 1) / chunk + 1);
-    tile_nch[tile] = (s + chunk - 1) / chunk;
+    const int64_t nch = (s + chunk - 1) / chunk;
+    tile_ncp[tile] = (int64_t)TILE_PGS * (nch + 1);
+    tile_nch[tile] = nch;
+    // *nch_max (from 0) only grows, so a value read is never above the
+    // current maximum and the read spares the atomics of smaller counts
+    const int c = (int)(nch < INT32_MAX ? nch : INT32_MAX);
+    if (c > *(volatile int*)nch_max) atomicMax(nch_max, c);
 }
 
 // Pixel-group pieces: the group's own ring / cell ranges, intersected with its
@@ -1886,7 +1937,6 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     int* flag = (int*)P.scratch.p;
     unsigned long long* nnz_total = (unsigned long long*)((char*)P.scratch.p + 8);
     int* blk_max = (int*)((char*)P.scratch.p + 16);  // most units in one block
-    int64_t* slot_total = (int64_t*)((char*)P.scratch.p + 24);  // after compaction
     int* run_max = (int*)((char*)P.scratch.p + 32);  // longest run past 64 entries, else 0
     void* scan_tmp = (char*)P.scratch.p + 64;
 
@@ -1930,11 +1980,11 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            flag);
         HG_STEP(hipGetLastError());
     }
+    // the scatter's cursors start as a copy of the cell offsets
     HG_STEP((scan_exclusive<uint32_t, uint32_t>((const uint32_t*)cnt.p, P.n_cells,
-                                                (uint32_t*)P.cell_off.p, (uint32_t*)scan_tmp, s)));
+                                                (uint32_t*)P.cell_off.p, (uint32_t*)scan_tmp, s,
+                                                n > 0 ? (uint32_t*)cursor.p : nullptr)));
     if (n > 0) {
-        HG_STEP(hipMemcpyAsync(cursor.p, P.cell_off.p, (size_t)P.n_cells * 4,
-                               hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                            (const uint32_t*)key.p, n, (uint32_t*)cursor.p, (uint32_t*)P.srt_idx.p);
         HG_STEP(hipGetLastError());
@@ -1970,23 +2020,20 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            P.cell_base, P.n_cells, (const uint32_t*)P.cell_off.p, P.map, eps,
                            (int4*)P.tile_piece.p, flag);
         HG_STEP(hipGetLastError());
+        // totals[6]: the most chunks a tile has before compaction (sizes the
+        // bucketing's LDS)
         hipLaunchKernelGGL(k_tile_prefix, dim3(blocks_for(P.ntiles, 256)), dim3(256), 0, s,
                            (int4*)P.tile_piece.p, P.ntiles, P.tile_rings, P.chunk,
-                           (int64_t*)tslots.p, (int64_t*)tcp.p, (int64_t*)tnch.p, flag);
-        HG_STEP(hipGetLastError());
-        // the most chunks a tile has before compaction (totals[6]): sizes the
-        // bucketing's LDS
-        hipLaunchKernelGGL(k_max_count, dim3(std::max<unsigned>(1, std::min<unsigned>(256, blocks_for(P.ntiles, 256)))),
-                           dim3(256), 0, s, (const int64_t*)tnch.p, P.ntiles,
+                           (int64_t*)tslots.p, (int64_t*)tcp.p, (int64_t*)tnch.p, flag,
                            (int*)((int64_t*)totals.p + 6));
         HG_STEP(hipGetLastError());
-        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tnch.p, P.ntiles,
-                                                  (int64_t*)P.tile_blk.p, (int64_t*)scan_tmp, s)));
-        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tslots.p, P.ntiles,
-                                                  (int64_t*)P.tile_nslots.p, (int64_t*)scan_tmp,
-                                                  s)));
-        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tcp.p, P.ntiles,
-                                                  (int64_t*)P.cp_base.p, (int64_t*)scan_tmp, s)));
+        {
+            const int64_t* in[] = {(const int64_t*)tnch.p, (const int64_t*)tslots.p,
+                                   (const int64_t*)tcp.p};
+            int64_t* out[] = {(int64_t*)P.tile_blk.p, (int64_t*)P.tile_nslots.p,
+                              (int64_t*)P.cp_base.p};
+            HG_STEP(scan_exclusive_many(in, out, 3, P.ntiles, (int64_t*)scan_tmp, s));
+        }
         int64_t np = P.npg * P.pg_rings;
         hipLaunchKernelGGL(k_pg_plan, dim3(blocks_for(np, 256)), dim3(256), 0, s,
                            rows_p, (const RowInfo*)rows_t.p, P.npgx, P.npg,
@@ -2113,7 +2160,15 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(dev_alloc(tbase3, sizeof(int64_t) * (size_t)(P.ntiles + 1)));
         HG_STEP(dev_alloc(slot3, (size_t)ts_pad * 4));
         HG_STEP(dev_alloc(perm, (size_t)(P.ent_cap ? P.ent_cap : 1) * 4));
-        HG_STEP(hipMemsetAsync(used.p, 0, (size_t)ts * 4, s));
+        {
+            ZeroList z{};
+            z.p[0] = (uint32_t*)used.p;
+            z.dwords[0] = ts;
+            z.n = 1;
+            hipLaunchKernelGGL(k_zero, dim3(std::max<unsigned>(1, std::min<unsigned>(2048, blocks_for(ts, 256)))),
+                               dim3(256), 0, s, z);
+            HG_STEP(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_mark_used, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
                            P.ntx, (const int64_t*)P.tile_nslots.p, (const int64_t*)P.pg_base.p,
                            (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
@@ -2144,13 +2199,15 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const int64_t*)tnch.p, (const int32_t*)tscr.p, P.chunk,
                            (const uint32_t*)slot2.p, (uint32_t*)slot3.p);
         HG_STEP(hipGetLastError());
+        // the dealt slot lists and their tile offsets replace the plan's (the
+        // old buffers go back to the cache with the transients)
         std::swap(P.slot_idx, slot3);
-        HG_STEP(hipMemcpyAsync(P.tile_nslots.p, tbase3.p, sizeof(int64_t) * (size_t)(P.ntiles + 1),
-                               hipMemcpyDeviceToDevice, s));
-        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tnch.p, P.ntiles,
-                                                  (int64_t*)P.tile_blk.p, (int64_t*)scan_tmp, s)));
-        HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tcp.p, P.ntiles,
-                                                  (int64_t*)P.cp_base.p, (int64_t*)scan_tmp, s)));
+        std::swap(P.tile_nslots, tbase3);
+        {
+            const int64_t* in[] = {(const int64_t*)tnch.p, (const int64_t*)tcp.p};
+            int64_t* out[] = {(int64_t*)P.tile_blk.p, (int64_t*)P.cp_base.p};
+            HG_STEP(scan_exclusive_many(in, out, 2, P.ntiles, (int64_t*)scan_tmp, s));
+        }
         // LDS for the largest dealt tile only (not the dealt limit), so that
         // more groups' waves are resident on the usual workloads
         const int32_t words = (int32_t)std::max<int64_t>(
@@ -2163,9 +2220,6 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
                            (uint32_t*)P.chunk_ptr.p, (uint32_t*)perm.p, words);
         HG_STEP(hipGetLastError());
-        // the slot total after padding: read back with the other sizes below
-        HG_STEP(hipMemcpyAsync(slot_total, (int64_t*)tbase3.p + P.ntiles, 8,
-                               hipMemcpyDeviceToDevice, s));
     } else {
         hipLaunchKernelGGL(k_chunk_ptr, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx,
                            P.npg, P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
@@ -2190,7 +2244,9 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                            (int64_t*)bcnt.p, (uint16_t*)P.blk_pgoff.p, (int32_t*)btile.p,
                            run_max);
         HG_STEP(hipGetLastError());
-        // the largest block sizes the channel kernel's LDS entry area
+        // the largest block sizes the channel kernel's LDS entry area (an
+        // atomic per block in the meta pass, read first to skip smaller
+        // counts, made that pass three times slower)
         hipLaunchKernelGGL(k_max_count, dim3(256), dim3(256), 0, s, (const int64_t*)bcnt.p,
                            P.n_blocks, blk_max);
         HG_STEP(hipGetLastError());
@@ -2201,7 +2257,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(sizes, sizeof(int64_t) * (size_t)(PACK_HEAD + P.ntiles + 1)));
     hipLaunchKernelGGL(k_pack_sizes, dim3(blocks_for(P.ntiles + 1, 256)), dim3(256), 0, s,
                        (const unsigned long long*)nnz_total, (const int64_t*)P.blk_base.p + P.n_blocks,
-                       (const int*)blk_max, (const int64_t*)slot_total,
+                       (const int*)blk_max, (const int64_t*)P.tile_nslots.p + P.ntiles,
                        (const int64_t*)P.cp_base.p + P.ntiles, (const int*)run_max,
                        (const int64_t*)P.tile_blk.p, P.ntiles, (int64_t*)sizes.p);
     HG_STEP(hipGetLastError());
