@@ -165,7 +165,7 @@ struct HostBuf {
 // tile * ncb + cb, or -1 for an idle workgroup (see launch_order).
 struct LaunchOrder {
     DevBuf items;               // int64 [n] on the device
-    std::vector<int64_t> host;  // the same on the host, the upload's source
+    HostBuf host;               // the same in page-locked memory, the upload's source
     hipEvent_t ready = nullptr; // recorded after the upload
     int64_t n = 0;
 };

@@ -213,7 +213,11 @@ void plan_free(Plan& P) {
     P.ev_free.clear();
     for (auto& kv : P.orders) {
         dev_free(kv.second.items);
-        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+        if (kv.second.ready) {
+            (void)hipEventSynchronize(kv.second.ready);  // the upload has read its source
+            (void)hipEventDestroy(kv.second.ready);
+        }
+        host_free(kv.second.host);
     }
     P.orders.clear();
 }
@@ -639,19 +643,30 @@ hipError_t launch_order(Plan& P, int32_t ncb, hipStream_t s, const int64_t** ite
         std::vector<int64_t> tb(P.tile_blk_host.begin() + t0, P.tile_blk_host.begin() + t1 + 1);
         for (auto& v : tb) v -= P.tile_blk_host[(size_t)t0];
         const std::vector<BatchItem> pos = plan_batch_items({tb}, {ncb}, n_items);
-        o.host.resize(pos.size());
-        for (size_t i = 0; i < pos.size(); i++)
-            o.host[i] = pos[i].field < 0 ? -1 : (t0 + pos[i].tile) * ncb + pos[i].cb;
         o.n = (int64_t)pos.size();
-        hipError_t e = dev_alloc(o.items, sizeof(int64_t) * (o.host.empty() ? 1 : o.host.size()));
+        // page-locked source: an upload from pageable memory is staged by the
+        // runtime, tens of microseconds before the first launch can start
+        const size_t bytes = sizeof(int64_t) * (size_t)(o.n ? o.n : 1);
+        hipError_t e = host_alloc(o.host, bytes);
+        if (e == hipSuccess) {
+            int64_t* h = (int64_t*)o.host.p;
+            for (size_t i = 0; i < pos.size(); i++)
+                h[i] = pos[i].field < 0 ? -1 : (t0 + pos[i].tile) * ncb + pos[i].cb;
+            e = dev_alloc(o.items, bytes);
+        }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&o.ready, hipEventDisableTiming);
-        if (e == hipSuccess && !o.host.empty())
-            e = hipMemcpyAsync(o.items.p, o.host.data(), sizeof(int64_t) * o.host.size(),
+        if (e == hipSuccess && o.n > 0)
+            e = hipMemcpyAsync(o.items.p, o.host.p, sizeof(int64_t) * (size_t)o.n,
                                hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipEventRecord(o.ready, s);
         if (e != hipSuccess) {
+            if (o.ready) {
+                (void)hipEventSynchronize(o.ready);
+                (void)hipEventDestroy(o.ready);
+            }
+            (void)hipStreamSynchronize(s);  // a copy may have started from the source
             dev_free(o.items);
-            if (o.ready) (void)hipEventDestroy(o.ready);
+            host_free(o.host);
             return e;
         }
         it = P.orders.emplace(key, std::move(o)).first;
