@@ -64,3 +64,20 @@ def test_setup_refuses_host_coordinates():
                          ctypes.byref(h))
     assert rc == api.HG_ERR_ARG and "ra_deg" in api.last_error()
     assert not h
+
+
+def test_support_over_too_many_rings_is_refused():
+    """A support that spans more HEALPix rings than the gather's LDS holds
+    (a pixel group's ring pieces plus its queue of in-support candidates,
+    against the 160 KB a workgroup can have) is refused with
+    HG_ERR_UNSUPPORTED before any launch: 4 deg on nside 8192 is about 1,700
+    rings, past the 1,514 that fit.  A tenth of that support sets up."""
+    rng = np.random.default_rng(3)
+    ra = 30.0 + (rng.random(200) - 0.5) * 0.2
+    dec = (rng.random(200) - 0.5) * 0.2
+    m = synth.make_map(30.0, 0.0, 4, 4)
+    with pytest.raises(api.HegridError) as e:
+        api.Plan(ra, dec, m, {"fwhm_deg": 3.0, "support_deg": 4.0}, nside=8192)
+    assert e.value.status == api.HG_ERR_UNSUPPORTED and "rings" in str(e.value)
+    with api.Plan(ra, dec, m, {"fwhm_deg": 0.3, "support_deg": 0.4}, nside=8192) as p:
+        assert p.stats()["nnz"] > 0
