@@ -523,12 +523,8 @@ int setup_fields(hg_batch* b, const hg_field* fields, int32_t nfields, const hg_
                 if (r2) return r2;
                 plans[i] = h;
                 h->owned_by_batch = true;
-                std::vector<int64_t> tb((size_t)h->P.ntiles + 1);
-                hipError_t e2 = hipMemcpyAsync(tb.data(), h->P.tile_blk.p, 8 * tb.size(),
-                                               hipMemcpyDeviceToHost, ws);
-                if (e2 == hipSuccess) e2 = hipStreamSynchronize(ws);
-                if (e2 != hipSuccess) return fail_hip(e2, "batch_create");
-                tile_blk[i] = std::move(tb);
+                // read back by setup with its other sizes
+                tile_blk[i] = h->P.tile_blk_host;
                 return HG_OK;
             });
             if (r) {
