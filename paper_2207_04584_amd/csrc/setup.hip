@@ -581,12 +581,17 @@ __global__ __launch_bounds__(256) void k_slot_fill(const int4* __restrict__ tile
                                                    const int64_t* __restrict__ tile_base,
                                                    const uint32_t* __restrict__ srt_idx,
                                                    uint32_t* __restrict__ slot_idx) {
+    // workgroup (tile, y) of gridDim.y copies every gridDim.y-th run of 256
+    // of each piece: a map of few tiles with many slots each still fills
+    // the device
     int64_t tile = blockIdx.x;
     const int4* tp = tile_piece + tile * tile_rings * 2;
     uint32_t* dst = slot_idx + tile_base[tile];
+    const int step = blockDim.x * gridDim.y;
     for (int k = 0; k < 2 * tile_rings; k++) {
         int4 p = tp[k];
-        for (int t = threadIdx.x; t < p.y; t += blockDim.x) dst[p.z + t] = srt_idx[p.x + t];
+        for (int t = blockIdx.y * blockDim.x + threadIdx.x; t < p.y; t += step)
+            dst[p.z + t] = srt_idx[p.x + t];
     }
 }
 
@@ -1116,8 +1121,9 @@ __global__ __launch_bounds__(256) void k_mark_used(
     const uint32_t* es = ent_slot + pg_base[pg];
     const uint32_t n = pg_cnt[pg];
     // ENTRY_REGS entries a lane per pass, their loads in flight together (a
-    // group of a wide support holds thousands of entries)
-    for (uint32_t t0 = 0; t0 < n; t0 += 64 * ENTRY_REGS) {
+    // group of a wide support holds thousands of entries); workgroup row y
+    // of gridDim.y takes every gridDim.y-th pass
+    for (uint32_t t0 = 64 * ENTRY_REGS * blockIdx.y; t0 < n; t0 += 64 * ENTRY_REGS * gridDim.y) {
         uint32_t w[ENTRY_REGS];
 #pragma unroll
         for (int k = 0; k < ENTRY_REGS; k++) {
@@ -1175,8 +1181,9 @@ __global__ __launch_bounds__(256) void k_remap_entries(
     uint32_t* es = ent_slot + pg_base[pg];
     const uint32_t n = pg_cnt[pg];
     // ENTRY_REGS entries a lane per pass: their loads, then their position
-    // lookups, each in flight together
-    for (uint32_t t0 = 0; t0 < n; t0 += 64 * ENTRY_REGS) {
+    // lookups, each in flight together; workgroup row y of gridDim.y takes
+    // every gridDim.y-th pass
+    for (uint32_t t0 = 64 * ENTRY_REGS * blockIdx.y; t0 < n; t0 += 64 * ENTRY_REGS * gridDim.y) {
         uint32_t w[ENTRY_REGS];
         int64_t np[ENTRY_REGS];
 #pragma unroll
@@ -2121,7 +2128,16 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
     HG_STEP(dev_alloc(P.blk_pgoff, sizeof(uint16_t) * PGOFF_STRIDE * (size_t)(P.n_blocks + 1)));
 
     // 5: candidate slots, neighbour gather, chunk pointers
-    hipLaunchKernelGGL(k_slot_fill, dim3((unsigned)P.ntiles), dim3(256), 0, s,
+    // Fields of few pixels and many samples have few tiles and groups, each
+    // with long lists: the per-tile and per-group passes over them split each
+    // list over more workgroups (a tile's slots are at most its chunk count
+    // before compaction times the chunk; a group's candidates average
+    // ent_cap / npg).
+    const unsigned fill_y = (unsigned)std::min<int64_t>(
+        64, std::max<int64_t>(1, nch_pre_max * P.chunk / 4096));
+    const unsigned ent_y = (unsigned)std::min<int64_t>(
+        16, std::max<int64_t>(1, P.ent_cap / std::max<int64_t>(1, P.npg) / 2048));
+    hipLaunchKernelGGL(k_slot_fill, dim3((unsigned)P.ntiles, fill_y), dim3(256), 0, s,
                        (const int4*)P.tile_piece.p, P.tile_rings, (const int64_t*)P.tile_nslots.p,
                        (const uint32_t*)P.srt_idx.p, (uint32_t*)P.slot_idx.p);
     HG_STEP(hipGetLastError());
@@ -2169,7 +2185,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
                                dim3(256), 0, s, z);
             HG_STEP(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_mark_used, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx, P.npg,
+        hipLaunchKernelGGL(k_mark_used, dim3(blocks_for(P.npg, 4), ent_y), dim3(256), 0, s, P.npgx, P.npg,
                            P.ntx, (const int64_t*)P.tile_nslots.p, (const int64_t*)P.pg_base.p,
                            (const uint32_t*)P.pg_cnt.p, (const uint32_t*)P.ent_slot.p,
                            (uint32_t*)used.p);
@@ -2183,7 +2199,7 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         HG_STEP(hipGetLastError());
         HG_STEP((scan_exclusive<int64_t, int64_t>((const int64_t*)tpad.p, P.ntiles,
                                                   (int64_t*)tbase3.p, (int64_t*)scan_tmp, s)));
-        hipLaunchKernelGGL(k_remap_entries, dim3(blocks_for(P.npg, 4)), dim3(256), 0, s, P.npgx,
+        hipLaunchKernelGGL(k_remap_entries, dim3(blocks_for(P.npg, 4), ent_y), dim3(256), 0, s, P.npgx,
                            P.npg, P.ntx, P.chunk, (const int64_t*)P.tile_nslots.p,
                            (const int64_t*)tbase2.p, (const int64_t*)tnch.p,
                            (const int32_t*)tscr.p, (const int64_t*)P.pg_base.p,
