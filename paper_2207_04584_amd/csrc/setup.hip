@@ -1251,6 +1251,7 @@ __global__ __launch_bounds__(256) void k_deal_slots(
 // its position in its chunk (the slot the fills store, so that they need not
 // read the entry's slot word).  Other tiles keep their (already sorted)
 // order, take their pointers by binary search and an identity perm.
+template <bool WIDE>
 __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     int32_t npgx, int64_t npg, int32_t ntx, int32_t chunk, const int64_t* __restrict__ tile_blk,
     const int32_t* __restrict__ tile_scr, const int64_t* __restrict__ cp_base,
@@ -1258,15 +1259,27 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     const uint32_t* __restrict__ ent_slot, uint32_t* __restrict__ chunk_ptr,
     uint32_t* __restrict__ perm, int32_t words) {
     static_assert(MAX_CHUNK <= 128, "a chunk's positions fit two 64-bit words");
-    // per wave: `words` presence words and as many chunk pointers; words
+    // per group: `words` presence words and as many chunk pointers; words
     // bounds nch * chunk_words(chunk) of every dealt tile (the host sizes it
-    // from the largest chunk count before compaction, which only drops slots)
+    // from the largest chunk count before compaction, which only drops slots).
+    // A wave a group, or (WIDE, for groups of many entries) the whole
+    // workgroup a group, its T threads sharing the group's passes.
+    constexpr int T = WIDE ? 64 * BUCKET_WAVES : 64;
     extern __shared__ unsigned long long sh_bucket[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t pg = (int64_t)blockIdx.x * BUCKET_WAVES + wave;
-    if (pg >= npg) return;  // uniform per wave; no workgroup barrier below
-    unsigned long long* bits = sh_bucket + (int64_t)wave * words;
-    uint32_t* ptr = (uint32_t*)(sh_bucket + (int64_t)BUCKET_WAVES * words) + (int64_t)wave * words;
+    const int tid = WIDE ? (int)threadIdx.x : lane;
+    const int64_t pg = WIDE ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * BUCKET_WAVES + wave;
+    // uniform per wave (per workgroup if WIDE): no barrier is skipped
+    if (pg >= npg) return;
+    unsigned long long* bits = sh_bucket + (WIDE ? 0 : (int64_t)wave * words);
+    uint32_t* ptr = (uint32_t*)(sh_bucket + (int64_t)(WIDE ? 1 : BUCKET_WAVES) * words) +
+                    (WIDE ? 0 : (int64_t)wave * words);
+    auto sync = [&]() {
+        if constexpr (WIDE)
+            __syncthreads();
+        else
+            __builtin_amdgcn_wave_barrier();
+    };
     const int gx = (int)(pg % npgx), gy = (int)(pg / npgx);
     const int64_t tile = (int64_t)(gy / TILE_PGY) * ntx + gx / TILE_PGX;
     const int lp = (gy % TILE_PGY) * TILE_PGX + gx % TILE_PGX;
@@ -1277,7 +1290,7 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
     uint32_t* pm = perm + base;
     const uint32_t ne = pg_cnt[pg];
     if (!tile_scr[tile]) {
-        for (int64_t c = lane; c <= nch; c += 64) {
+        for (int64_t c = tid; c <= nch; c += T) {
             const uint32_t target = (uint32_t)(c * chunk);
             uint32_t lo = 0, hi = ne;
             while (lo < hi) {
@@ -1289,64 +1302,66 @@ __global__ __launch_bounds__(64 * BUCKET_WAVES) void k_bucket_entries(
             }
             cp[c] = lo;
         }
-        for (uint32_t t = lane; t < ne; t += 64)
+        for (uint32_t t = tid; t < ne; t += T)
             pm[t] = (t << PERM_POS_BITS) | ((es[t] & SLOT_MASK) % (uint32_t)chunk);
         return;
     }
     // dealt tiles: nch * nw <= SCRAMBLE_MAX_WORDS
     const int nw = chunk_words(chunk);
-    for (int64_t i = lane; i < nch * nw; i += 64) bits[i] = 0ull;
-    __builtin_amdgcn_wave_barrier();
+    for (int64_t i = tid; i < nch * nw; i += T) bits[i] = 0ull;
+    sync();
     // the group's slot words come BUCKET_REGS a lane at a time, all loads of
     // a round issued before any is used, so that a wave waits for memory once
     // a round rather than once an entry
-    for (uint32_t t0 = 0; t0 < ne; t0 += 64 * BUCKET_REGS) {
+    for (uint32_t t0 = 0; t0 < ne; t0 += T * BUCKET_REGS) {
         uint32_t loc[BUCKET_REGS];
 #pragma unroll
         for (int k = 0; k < BUCKET_REGS; k++) {
-            const uint32_t t = t0 + lane + 64 * k;
+            const uint32_t t = t0 + tid + T * k;
             loc[k] = t < ne ? es[t] & SLOT_MASK : 0u;
         }
 #pragma unroll
         for (int k = 0; k < BUCKET_REGS; k++) {
-            if (t0 + lane + 64 * k < ne) {
+            if (t0 + tid + T * k < ne) {
                 const uint32_t c = loc[k] / chunk, j = loc[k] % chunk;
                 atomicOr(&bits[c * nw + j / 64], 1ull << (j % 64));
             }
         }
     }
-    __builtin_amdgcn_wave_barrier();
-    // exclusive scan of the chunks' entry counts: the chunk pointers
-    uint32_t carry = 0;
-    for (int64_t c0 = 0; c0 < nch; c0 += 64) {
-        const int64_t c = c0 + lane;
-        uint32_t v = 0;
-        if (c < nch)
-            for (int w = 0; w < nw; w++) v += (uint32_t)__builtin_popcountll(bits[c * nw + w]);
-        uint32_t x = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+    sync();
+    // exclusive scan of the chunks' entry counts: the chunk pointers (one wave)
+    if (!WIDE || wave == 0) {
+        uint32_t carry = 0;
+        for (int64_t c0 = 0; c0 < nch; c0 += 64) {
+            const int64_t c = c0 + lane;
+            uint32_t v = 0;
+            if (c < nch)
+                for (int w = 0; w < nw; w++) v += (uint32_t)__builtin_popcountll(bits[c * nw + w]);
+            uint32_t x = v;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            const uint32_t excl = carry + x - v;
+            if (c < nch) {
+                cp[c] = excl;
+                ptr[c] = excl;
+            }
+            carry += __shfl(x, 63, 64);
         }
-        const uint32_t excl = carry + x - v;
-        if (c < nch) {
-            cp[c] = excl;
-            ptr[c] = excl;
-        }
-        carry += __shfl(x, 63, 64);
+        if (lane == 0) cp[nch] = carry;
     }
-    if (lane == 0) cp[nch] = carry;
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t t0 = 0; t0 < ne; t0 += 64 * BUCKET_REGS) {
+    sync();
+    for (uint32_t t0 = 0; t0 < ne; t0 += T * BUCKET_REGS) {
         uint32_t loc[BUCKET_REGS];
 #pragma unroll
         for (int k = 0; k < BUCKET_REGS; k++) {
-            const uint32_t t = t0 + lane + 64 * k;
+            const uint32_t t = t0 + tid + T * k;
             loc[k] = t < ne ? es[t] & SLOT_MASK : 0u;
         }
 #pragma unroll
         for (int k = 0; k < BUCKET_REGS; k++) {
-            const uint32_t t = t0 + lane + 64 * k;
+            const uint32_t t = t0 + tid + T * k;
             if (t < ne) {
                 const uint32_t c = loc[k] / chunk, j = loc[k] % chunk;
                 const unsigned long long* cw = bits + c * nw;
@@ -2228,8 +2243,12 @@ hipError_t launch_setup(Plan& P, const double* ra_deg, const double* dec_deg, hi
         // more groups' waves are resident on the usual workloads
         const int32_t words = (int32_t)std::max<int64_t>(
             1, std::min<int64_t>(SCRAMBLE_MAX_WORDS, nch_pre_max * chunk_words(P.chunk)));
-        const size_t bshm = (size_t)BUCKET_WAVES * words * (sizeof(unsigned long long) + 4);
-        hipLaunchKernelGGL(k_bucket_entries, dim3(blocks_for(P.npg, BUCKET_WAVES)),
+        // groups of many candidates (dense fields) take a workgroup each
+        const bool wide = P.ent_cap / std::max<int64_t>(1, P.npg) >= 4096;
+        const size_t bshm =
+            (size_t)(wide ? 1 : BUCKET_WAVES) * words * (sizeof(unsigned long long) + 4);
+        hipLaunchKernelGGL(wide ? k_bucket_entries<true> : k_bucket_entries<false>,
+                           dim3(wide ? (unsigned)P.npg : blocks_for(P.npg, BUCKET_WAVES)),
                            dim3(64 * BUCKET_WAVES), bshm, s, P.npgx, P.npg, P.ntx, P.chunk,
                            (const int64_t*)P.tile_blk.p, (const int32_t*)tscr.p,
                            (const int64_t*)P.cp_base.p, (const int64_t*)P.pg_base.p,
