@@ -128,6 +128,31 @@ def test_small_field_parity(name):
     check_field(ra, dec, vals, m, k)
 
 
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_dense_groups_on_dealt_tiles(form):
+    """Pixel groups of over 4,096 entries on tiles still light enough to deal
+    (about 22 samples a square arcminute, 50,000 in all, under a 6.3 arcmin
+    beam): the bucketing then takes a workgroup a group, and the slot fill,
+    marking and remapping split each list over several workgroups.  Lists,
+    counts, W and maps against the reference on every pixel.  With about
+    4,400 neighbours a pixel the FP32 form is held to its rounding bound cell
+    by cell (check_field's assert_fp32_bound; its normwise figure only to
+    1e-3), the BF16 form to 2e-3 and its weights to their rounding unit."""
+    if form == "fp32":
+        prec, dt, u, tol = api.HG_PREC_FP32, torch.float32, 1e-6, 1e-3
+    else:
+        prec, dt, u = MFMA[form]
+        tol = MFMA_TOL
+    ra, dec, vals, m, k = rand_field(31, 50000, 32, 32, 60.0, 10.0, fwhm=6.3, C=3, spread=1.5,
+                                     dtype=dt)
+    _, _, st = check_field(ra, dec, vals, m, k, tol=tol, w_rtol=u, precision=prec)
+    # a group's entries are at least the largest of its four pixels' counts,
+    # so the groups average at least nnz / npix entries (and more candidates)
+    npix = m["nx"] * m["ny"]
+    print(f"  neighbours per pixel {st['nnz'] / npix:.0f}, chunk {st['chunk']}", flush=True)
+    assert st["nnz"] / npix > 4096
+
+
 @pytest.mark.parametrize("nside,chunk", [(64, 8), (512, 32), (16384, 24), (4096, 16)])
 def test_nside_and_chunk_overrides(nside, chunk):
     ra, dec, vals, m, k = rand_field(21, 2500, 26, 23, 95.0, -20.0, C=7)
