@@ -112,6 +112,29 @@ int64_t choose_nside(Plan& P) {
     return N;
 }
 
+// First chunk length of a batch field in a 16-bit form: the longest of 112
+// and 88 slots whose predicted densest block fits two staged chunks in LDS
+// and keeps a group's run in a chunk within a lane each, else 64.  A dealt
+// chunk samples its whole tile, so a group's mean run in a chunk is the
+// chunk times the group's share of the tile's slot region: (R + 1)^2 pi over
+// (16 + 2R)^2 for a support of R pixels, whatever the density.  The margins
+// (twice the mean run and block) stand for the spread between groups
+// and tiles; a miss costs the field a second setup at the next length.
+int32_t batch_first_chunk(const Plan& P) {
+    const hg_map& m = P.map;
+    const double pix = m.proj == HG_PROJ_HEALPIX ? sqrt(kPi / 3.0) / (double)m.nside
+                                                 : m.ddec_deg * kDeg;
+    const double R = P.r_rad / pix;
+    const double tile = 16.0 + 2.0 * R;
+    const double share = kPi * (R + 1.0) * (R + 1.0) / (tile * tile);
+    for (int32_t c : {112, 88}) {
+        const double run = c * share;
+        const double units = 64.0 * (run / 4.0 + 1.0);
+        if (2.0 * run <= 64.0 && channel_lds_fits(true, c, (int)(2.0 * units))) return c;
+    }
+    return 64;
+}
+
 }  // namespace
 
 hipError_t dev_alloc(DevBuf& b, size_t bytes) {
@@ -390,14 +413,20 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     // staged chunks of the plan's densest entry block in LDS (longer chunks
     // mean fewer synchronisations per tile; the fit is known only once the
     // blocks are built, so a plan that does not fit is rebuilt shorter).  A
-    // batch's fields start at 64 slots: their set-ups run side by side and
-    // dense fields, which 112 slots do not fit, would each be set up again.
+    // batch's fields start at the longest length predicted to fit (at most
+    // 64 slots where the prediction sees no room for more).
     const bool m16 = P.opts.precision != HG_PREC_FP32;
     std::vector<int32_t> chunks;
     if (o && o->chunk)
         chunks = {o->chunk};
-    else if (m16 && batch_field)
-        chunks = {64, 48, 32, 16, 8};
+    else if (m16 && batch_field) {
+        // set up side by side, a field rebuilt at a shorter chunk delays the
+        // batch: start at the longest chunk predicted to fit
+        const int32_t first = batch_first_chunk(P);
+        chunks = first == 112 ? std::vector<int32_t>{112, 88, 64, 48, 32, 16, 8}
+                 : first == 88 ? std::vector<int32_t>{88, 64, 48, 32, 16, 8}
+                               : std::vector<int32_t>{64, 48, 32, 16, 8};
+    }
     else if (m16)
         chunks = {112, 88, 64, 48, 32, 16, 8};
     else
