@@ -112,27 +112,34 @@ int64_t choose_nside(Plan& P) {
     return N;
 }
 
-// First chunk length of a batch field in a 16-bit form: the longest of 112
-// and 88 slots whose predicted densest block fits two staged chunks in LDS
-// and keeps a group's run in a chunk within a lane each, else 64.  A dealt
-// chunk samples its whole tile, so a group's mean run in a chunk is the
-// chunk times the group's share of the tile's slot region: (R + 1)^2 pi over
-// (16 + 2R)^2 for a support of R pixels, whatever the density.  The margins
-// (twice the mean run and block) stand for the spread between groups
-// and tiles; a miss costs the field a second setup at the next length.
-int32_t batch_first_chunk(const Plan& P) {
+// First chunk length of a batch field: the longest of the form's lengths
+// (112, 88 for the 16-bit forms; 56, 48 for FP32) whose predicted densest
+// block fits two staged chunks in LDS and keeps a group's run in a chunk
+// within a lane each, else the next (64; 32).  A dealt chunk samples its
+// whole tile, so a group's mean run in a chunk is the chunk times the
+// group's share of the tile's slot region: (R + 1)^2 pi over (16 + 2R)^2 for
+// a support of R pixels, whatever the density.  The margins over the mean
+// stand for the spread between groups and tiles (measured on 64 fields of
+// 2-5 arcmin beams: 2 for the 16-bit forms; 1.2 and 1.5 for the FP32 form,
+// whose 56-slot blocks of a 3 arcmin beam already fit within 1.39 of the
+// mean); a miss costs the field a second setup at the next length.
+int32_t batch_first_chunk(const Plan& P, bool m16) {
     const hg_map& m = P.map;
     const double pix = m.proj == HG_PROJ_HEALPIX ? sqrt(kPi / 3.0) / (double)m.nside
                                                  : m.ddec_deg * kDeg;
     const double R = P.r_rad / pix;
     const double tile = 16.0 + 2.0 * R;
     const double share = kPi * (R + 1.0) * (R + 1.0) / (tile * tile);
-    for (int32_t c : {112, 88}) {
+    const int32_t c16[2] = {112, 88}, c32[2] = {56, 48};
+    const double g16[2] = {2.0, 2.0}, g32[2] = {1.2, 1.5};
+    for (int k = 0; k < 2; k++) {
+        const int32_t c = m16 ? c16[k] : c32[k];
+        const double g = m16 ? g16[k] : g32[k];
         const double run = c * share;
         const double units = 64.0 * (run / 4.0 + 1.0);
-        if (2.0 * run <= 64.0 && channel_lds_fits(true, c, (int)(2.0 * units))) return c;
+        if ((c <= 64 || g * run <= 64.0) && channel_lds_fits(m16, c, (int)(g * units))) return c;
     }
-    return 64;
+    return m16 ? 64 : 32;
 }
 
 }  // namespace
@@ -419,18 +426,16 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
     std::vector<int32_t> chunks;
     if (o && o->chunk)
         chunks = {o->chunk};
-    else if (m16 && batch_field) {
-        // set up side by side, a field rebuilt at a shorter chunk delays the
-        // batch: start at the longest chunk predicted to fit
-        const int32_t first = batch_first_chunk(P);
-        chunks = first == 112 ? std::vector<int32_t>{112, 88, 64, 48, 32, 16, 8}
-                 : first == 88 ? std::vector<int32_t>{88, 64, 48, 32, 16, 8}
-                               : std::vector<int32_t>{64, 48, 32, 16, 8};
-    }
     else if (m16)
         chunks = {112, 88, 64, 48, 32, 16, 8};
     else
         chunks = {56, 48, 32, 16, 8};
+    if (batch_field && !(o && o->chunk)) {
+        // set up side by side, a field rebuilt at a shorter chunk delays the
+        // batch: start at the longest chunk predicted to fit
+        const int32_t first = batch_first_chunk(P, m16);
+        while (chunks.size() > 1 && chunks.front() != first) chunks.erase(chunks.begin());
+    }
     for (size_t ci = 0; ci < chunks.size(); ci++) {
         P.chunk = chunks[ci];
         std::string err;

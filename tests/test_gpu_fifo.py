@@ -47,9 +47,11 @@ def same(a, b):
 
 @pytest.mark.parametrize("streams", [1, 3, 8])
 def test_fifo_equals_batch_bitwise(streams):
+    """At one chunk length for every field (a batch otherwise starts each
+    field at its own predicted length, which sets the summation's grouping)."""
     fs = fields()
-    got = pipeline.grid_fields_fifo(fs, n_streams=streams)
-    with api.Batch(fs) as b:
+    got = pipeline.grid_fields_fifo(fs, n_streams=streams, chunk=48)
+    with api.Batch(fs, chunk=48) as b:
         ref = [o.clone() if o is not None else None for o in b.run()]
     for i, (g, r) in enumerate(zip(got, ref)):
         assert (g is None) == (r is None), i

@@ -135,8 +135,10 @@ def test_batch_mixing_healpix_and_plate_carree_fields():
                "kernel": synth.make_kernel(3.0), "values": v2}]
     with api.Batch(fields) as b:
         outs = [o.clone() for o in b.run()]
-    for f, o in zip(fields, outs):
-        with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"]) as p:
+        # the single plans at each batch field's own chunk length
+        chunks = [b.plan(i).stats()["chunk"] for i in range(len(fields))]
+    for f, o, c in zip(fields, outs, chunks):
+        with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"], chunk=c) as p:
             single = p.grid(f["values"])
         assert torch.equal(torch.isnan(o), torch.isnan(single))
         assert torch.equal(torch.nan_to_num(o), torch.nan_to_num(single))
