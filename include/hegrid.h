@@ -126,8 +126,10 @@ typedef struct {
     int32_t chunk;          /* tile slots staged per step, a multiple of 8 up to 64
                                (FP32 form, 1 KB rows) or 112 (16-bit forms, 512 B
                                rows), else HG_ERR_ARG; 0 = the longest that fits (56
-                               for the FP32 form, 112 for the 16-bit forms -- 64 for
-                               a batch's fields --, shorter for dense fields).  An explicit chunk whose densest
+                               for the FP32 form, 112 for the 16-bit forms, shorter
+                               for dense fields), tried from the longest, or with
+                               HG_FLAG_PREDICT_CHUNK (and for a batch's fields) from
+                               the length predicted from the support.  An explicit chunk whose densest
                                entry block would not fit two staged chunks in LDS,
                                or (past 64 slots) where one pixel group takes more
                                than 64 entries of a chunk, fails (HG_ERR_UNSUPPORTED) */
@@ -147,6 +149,13 @@ typedef struct {
 } hg_opts;
 
 #define HG_FLAG_TIME_CHANNELS 1u /* record HIP events around channel kernels   */
+/* chunk 0: start at the longest length predicted to fit from the support in
+   pixels (a group's mean run in a dealt chunk is the chunk times the group's
+   share of its tile's slot region, with a margin) instead of at the longest
+   of all; a field that does not fit is still set up again shorter.  Fewer
+   dense fields are set up twice, at the cost of shorter chunks where the
+   margin was not needed.  Batch fields always start this way. */
+#define HG_FLAG_PREDICT_CHUNK 2u
 
 typedef struct {
     int64_t n_samples;   /* samples passed to setup                              */

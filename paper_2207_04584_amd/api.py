@@ -18,6 +18,7 @@ HG_OK, HG_ERR_ARG, HG_ERR_STATE, HG_ERR_NOMEM, HG_ERR_DEVICE, HG_ERR_UNSUPPORTED
 HG_F32, HG_BF16, HG_F16 = 0, 1, 2
 HG_PREC_FP32, HG_PREC_MFMA_BF16, HG_PREC_MFMA_F16 = 0, 1, 2
 HG_FLAG_TIME_CHANNELS = 1
+HG_FLAG_PREDICT_CHUNK = 2
 
 ABI_FUNCTIONS = ("hg_grid_setup", "hg_grid_channels", "hg_grid_finish", "hg_plan_stats",
                  "hg_plan_counts", "hg_plan_weight_sums", "hg_plan_neighbours",
@@ -210,10 +211,13 @@ def _dtype_code(t):
 
 class Plan:
     """A gridding plan: grid_setup on construction, grid_channels per call,
-    grid_finish on close()."""
+    grid_finish on close().  predict_chunk (with chunk 0): start at the chunk
+    length predicted from the support, as a batch's fields do
+    (HG_FLAG_PREDICT_CHUNK), rather than at the longest."""
 
     def __init__(self, ra_deg, dec_deg, map, kernel, precision=HG_PREC_FP32, nside=0, chunk=0,
-                 device_mem_cap=0, time_channels=False, stream=None, waves=0, chan_block=0):
+                 device_mem_cap=0, time_channels=False, stream=None, waves=0, chan_block=0,
+                 predict_chunk=False):
         L = lib()
         ra, dec = _dev_f64(ra_deg), _dev_f64(dec_deg)
         if ra.shape != dec.shape or ra.dim() != 1:
@@ -223,7 +227,8 @@ class Plan:
         self.n = ra.shape[0]
         self._m, self._k = make_map(map), make_kernel(kernel)
         self._o = hg_opts(int(precision), int(nside), int(chunk), int(waves), int(device_mem_cap),
-                          HG_FLAG_TIME_CHANNELS if time_channels else 0, int(chan_block))
+                          (HG_FLAG_TIME_CHANNELS if time_channels else 0)
+                          | (HG_FLAG_PREDICT_CHUNK if predict_chunk else 0), int(chan_block))
         self._h = ctypes.c_void_p()
         rc = L.hg_grid_setup(ctypes.c_void_p(ra.data_ptr() if self.n else 0),
                              ctypes.c_void_p(dec.data_ptr() if self.n else 0), self.n,

@@ -430,7 +430,7 @@ int make_plan(const double* ra_deg, const double* dec_deg, int64_t n, const hg_k
         chunks = {112, 88, 64, 48, 32, 16, 8};
     else
         chunks = {56, 48, 32, 16, 8};
-    if (batch_field && !(o && o->chunk)) {
+    if ((batch_field || (P.opts.flags & HG_FLAG_PREDICT_CHUNK)) && !(o && o->chunk)) {
         // set up side by side, a field rebuilt at a shorter chunk delays the
         // batch: start at the longest chunk predicted to fit
         const int32_t first = batch_first_chunk(P, m16);

@@ -47,8 +47,10 @@ def grid_fields_fifo(fields, n_streams=4, precision=api.HG_PREC_FP32, chunk=0):
                     break
                 f = fields[i]
                 try:
+                    # chunk lengths as a batch's fields take them (predicted
+                    # from the support), so the two forms give the same maps
                     p = api.Plan(f["ra"], f["dec"], f["map"], f["kernel"], precision=precision,
-                                 chunk=chunk, stream=s)
+                                 chunk=chunk, predict_chunk=True, stream=s)
                     plans[i] = p
                     if f.get("values") is not None:
                         p.grid(f["values"], out=outs[i], stream=s)

@@ -45,13 +45,13 @@ def same(a, b):
     return torch.equal(torch.nan_to_num(a, nan=1e30), torch.nan_to_num(b, nan=1e30))
 
 
-@pytest.mark.parametrize("streams", [1, 3, 8])
-def test_fifo_equals_batch_bitwise(streams):
-    """At one chunk length for every field (a batch otherwise starts each
-    field at its own predicted length, which sets the summation's grouping)."""
+@pytest.mark.parametrize("streams,chunk", [(1, 0), (3, 0), (8, 0), (3, 48)])
+def test_fifo_equals_batch_bitwise(streams, chunk):
+    """The FIFO's plans take their chunk lengths as a batch's fields do
+    (predicted from the support, or the one given)."""
     fs = fields()
-    got = pipeline.grid_fields_fifo(fs, n_streams=streams, chunk=48)
-    with api.Batch(fs, chunk=48) as b:
+    got = pipeline.grid_fields_fifo(fs, n_streams=streams, chunk=chunk)
+    with api.Batch(fs, chunk=chunk) as b:
         ref = [o.clone() if o is not None else None for o in b.run()]
     for i, (g, r) in enumerate(zip(got, ref)):
         assert (g is None) == (r is None), i
@@ -67,7 +67,7 @@ def test_fifo_f16_mfma_equals_single_plans():
             assert got[i] is None
             continue
         with api.Plan(f["ra"], f["dec"], f["map"], f["kernel"],
-                      precision=api.HG_PREC_MFMA_F16) as p:
+                      precision=api.HG_PREC_MFMA_F16, predict_chunk=True) as p:
             assert same(got[i], p.grid(f["values"])), f"field {i}"
 
 
