@@ -327,3 +327,19 @@ def test_binding_refuses_a_host_output_tensor():
         api._out_arg(torch.empty(3, 2, 2, dtype=torch.float64), 3, 2, 2, dev)
     with pytest.raises(api.HegridError):
         api._out_arg(torch.empty(2, 2, 2, dtype=torch.float32), 3, 2, 2, dev)
+
+
+def test_binding_constants_match_the_header():
+    """Every integer #define and kernel enum value of include/hegrid.h that the binding also names
+    has the same value there (status codes, dtypes, forms, projections,
+    flags, kernel shapes)."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(api.LIB_PATH), "..", "include", "hegrid.h")).read()
+    pairs = re.findall(r"^#define (HG_\w+) (\d+)u?\b", hdr, flags=re.M)
+    pairs += re.findall(r"^\s+(HG_KERNEL_\w+) = (\d+)", hdr, flags=re.M)  # the kernel enum
+    found = 0
+    for name, val in pairs:
+        if hasattr(api, name):
+            assert getattr(api, name) == int(val), name
+            found += 1
+    assert found == 20
