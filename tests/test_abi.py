@@ -330,10 +330,9 @@ def test_binding_refuses_a_host_output_tensor():
 
 
 def test_binding_constants_match_the_header():
-    """Every integer #define and kernel enum value of include/hegrid.h that the binding also names
-    has the same value there (status codes, dtypes, forms, projections,
-    flags, kernel shapes)."""
-    import re
+    """Every integer #define and kernel enum value of include/hegrid.h that
+    the binding also names has the same value there (status codes, dtypes,
+    forms, projections, flags, kernel shapes)."""
     hdr = open(os.path.join(os.path.dirname(api.LIB_PATH), "..", "include", "hegrid.h")).read()
     pairs = re.findall(r"^#define (HG_\w+) (\d+)u?\b", hdr, flags=re.M)
     pairs += re.findall(r"^\s+(HG_KERNEL_\w+) = (\d+)", hdr, flags=re.M)  # the kernel enum
